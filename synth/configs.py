@@ -1,0 +1,186 @@
+"""Workload definitions: hierarchy, sampled fields and run parameters.
+
+Each builder returns a :class:`Problem`.  Fields are callables
+``f(level, cell_ijk) -> float64 array`` so that each consumer can sample them
+in its own cell order.  Every value comes from seeded random numbers or closed
+-form profiles; nothing here computes any part of the diffusion solve.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from functools import lru_cache
+from typing import Callable, Optional
+
+import numpy as np
+
+from .fields import PowerLawField, cell_centres, gaussian_pulse
+from .hierarchy import (Hierarchy, budgeted_hierarchy, centred_box_hierarchy,
+                        random_balanced_hierarchy, uniform_hierarchy)
+
+BC_MODES = {"dirichlet": 0, "neumann": 1, "robin": 2}
+
+
+@dataclass
+class Problem:
+    name: str
+    hierarchy: Hierarchy
+    rho: Callable
+    E: Callable
+    T: Optional[Callable] = None
+    kmode: str = "lp"            # "const" or "lp"
+    K_const: float = 1.0
+    kappa_R: float = 1.0
+    kappa_P: float = 1.0
+    c_light: float = 1.0
+    a_rad: float = 1.0
+    c_v: float = 1.0
+    dt_coarse: float = 1.0
+    bc_mode: str = "dirichlet"
+    robin_alpha: float = 0.5
+    tol: float = 1e-10
+    n_coarse_steps: int = 1
+    nsub: dict = field(default_factory=dict)   # level -> substeps per parent step (default 2)
+    abs_floor: float = 1e-14
+    linf_test: bool = True
+    max_iter: int = 10000
+    info: dict = field(default_factory=dict)
+
+    def nsub_of(self, level: int) -> int:
+        return int(self.nsub.get(level, 2))
+
+
+@lru_cache(maxsize=8)
+def _field(n: int, slope: float, seed: int) -> PowerLawField:
+    return PowerLawField(n, slope, seed)
+
+
+def config_heat_gaussian(n_coarse_steps: int = 4, dt_scale: float = 1.0) -> Problem:
+    """3D heat equation, constant K = 1, on a 16^3 base with the central 8^3 coarse
+    cells refined once (512 octs).  Gaussian pulse (sigma 0.05) plus 1e-3 background;
+    coarse dt = 4 dx^2 / K; Dirichlet interfaces; tolerance 1e-12."""
+    h = centred_box_hierarchy(4, 4, 12, seed=11)
+
+    def E(level, ijk):
+        return gaussian_pulse(cell_centres(level, ijk))
+
+    def rho(level, ijk):
+        return np.ones(len(ijk))
+
+    return Problem("heat_gaussian_16c_2lev", h, rho, E, kmode="const", K_const=1.0,
+                   dt_coarse=dt_scale * 4.0 / 256.0, bc_mode="dirichlet", tol=1e-12,
+                   n_coarse_steps=n_coarse_steps)
+
+
+def _lognormal_rho(field_n: int, sigma: float, seed: int):
+    g = _field(field_n, 4.0, seed)
+    mu = -0.5 * sigma * sigma
+
+    def rho(level, ijk):
+        return np.exp(mu + sigma * g.sample(cell_centres(level, ijk)))
+
+    def criterion(level, ijk):
+        x = cell_centres(level, ijk)
+        dx = 1.0 / (1 << level)
+        s = np.zeros(len(x))
+        for d in range(3):
+            e = np.zeros(3)
+            e[d] = dx
+            s += (0.5 * sigma * (g.sample(x + e) - g.sample(x - e))) ** 2
+        return np.sqrt(s)
+
+    return rho, criterion
+
+
+def _perturbed_E(field_n: int, seed: int, amp: float = 0.1):
+    g = _field(field_n, 4.0, seed)
+
+    def E(level, ijk):
+        return 1.0 + amp * np.clip(g.sample(cell_centres(level, ijk)), -3.0, 3.0)
+
+    return E
+
+
+def config_fld_lognormal(base_level: int = 6, max_level: int = 9, field_n: int = 256,
+                         quota: int = 156250, threshold: float = 0.2, sigma: float = 1.5,
+                         rho_seed: int = 1401, E_seed: int = 1112, tol: float = 1e-10,
+                         bc_mode: str = "dirichlet", robin_alpha: float = 0.5) -> Problem:
+    """Flux-limited radiative diffusion on a density-gradient-refined hierarchy.
+
+    Log-normal density (sigma_ln = ``sigma``, k^-4 spectrum, mean 1), kappa = c = 1,
+    Levermore-Pomraning limited diffusivity, E = 1 + 10% k^-4 perturbation.  Levels
+    ``base_level..max_level``; at each level the eligible cells with the largest
+    |grad rho| dx / rho above ``threshold`` are refined, at most ``quota`` per level.
+    Coarse dt = 4 dx_base^2 / K_thick with K_thick = c / (3 rho kappa) = 1/3."""
+    rho, crit = _lognormal_rho(field_n, sigma, rho_seed)
+    h, counts = budgeted_hierarchy(base_level, max_level, crit, threshold, quota, seed=rho_seed)
+    E = _perturbed_E(field_n, E_seed)
+    dxb = 1.0 / (1 << base_level)
+    return Problem(f"fld_lognormal_L{base_level}-{max_level}", h, rho, E, kmode="lp",
+                   dt_coarse=4.0 * dxb * dxb * 3.0, bc_mode=bc_mode, robin_alpha=robin_alpha,
+                   tol=tol, n_coarse_steps=1, info={"refined_per_level": counts})
+
+
+def config_tiny(seed: int, base_level: int = 2, max_level: int = 4, kmode: str = "lp",
+                bc_mode: str = "dirichlet", dt_scale: float = 1.0, p_refine: float = 0.35,
+                tol: float = 1e-12, robin_alpha: float = 0.5) -> Problem:
+    """Small random balanced hierarchy with a smooth log-normal density and a smooth
+    positive energy field; sized so that dense direct solves are cheap."""
+    h = random_balanced_hierarchy(seed, base_level, max_level, p_refine=p_refine)
+    rho, _ = _lognormal_rho(16, 1.0, 7000 + seed)
+    E = _perturbed_E(16, 8000 + seed, amp=0.3)
+    dxb = 1.0 / (1 << base_level)
+    return Problem(f"tiny_{seed}", h, rho, E, kmode=kmode, K_const=1.0,
+                   dt_coarse=dt_scale * 4.0 * dxb * dxb * 3.0, bc_mode=bc_mode,
+                   robin_alpha=robin_alpha, tol=tol, n_coarse_steps=1)
+
+
+def config_uniform(level: int, kmode: str = "const", seed: int = 0, dt: float = None,
+                   tol: float = 1e-12) -> Problem:
+    """A single uniform level (no refinement)."""
+    h = uniform_hierarchy(level, seed=seed)
+    rho, _ = _lognormal_rho(16, 1.0, 9000 + seed)
+    E = _perturbed_E(16, 9100 + seed, amp=0.3)
+    dx = 1.0 / (1 << level)
+    return Problem(f"uniform_L{level}", h, rho, E, kmode=kmode, K_const=1.0,
+                   dt_coarse=dt if dt is not None else 4.0 * dx * dx, tol=tol)
+
+
+@dataclass
+class Patch:
+    """One independent single-level problem on an n^3 box of cell size 1/n."""
+    n: int
+    dx: float
+    dt: float
+    rho: np.ndarray          # (n, n, n), x-major: index [i, j, k]
+    E: np.ndarray
+    face_mode: np.ndarray    # int32[6]: -x,+x,-y,+y,-z,+z ; 0 Dirichlet, 1 Neumann, 2 Robin
+    face_ghost: np.ndarray   # float64[6] Dirichlet / Robin outside value
+    face_flux: np.ndarray    # float64[6] inflow per face cell per step in E units (Neumann / Robin)
+
+
+def patch_sizes(seed: int, n_patches: int, n_min: int = 8, n_max: int = 128):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(np.log(n_min), np.log(n_max), size=n_patches)
+    return (2 * np.round(0.5 * np.exp(u))).astype(int)
+
+
+def patch_batch(base_seed: int = 4000, n_patches: int = 512, n_min: int = 8, n_max: int = 128,
+                sigma: float = 1.0, robin_alpha: float = 0.5):
+    """Independent patches with log-uniform sizes, own log-normal density and energy,
+    and a boundary mode drawn per face."""
+    sizes = patch_sizes(base_seed, n_patches, n_min, n_max)
+    out = []
+    for i, n in enumerate(sizes):
+        rng = np.random.default_rng(base_seed + i)
+        n = int(max(2, n))
+        fld = PowerLawField(n, 4.0, base_seed + i)
+        rho = np.exp(-0.5 * sigma * sigma + sigma * fld.grid)
+        e = PowerLawField(n, 4.0, base_seed + 100000 + i)
+        E = 1.0 + 0.1 * np.clip(e.grid, -3.0, 3.0)
+        dx = 1.0 / n
+        dt = 4.0 * dx * dx * 3.0
+        modes = rng.integers(0, 3, size=6).astype(np.int32)
+        ghost = rng.uniform(0.9, 1.1, size=6)
+        phi = rng.uniform(-0.05, 0.05, size=6)
+        out.append(Patch(n, dx, dt, rho, E, modes, ghost, phi * dt / dx))
+    return out, robin_alpha
