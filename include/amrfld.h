@@ -1,0 +1,165 @@
+/*
+ * amrfld — level-by-level implicit diffusion solve for adaptive time-stepping
+ * on oct-based AMR grids, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Commercon, Debout & Teyssier 2014):
+ *   - backward-Euler finite-volume update of dE/dt = div(K grad E) on the leaf
+ *     cells of ONE level at a time (Sect. 3.1, eqs. Er_imp and Er_imp1):
+ *       (1 + sum_f C_f) E_i^{n+1} - sum_f C_f E_nb^{n+1} = E_i^n,
+ *     C_f = K_f dt / dx^2 for same-level and coarse-to-fine faces and
+ *     (2/3) K_f dt / dx^2 for a face towards a coarser leaf (Sect. 3.1);
+ *   - level-interface conditions (Sect. 3.2, 3.3): fine-to-coarse faces are
+ *     Dirichlet with the coarse energy at the start of the coarse step;
+ *     coarse-to-fine faces are Dirichlet (restricted fine energy), Neumann
+ *     (stored fine flux, eq. mean_flux) or Robin (weight alpha);
+ *   - Jacobi-preconditioned conjugate gradient with the L2-residual and
+ *     L-infinity-change stopping test (Sect. 3.3.4);
+ *   - adaptive time-stepping, finer levels first, dt_l = dt_{l-1} / nsub
+ *     (Sect. 2.2);
+ *   - Levermore-Pomraning limited diffusivity K = c lambda(R) / (rho kappa_R)
+ *     and the linearised two-temperature coupling term (Sect. 2.1).
+ *
+ * Conventions for every call:
+ *   - Every call returns an amrfld_status; nothing aborts or throws across the
+ *     ABI.  amrfld_last_error() gives a message for the last failure.
+ *   - Arguments are validated before any device work; on AMRFLD_E_INVALID no
+ *     state has changed.
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary CPU memory.  Caller buffers are borrowed for the
+ *     duration of the call only.  The library owns its tables, fields and
+ *     workspace (device memory, freed by amrfld_destroy).
+ *   - Work is ordered on opts.stream (a hipStream_t, NULL = the null stream).
+ *     Solve calls return after the solve has finished on that stream
+ *     (convergence is known on return); set/get calls are stream-ordered.
+ *   - A context is not thread-safe: one host thread at a time.
+ *   - Per-cell arrays use the library's cell order for that level ("slot"
+ *     order): octs sorted by Morton key of their coordinates, 8 cells per oct,
+ *     x fastest within the oct.  amrfld_level_info returns the coordinates.
+ */
+#ifndef AMRFLD_H
+#define AMRFLD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amrfld_ctx amrfld_ctx;
+
+typedef enum {
+  AMRFLD_OK = 0,
+  AMRFLD_E_INVALID = -1,   /* bad argument, unbalanced hierarchy, wrong call order */
+  AMRFLD_E_STATE = -2,     /* call not valid in the current state (e.g. no fields yet) */
+  AMRFLD_E_NOMEM = -3,     /* device or host allocation failed */
+  AMRFLD_E_DEVICE = -4,    /* a HIP runtime call failed */
+  AMRFLD_E_NOCONV = -5,    /* PCG hit max_iter; E holds the last iterate */
+  AMRFLD_E_NONFINITE = -6  /* NaN or Inf met in the residual of a solve */
+} amrfld_status;
+
+typedef enum { AMRFLD_BC_DIRICHLET = 0, AMRFLD_BC_NEUMANN = 1, AMRFLD_BC_ROBIN = 2 } amrfld_bc;
+typedef enum { AMRFLD_FP64 = 0, AMRFLD_MIXED = 1 } amrfld_precision;
+typedef enum { AMRFLD_K_CONST = 0, AMRFLD_K_LP = 1 } amrfld_kmode;
+
+typedef struct {
+  int base_level;        /* coarsest level; it must cover the unit box */
+  int max_level;         /* finest level that will be built (<= 20) */
+  double robin_alpha;    /* Robin weight of the Dirichlet part, 0..1 (Sect. 3.2.3); default 0.5 */
+  int max_iter;          /* PCG iteration cap, then AMRFLD_E_NOCONV; default 10000 */
+  int precision;         /* amrfld_precision */
+  int linf_test;         /* 1: also require max |dx|/|x| < tol (Sect. 3.3.4); default 1 */
+  double abs_floor;      /* also converged when ||r|| <= abs_floor ||b||; default 1e-14 */
+  double a_rad;          /* radiation constant of the coupling term; default 1 */
+  double c_v;            /* specific heat of the coupling term; default 1 */
+  int nsub[32];          /* substeps of level l per step of level l-1; 0 means 2 */
+  int check_every;       /* PCG iterations between host convergence checks; 0 = auto */
+  int true_residual;     /* 1: compute ||b - A x|| after each solve for the stats */
+  int time_sweeps;       /* 1: time every PCG sweep with HIP events (stats pass_a_ms, pass_b_ms) */
+  void* stream;          /* hipStream_t */
+} amrfld_opts;
+
+typedef struct {
+  int level, iters, converged, status;
+  int64_t n_leaf;
+  double rel_res;        /* ||r_j|| / ||r_0|| of the recursive residual */
+  double true_rel_res;   /* ||b - A x|| / ||r_0|| (or -1 when not computed) */
+  double linf_change;    /* max |x_j - x_{j-1}| / |x_{j-1}| of the last iteration */
+  double min_E;          /* smallest leaf energy after the solve (negative energies, Sect. 3.3.5) */
+  double ms;             /* device time of the whole solve (setup + PCG + post-solve) */
+  double pcg_ms;         /* device time of the PCG iterations only */
+  double dt;
+  int outer_iters;       /* refinement sweeps (mixed precision), else 0 */
+  int n_timed;           /* sweeps of each kind timed (time_sweeps), else 0 */
+  double pass_a_ms;      /* summed device time of the timed operator sweeps (pass A) */
+  double pass_b_ms;      /* summed device time of the timed update sweeps (pass B) */
+} amrfld_stats;
+
+/* Fill *o with the defaults listed above. */
+void amrfld_default_opts(amrfld_opts* o);
+
+/* Create a context for one hierarchy.  o->base_level >= 1, base <= max <= 20. */
+amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out);
+void amrfld_destroy(amrfld_ctx* c);
+
+/* Build level `level` from a HOST array of oct coordinates oct_ijk[n_oct][3]
+ * (int32, each in [0, 2^(level-1))): the oct (I,J,K) holds cells (2I+a, 2J+b,
+ * 2K+c) and its parent cell is (I,J,K) at level-1 (Fig. 1).  Levels are built
+ * base first, then each next finer level.  The base level must list every oct
+ * of the box.  Rejected with AMRFLD_E_INVALID: out-of-range or duplicate
+ * octs, an oct whose parent cell is absent, and an oct whose parent has a face
+ * neighbour position inside the box but absent at level-1 (the hierarchy must
+ * keep face neighbours within one level, Sect. 3.1). */
+amrfld_status amrfld_build_level(amrfld_ctx* c, int level, int64_t n_oct, const int32_t* oct_ijk);
+
+/* Sizes of a built level: slots (8 per oct) and leaves (unrefined slots).
+ * cell_ijk_out, if not NULL, is a HOST int32[n_slots][3] that receives the
+ * cell coordinates in slot order. */
+amrfld_status amrfld_level_info(const amrfld_ctx* c, int level, int64_t* n_slots, int64_t* n_leaf,
+                                int32_t* cell_ijk_out);
+
+/* Set the fields of a level from DEVICE float64 arrays of n_slots values in
+ * slot order: density rho (> 0), radiative energy E (> 0 in LP mode) and gas
+ * temperature T (NULL: no coupling term on this level).  Refined slots carry the
+ * value used for their restricted cell until the next restriction replaces E.
+ * kappa_R, kappa_P: opacities per unit mass; c_light: speed of light; kmode:
+ * AMRFLD_K_CONST (K = K_const everywhere, the heat equation of Sect. 1) or
+ * AMRFLD_K_LP (K = c lambda(R) / (rho kappa_R), Sect. 2.1).  The values are
+ * copied (stream-ordered) before return. */
+amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, const double* E,
+                                const double* T, double kappa_R, double kappa_P, double c_light,
+                                int kmode, double K_const);
+
+/* Advance level `level` alone by dt: assemble its system with the interface
+ * rows of Sect. 3.2 (bc_mode for coarse-to-fine faces; fine-to-coarse faces are
+ * always Dirichlet with the current coarse energy), solve with Jacobi PCG to
+ * relative residual tol (Sect. 3.3.4), write the new leaf energies, add the
+ * fine-to-coarse face energies to the parent level's flux register in Neumann /
+ * Robin mode (eq. mean_flux) and clear this level's register.  With a
+ * temperature the coupling term is included and T is updated.
+ * Returns AMRFLD_E_NOCONV if max_iter was reached. */
+amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mode, double tol);
+
+/* One step dt_coarse of the base level with adaptive time-stepping (Sect. 2.2):
+ * step(l, dt) = { nsub(l+1) x step(l+1, dt/nsub(l+1)); restrict l+1 into l;
+ * solve_level(l, dt) }.  Returns the first non-OK status of its solves. */
+amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_mode, double tol);
+
+/* Copy a level's E (and T when T_out is not NULL) to DEVICE arrays of n_slots
+ * float64 in slot order (stream-ordered). */
+amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double* T_out);
+
+/* Stats of the solves made by the last solve / advance / batch call, in order.
+ * Writes min(max_n, count) entries to out and the count to *n. */
+amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_n, int* n);
+
+/* Message of the last failure on this context ("" if none). */
+const char* amrfld_last_error(const amrfld_ctx* c);
+
+/* Message of the last failure of amrfld_create (no context exists then). */
+const char* amrfld_create_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMRFLD_H */

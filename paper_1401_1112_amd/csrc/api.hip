@@ -1,0 +1,567 @@
+// C ABI of the level solve: context, hierarchy tables, fields, the per-level
+// solve (assembly + Jacobi PCG + post-solve) and the adaptive time-stepping
+// driver (Sect. 2.2, Sect. 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/amrfld.h"
+#include "device.h"
+#include "tables.h"
+
+using namespace amrfld;
+
+namespace {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct NoMem : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+void check(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) throw NoMem(std::string(what) + ": out of device memory");
+  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+T* dalloc(int64_t n, const char* what) {
+  void* p = nullptr;
+  if (n <= 0) n = 1;
+  check(hipMalloc(&p, size_t(n) * sizeof(T)), what);
+  return static_cast<T*>(p);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+struct LevelState {
+  LevelTables t;
+  int32_t *nbr = nullptr, *cnb = nullptr, *parent = nullptr, *child = nullptr;
+  bool child_dirty = true;
+  double *rho = nullptr, *E = nullptr, *T = nullptr, *K = nullptr;
+  double *Cp = nullptr, *diag = nullptr, *b = nullptr, *reg = nullptr;
+  bool has_fields = false, has_T = false;
+  int kmode = 1;
+  double K_const = 1.0, kappa_R = 1.0, kappa_P = 1.0, c_light = 1.0;
+
+  DevLevel dev() const {
+    DevLevel d;
+    d.n_slots = int(t.n_slots());
+    d.n_oct = int(t.n_oct);
+    d.nbr = nbr;
+    d.cnb = cnb;
+    d.child = child;
+    d.parent = parent;
+    d.dx = 1.0 / double(int64_t(1) << t.level);
+    d.vol = d.dx * d.dx * d.dx;
+    return d;
+  }
+  void release() {
+    for (void* p : {(void*)nbr, (void*)cnb, (void*)parent, (void*)child, (void*)rho, (void*)E,
+                    (void*)T, (void*)K, (void*)Cp, (void*)diag, (void*)b, (void*)reg})
+      dfree(p);
+    nbr = cnb = parent = child = nullptr;
+    rho = E = T = K = Cp = diag = b = reg = nullptr;
+  }
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct amrfld_ctx {
+  amrfld_opts o{};
+  std::string err;
+  int finest = -1;
+  std::vector<LevelState> lev;  // index: level - base
+  int64_t ws_n = 0;
+  double *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *partials = nullptr;
+  int64_t partial_n = 0;
+  PcgScalars* sc = nullptr;
+  PcgScalars* h_sc = nullptr;  // pinned
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> sweep_ev;  // 4 per iteration when sweeps are timed
+  std::vector<amrfld_stats> stats;
+
+  hipStream_t stream() const { return static_cast<hipStream_t>(o.stream); }
+  LevelState& L(int level) { return lev[level - o.base_level]; }
+  const LevelState& L(int level) const { return lev[level - o.base_level]; }
+  int nsub(int level) const {
+    const int v = (level >= 0 && level < 32) ? o.nsub[level] : 0;
+    return v > 0 ? v : 2;
+  }
+};
+
+namespace {
+
+amrfld_status fail(amrfld_ctx* c, amrfld_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+template <class F>
+amrfld_status guarded(amrfld_ctx* c, F&& f) {
+  try {
+    return f();
+  } catch (const NoMem& e) {
+    return fail(c, AMRFLD_E_NOMEM, e.what());
+  } catch (const HipError& e) {
+    return fail(c, AMRFLD_E_DEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(c, AMRFLD_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, AMRFLD_E_INVALID, e.what());
+  }
+}
+
+void ensure_workspace(amrfld_ctx* c, int64_t n) {
+  if (n > c->ws_n) {
+    dfree(c->r);
+    dfree(c->p[0]);
+    dfree(c->p[1]);
+    dfree(c->q);
+    c->r = c->p[0] = c->p[1] = c->q = nullptr;
+    c->ws_n = 0;
+    c->r = dalloc<double>(n, "workspace r");
+    c->p[0] = dalloc<double>(n, "workspace p");
+    c->p[1] = dalloc<double>(n, "workspace p");
+    c->q = dalloc<double>(n, "workspace q");
+    c->ws_n = n;
+  }
+  const int64_t g = int64_t(grid_for(n)) * 4;
+  if (g > c->partial_n) {
+    dfree(c->partials);
+    c->partials = nullptr;
+    c->partials = dalloc<double>(g, "partials");
+    c->partial_n = g;
+  }
+}
+
+void upload_tables(amrfld_ctx* c, LevelState& L) {
+  const hipStream_t s = c->stream();
+  if (!L.nbr) {
+    const int64_t n_oct = L.t.n_oct;
+    L.nbr = dalloc<int32_t>(6 * n_oct, "tables");
+    L.cnb = dalloc<int32_t>(6 * n_oct, "tables");
+    L.parent = dalloc<int32_t>(n_oct, "tables");
+    L.child = dalloc<int32_t>(8 * n_oct, "tables");
+    check(hipMemcpyAsync(L.nbr, L.t.nbr.data(), 6 * n_oct * 4, hipMemcpyHostToDevice, s), "upload");
+    check(hipMemcpyAsync(L.cnb, L.t.cnb.data(), 6 * n_oct * 4, hipMemcpyHostToDevice, s), "upload");
+    check(hipMemcpyAsync(L.parent, L.t.parent.data(), n_oct * 4, hipMemcpyHostToDevice, s), "upload");
+  }
+  if (L.child_dirty) {
+    check(hipMemcpyAsync(L.child, L.t.child.data(), 8 * L.t.n_oct * 4, hipMemcpyHostToDevice, s),
+          "upload");
+    check(hipStreamSynchronize(s), "upload");
+    L.child_dirty = false;
+  }
+}
+
+CellKParams kparams(const LevelState& L) {
+  CellKParams k;
+  k.kmode = L.kmode;
+  k.K_const = L.K_const;
+  k.kappa_R = L.kappa_R;
+  k.c_light = L.c_light;
+  return k;
+}
+
+CouplingParams cparams(const amrfld_ctx* c, const LevelState& L) {
+  CouplingParams p;
+  p.T = L.has_T ? L.T : nullptr;
+  p.kappa_P = L.kappa_P;
+  p.c_light = L.c_light;
+  p.a_rad = c->o.a_rad;
+  p.c_v = c->o.c_v;
+  return p;
+}
+
+double* ensure_reg(amrfld_ctx* c, LevelState& L) {
+  if (!L.reg) {
+    const int64_t n = 6 * L.t.n_slots();
+    L.reg = dalloc<double>(n, "flux register");
+    launch_fill(c->stream(), L.reg, n, 0.0);
+  }
+  return L.reg;
+}
+
+amrfld_status check_level_ready(amrfld_ctx* c, int level) {
+  if (level < c->o.base_level || level > c->finest)
+    return fail(c, AMRFLD_E_INVALID, "level not built");
+  if (!c->L(level).has_fields) return fail(c, AMRFLD_E_STATE, "fields of the level not set");
+  for (int l = level - 1; l >= std::max(c->o.base_level, level - 2); --l)
+    if (!c->L(l).has_fields) return fail(c, AMRFLD_E_STATE, "fields of a coarser level not set");
+  return AMRFLD_OK;
+}
+
+// One backward-Euler step of one level (Sect. 3.3.4).
+amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double tol) {
+  const hipStream_t s = c->stream();
+  LevelState& L = c->L(level);
+  LevelState* Lc = level > c->o.base_level ? &c->L(level - 1) : nullptr;
+  upload_tables(c, L);
+  if (Lc) upload_tables(c, *Lc);
+  const DevLevel D = L.dev();
+  ensure_workspace(c, D.n_slots);
+  check(hipEventRecord(c->ev[0], s), "event");
+
+  // diffusivities of this level and of the coarser one (fine-to-coarse faces)
+  if (Lc) {
+    const double* Ecc = level - 1 > c->o.base_level ? c->L(level - 2).E : nullptr;
+    launch_cell_K(s, Lc->dev(), Lc->E, Lc->rho, Ecc, kparams(*Lc), Lc->K);
+  }
+  launch_cell_K(s, D, L.E, L.rho, Lc ? Lc->E : nullptr, kparams(L), L.K);
+  const double w = mode == AMRFLD_BC_DIRICHLET ? 1.0 : mode == AMRFLD_BC_NEUMANN ? 0.0 : c->o.robin_alpha;
+  const CouplingParams cp = cparams(c, L);
+  launch_assemble(s, D, L.K, Lc ? Lc->K : nullptr, L.E, Lc ? Lc->E : nullptr, L.rho, L.reg, dt, w,
+                  cp, L.Cp, L.diag, L.b);
+
+  PcgScalars init{};
+  init.tol = tol;
+  init.abs_floor = c->o.abs_floor;
+  init.max_iter = c->o.max_iter;
+  init.linf_test = c->o.linf_test;
+  *c->h_sc = init;
+  check(hipMemcpyAsync(c->sc, c->h_sc, sizeof(PcgScalars), hipMemcpyHostToDevice, s), "scalars");
+  launch_pcg_init(s, D, L.Cp, L.diag, L.b, L.E, c->r, c->p[0], c->sc, c->partials);
+  check(hipEventRecord(c->ev[1], s), "event");
+
+  int launched = 0;
+  int chunk = c->o.check_every > 0 ? c->o.check_every : 8;
+  const bool autochunk = c->o.check_every <= 0;
+  check(hipMemcpyAsync(c->h_sc, c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
+  check(hipStreamSynchronize(s), "sync");
+  while (!c->h_sc->done && launched < c->o.max_iter) {
+    const int k = std::min(chunk, c->o.max_iter - launched);
+    if (c->o.time_sweeps) {
+      while (int(c->sweep_ev.size()) < 4 * (launched + k)) {
+        hipEvent_t e;
+        check(hipEventCreate(&e), "event");
+        c->sweep_ev.push_back(e);
+      }
+    }
+    for (int t = 0; t < k; ++t) {
+      const int it = launched + t + 1;
+      double* pn = c->p[it & 1];
+      const double* po = c->p[(it & 1) ^ 1];
+      hipEvent_t* e = c->o.time_sweeps ? &c->sweep_ev[4 * (it - 1)] : nullptr;
+      if (e) check(hipEventRecord(e[0], s), "event");
+      launch_pass_a(s, D, L.Cp, L.diag, c->r, po, pn, c->q, c->sc, c->partials);
+      if (e) check(hipEventRecord(e[1], s), "event");
+      launch_pass_b(s, D, L.diag, pn, c->q, L.E, c->r, c->sc, c->partials);
+      if (e) check(hipEventRecord(e[2], s), "event");
+    }
+    launched += k;
+    check(hipGetLastError(), "launch");
+    check(hipMemcpyAsync(c->h_sc, c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
+    check(hipStreamSynchronize(s), "sync");
+    if (autochunk && !c->h_sc->done) {
+      const PcgScalars& h = *c->h_sc;
+      const double ratio = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 1.0;
+      int est = 2 * chunk;
+      if (h.iter > 0 && ratio > 0 && ratio < 1 && h.rnorm > h.thresh) {
+        const double rate = std::log(ratio) / h.iter;  // log reduction per iteration (< 0)
+        const double need = std::log(h.thresh / h.rnorm) / rate;
+        est = int(std::ceil(need)) + 2;
+      }
+      chunk = std::max(2, std::min(256, est));
+    }
+  }
+  check(hipEventRecord(c->ev[2], s), "event");
+  if (c->o.true_residual)
+    launch_true_residual(s, D, L.Cp, L.diag, L.b, L.E, c->sc, c->partials);
+  launch_post_solve(s, D, L.E, L.rho, cp, dt, L.T, c->sc, c->partials);
+  if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN)) {
+    double* reg = ensure_reg(c, *Lc);
+    launch_flux_register(s, D, L.K, Lc->K, L.E, Lc->E, dt, reg, int(Lc->t.n_slots()));
+  }
+  if (L.reg) launch_fill(s, L.reg, 6 * L.t.n_slots(), 0.0);
+  check(hipEventRecord(c->ev[3], s), "event");
+  check(hipMemcpyAsync(c->h_sc, c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
+  check(hipStreamSynchronize(s), "sync");
+  check(hipGetLastError(), "kernels");
+
+  const PcgScalars& h = *c->h_sc;
+  amrfld_stats st{};
+  st.level = level;
+  st.iters = h.iter;
+  st.converged = h.converged;
+  st.n_leaf = L.t.n_leaf;
+  st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
+  st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+  st.linf_change = h.linf;
+  st.min_E = h.min_E;
+  st.dt = dt;
+  float ms = 0.f, pms = 0.f;
+  check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
+  check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
+  st.ms = ms;
+  st.pcg_ms = pms;
+  if (c->o.time_sweeps) {
+    // the sweeps that did work: iterations 1..iter (later launches returned at once)
+    double a = 0.0, bsum = 0.0;
+    for (int it = 1; it <= h.iter && 4 * it <= int(c->sweep_ev.size()); ++it) {
+      float ta = 0.f, tb = 0.f;
+      check(hipEventElapsedTime(&ta, c->sweep_ev[4 * (it - 1)], c->sweep_ev[4 * (it - 1) + 1]), "event");
+      check(hipEventElapsedTime(&tb, c->sweep_ev[4 * (it - 1) + 1], c->sweep_ev[4 * (it - 1) + 2]), "event");
+      a += ta;
+      bsum += tb;
+    }
+    st.n_timed = h.iter;
+    st.pass_a_ms = a;
+    st.pass_b_ms = bsum;
+  }
+  amrfld_status status = AMRFLD_OK;
+  if (h.nonfinite) status = AMRFLD_E_NONFINITE;
+  else if (!h.converged) status = AMRFLD_E_NOCONV;
+  st.status = status;
+  c->stats.push_back(st);
+  if (status == AMRFLD_E_NONFINITE)
+    return fail(c, status, "non-finite value in the residual of level " + std::to_string(level));
+  if (status == AMRFLD_E_NOCONV)
+    return fail(c, status, "PCG did not converge within max_iter on level " + std::to_string(level));
+  return AMRFLD_OK;
+}
+
+amrfld_status step(amrfld_ctx* c, int level, double dt, int mode, double tol) {
+  amrfld_status worst = AMRFLD_OK;
+  if (level < c->finest) {
+    const int ns = c->nsub(level + 1);
+    for (int k = 0; k < ns; ++k) {
+      const amrfld_status s = step(c, level + 1, dt / ns, mode, tol);
+      if (s != AMRFLD_OK && worst == AMRFLD_OK) worst = s;
+      if (s == AMRFLD_E_NONFINITE || s == AMRFLD_E_DEVICE) return s;
+    }
+    LevelState& F = c->L(level + 1);
+    launch_restrict(c->stream(), F.dev(), F.E, c->L(level).E);
+  }
+  const amrfld_status s = solve_one(c, level, dt, mode, tol);
+  return worst != AMRFLD_OK ? worst : s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void amrfld_default_opts(amrfld_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->base_level = 1;
+  o->max_level = 1;
+  o->robin_alpha = 0.5;
+  o->max_iter = 10000;
+  o->precision = AMRFLD_FP64;
+  o->linf_test = 1;
+  o->abs_floor = 1e-14;
+  o->a_rad = 1.0;
+  o->c_v = 1.0;
+  o->check_every = 0;
+  o->true_residual = 1;
+  o->stream = nullptr;
+}
+
+const char* amrfld_create_error(void) { return g_create_error.c_str(); }
+
+amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
+  g_create_error.clear();
+  if (!o || !out) {
+    g_create_error = "NULL argument";
+    return AMRFLD_E_INVALID;
+  }
+  *out = nullptr;
+  if (o->base_level < 1 || o->max_level < o->base_level || o->max_level > 20) {
+    g_create_error = "levels must satisfy 1 <= base_level <= max_level <= 20";
+    return AMRFLD_E_INVALID;
+  }
+  if (!(o->robin_alpha >= 0.0 && o->robin_alpha <= 1.0)) {
+    g_create_error = "robin_alpha must be in [0, 1]";
+    return AMRFLD_E_INVALID;
+  }
+  if (o->max_iter < 1 || !(o->abs_floor >= 0.0) || o->precision < 0 || o->precision > 1) {
+    g_create_error = "max_iter >= 1, abs_floor >= 0 and a known precision are required";
+    return AMRFLD_E_INVALID;
+  }
+  amrfld_ctx* c = nullptr;
+  try {
+    c = new amrfld_ctx();
+    c->o = *o;
+    c->lev.resize(o->max_level - o->base_level + 1);
+    c->sc = dalloc<PcgScalars>(1, "scalars");
+    check(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(PcgScalars), 0), "pinned scalars");
+    for (auto& e : c->ev) check(hipEventCreate(&e), "event");
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    amrfld_destroy(c);
+    return AMRFLD_E_DEVICE;
+  }
+  *out = c;
+  return AMRFLD_OK;
+}
+
+void amrfld_destroy(amrfld_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream());
+  for (auto& L : c->lev) L.release();
+  for (void* p : {(void*)c->r, (void*)c->p[0], (void*)c->p[1], (void*)c->q, (void*)c->partials,
+                  (void*)c->sc})
+    dfree(p);
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->sweep_ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+amrfld_status amrfld_build_level(amrfld_ctx* c, int level, int64_t n_oct, const int32_t* oct_ijk) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (!oct_ijk) return fail(c, AMRFLD_E_INVALID, "oct_ijk is NULL");
+  const int expect = c->finest < 0 ? c->o.base_level : c->finest + 1;
+  if (level != expect)
+    return fail(c, AMRFLD_E_INVALID, "levels must be built base first, one finer level at a time (expected level " +
+                                          std::to_string(expect) + ")");
+  if (level > c->o.max_level) return fail(c, AMRFLD_E_INVALID, "level above max_level");
+  return guarded(c, [&]() -> amrfld_status {
+    LevelTables t;
+    const bool base = level == c->o.base_level;
+    LevelTables* coarser = base ? nullptr : &c->L(level - 1).t;
+    // validate against a copy so that a rejected level leaves the coarser tables untouched
+    LevelTables coarse_copy;
+    if (coarser) coarse_copy = *coarser;
+    const std::string why = build_level_tables(level, base, n_oct, oct_ijk, coarser ? &coarse_copy : nullptr, &t);
+    if (!why.empty()) return fail(c, AMRFLD_E_INVALID, why);
+    if (coarser) {
+      *coarser = std::move(coarse_copy);
+      c->L(level - 1).child_dirty = true;
+    }
+    LevelState& L = c->L(level);
+    L.release();
+    L.t = std::move(t);
+    L.child_dirty = true;
+    const int64_t n = L.t.n_slots();
+    L.rho = dalloc<double>(n, "fields");
+    L.E = dalloc<double>(n, "fields");
+    L.K = dalloc<double>(n, "fields");
+    L.Cp = dalloc<double>(3 * n, "fields");
+    L.diag = dalloc<double>(n, "fields");
+    L.b = dalloc<double>(n, "fields");
+    L.has_fields = false;
+    c->finest = level;
+    upload_tables(c, L);
+    if (coarser) upload_tables(c, c->L(level - 1));
+    return AMRFLD_OK;
+  });
+}
+
+amrfld_status amrfld_level_info(const amrfld_ctx* c, int level, int64_t* n_slots, int64_t* n_leaf,
+                                int32_t* cell_ijk_out) {
+  if (!c) return AMRFLD_E_INVALID;
+  amrfld_ctx* m = const_cast<amrfld_ctx*>(c);
+  if (level < c->o.base_level || level > c->finest) return fail(m, AMRFLD_E_INVALID, "level not built");
+  const LevelState& L = c->L(level);
+  if (n_slots) *n_slots = L.t.n_slots();
+  if (n_leaf) *n_leaf = L.t.n_leaf;
+  if (cell_ijk_out) {
+    for (int64_t o = 0; o < L.t.n_oct; ++o)
+      for (int pos = 0; pos < 8; ++pos) {
+        int32_t* p = cell_ijk_out + 3 * (8 * o + pos);
+        p[0] = 2 * L.t.ijk[3 * o] + (pos & 1);
+        p[1] = 2 * L.t.ijk[3 * o + 1] + ((pos >> 1) & 1);
+        p[2] = 2 * L.t.ijk[3 * o + 2] + ((pos >> 2) & 1);
+      }
+  }
+  return AMRFLD_OK;
+}
+
+amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, const double* E,
+                                const double* T, double kappa_R, double kappa_P, double c_light,
+                                int kmode, double K_const) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (level < c->o.base_level || level > c->finest) return fail(c, AMRFLD_E_INVALID, "level not built");
+  if (!rho || !E) return fail(c, AMRFLD_E_INVALID, "rho and E are required");
+  if (kmode != AMRFLD_K_CONST && kmode != AMRFLD_K_LP) return fail(c, AMRFLD_E_INVALID, "unknown kmode");
+  if (kmode == AMRFLD_K_LP && !(kappa_R > 0.0 && c_light > 0.0))
+    return fail(c, AMRFLD_E_INVALID, "kappa_R and c_light must be positive");
+  if (kmode == AMRFLD_K_CONST && !(K_const >= 0.0)) return fail(c, AMRFLD_E_INVALID, "K_const must be >= 0");
+  if (T && !(kappa_P >= 0.0 && c_light > 0.0)) return fail(c, AMRFLD_E_INVALID, "kappa_P >= 0 and c_light > 0 needed with T");
+  return guarded(c, [&]() -> amrfld_status {
+    LevelState& L = c->L(level);
+    const int64_t n = L.t.n_slots();
+    const hipStream_t s = c->stream();
+    check(hipMemcpyAsync(L.rho, rho, n * 8, hipMemcpyDeviceToDevice, s), "set rho");
+    check(hipMemcpyAsync(L.E, E, n * 8, hipMemcpyDeviceToDevice, s), "set E");
+    if (T) {
+      if (!L.T) L.T = dalloc<double>(n, "fields");
+      check(hipMemcpyAsync(L.T, T, n * 8, hipMemcpyDeviceToDevice, s), "set T");
+    }
+    L.has_T = T != nullptr;
+    L.kmode = kmode;
+    L.K_const = K_const;
+    L.kappa_R = kappa_R;
+    L.kappa_P = kappa_P;
+    L.c_light = c_light;
+    L.has_fields = true;
+    return AMRFLD_OK;
+  });
+}
+
+amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mode, double tol) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, AMRFLD_E_INVALID, "dt must be positive");
+  if (bc_mode < 0 || bc_mode > 2) return fail(c, AMRFLD_E_INVALID, "unknown bc_mode");
+  if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
+  const amrfld_status r = check_level_ready(c, level);
+  if (r != AMRFLD_OK) return r;
+  c->stats.clear();
+  return guarded(c, [&]() { return solve_one(c, level, dt, bc_mode, tol); });
+}
+
+amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_mode, double tol) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (!(dt_coarse > 0.0) || !std::isfinite(dt_coarse)) return fail(c, AMRFLD_E_INVALID, "dt must be positive");
+  if (bc_mode < 0 || bc_mode > 2) return fail(c, AMRFLD_E_INVALID, "unknown bc_mode");
+  if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
+  if (c->finest < 0) return fail(c, AMRFLD_E_STATE, "no level built");
+  for (int l = c->o.base_level; l <= c->finest; ++l) {
+    const amrfld_status r = check_level_ready(c, l);
+    if (r != AMRFLD_OK) return r;
+  }
+  c->stats.clear();
+  return guarded(c, [&]() { return step(c, c->o.base_level, dt_coarse, bc_mode, tol); });
+}
+
+amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double* T_out) {
+  if (!c) return AMRFLD_E_INVALID;
+  amrfld_ctx* m = const_cast<amrfld_ctx*>(c);
+  if (level < c->o.base_level || level > c->finest) return fail(m, AMRFLD_E_INVALID, "level not built");
+  if (!E_out && !T_out) return fail(m, AMRFLD_E_INVALID, "no output");
+  const LevelState& L = c->L(level);
+  if (T_out && !L.has_T) return fail(m, AMRFLD_E_STATE, "level has no temperature");
+  return guarded(m, [&]() -> amrfld_status {
+    const int64_t n = L.t.n_slots();
+    if (E_out) check(hipMemcpyAsync(E_out, L.E, n * 8, hipMemcpyDeviceToDevice, c->stream()), "get E");
+    if (T_out) check(hipMemcpyAsync(T_out, L.T, n * 8, hipMemcpyDeviceToDevice, c->stream()), "get T");
+    return AMRFLD_OK;
+  });
+}
+
+amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_n, int* n) {
+  if (!c) return AMRFLD_E_INVALID;
+  const int cnt = int(c->stats.size());
+  if (n) *n = cnt;
+  if (out)
+    for (int k = 0; k < std::min(cnt, max_n); ++k) out[k] = c->stats[k];
+  return AMRFLD_OK;
+}
+
+const char* amrfld_last_error(const amrfld_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+"""Convenience wrapper over the C ABI: one context per hierarchy, torch tensors for
+device memory and the current torch stream for ordering."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class HierarchySolver:
+    def __init__(self, base_level, octs, *, robin_alpha=0.5, max_iter=10000, precision=L.FP64,
+                 linf_test=True, abs_floor=1e-14, a_rad=1.0, c_v=1.0, nsub=None, check_every=0,
+                 true_residual=True, time_sweeps=False, device="cuda:0", stream=None):
+        L.load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        o = L.amrfld_default_opts()
+        o.base_level = int(base_level)
+        o.max_level = int(max(octs))
+        o.robin_alpha = float(robin_alpha)
+        o.max_iter = int(max_iter)
+        o.precision = int(precision)
+        o.linf_test = int(bool(linf_test))
+        o.abs_floor = float(abs_floor)
+        o.a_rad = float(a_rad)
+        o.c_v = float(c_v)
+        for lvl, v in (nsub or {}).items():
+            o.nsub[int(lvl)] = int(v)
+        o.check_every = int(check_every)
+        o.true_residual = int(bool(true_residual))
+        o.time_sweeps = int(bool(time_sweeps))
+        o.stream = self.stream.cuda_stream
+        self.ctx = L.amrfld_create(o)
+        self.levels = list(range(int(base_level), int(max(octs)) + 1))
+        self._cells = {}
+        for lvl in self.levels:
+            st = L.amrfld_build_level(self.ctx, lvl, octs[lvl])
+            if st != L.OK:
+                msg = L.amrfld_last_error(self.ctx)
+                self.close()
+                raise L.AmrfldError(st, msg)
+        self._fields = {}
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            L.amrfld_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != L.OK:
+            raise L.AmrfldError(st, L.amrfld_last_error(self.ctx))
+        return st
+
+    def info(self, level):
+        ns, nl, _ = L.amrfld_level_info(self.ctx, level, want_cells=False)
+        return ns, nl
+
+    def cells(self, level):
+        if level not in self._cells:
+            self._cells[level] = L.amrfld_level_info(self.ctx, level)[2]
+        return self._cells[level]
+
+    def _dev(self, a):
+        if a is None:
+            return None
+        t = torch.as_tensor(a, dtype=torch.float64)
+        return t.to(self.device).contiguous()
+
+    def set_fields(self, level, rho, E, T=None, *, kappa_R=1.0, kappa_P=1.0, c_light=1.0,
+                   kmode=L.K_LP, K_const=1.0):
+        r, e, t = self._dev(rho), self._dev(E), self._dev(T)
+        self._fields[level] = (r, e, t)  # keep alive until the stream-ordered copy ran
+        self._check(L.amrfld_set_coeffs(self.ctx, level, r, e, t, kappa_R, kappa_P, c_light,
+                                        kmode, K_const))
+
+    def solve_level(self, level, dt, bc_mode=L.BC_DIRICHLET, tol=1e-10, raise_on_error=True):
+        st = L.amrfld_solve_level(self.ctx, level, dt, bc_mode, tol)
+        if raise_on_error and st not in (L.OK,):
+            self._check(st)
+        return st
+
+    def advance(self, dt, bc_mode=L.BC_DIRICHLET, tol=1e-10, raise_on_error=True):
+        st = L.amrfld_advance_subcycled(self.ctx, dt, bc_mode, tol)
+        if raise_on_error and st != L.OK:
+            self._check(st)
+        return st
+
+    def E(self, level, with_T=False):
+        ns, _ = self.info(level)
+        e = torch.empty(ns, dtype=torch.float64, device=self.device)
+        t = torch.empty(ns, dtype=torch.float64, device=self.device) if with_T else None
+        self._check(L.amrfld_get_E(self.ctx, level, e, t))
+        return (e, t) if with_T else e
+
+    def stats(self):
+        return L.amrfld_last_stats(self.ctx)
+
+    def last_error(self):
+        return L.amrfld_last_error(self.ctx)
+
+
+def sample_problem_fields(solver: HierarchySolver, problem):
+    """Sample a problem's fields in the library's cell order and upload them."""
+    kmode = L.K_CONST if problem.kmode == "const" else L.K_LP
+    for lvl in solver.levels:
+        c = solver.cells(lvl)
+        T = None if problem.T is None else problem.T(lvl, c)
+        solver.set_fields(lvl, problem.rho(lvl, c), problem.E(lvl, c), T, kappa_R=problem.kappa_R,
+                          kappa_P=problem.kappa_P, c_light=problem.c_light, kmode=kmode,
+                          K_const=problem.K_const)
+
+
+def solver_from_problem(problem, **over):
+    kw = dict(robin_alpha=problem.robin_alpha, max_iter=problem.max_iter, linf_test=problem.linf_test,
+              abs_floor=problem.abs_floor, a_rad=problem.a_rad, c_v=problem.c_v, nsub=problem.nsub)
+    kw.update(over)
+    s = HierarchySolver(problem.hierarchy.base_level, problem.hierarchy.octs, **kw)
+    sample_problem_fields(s, problem)
+    return s
+
+
+def to_numpy(t):
+    return t.detach().cpu().numpy() if isinstance(t, torch.Tensor) else np.asarray(t)

@@ -1,0 +1,248 @@
+"""Parity of the HIP library (through its C ABI) with the CPU FP64 oracle.
+
+Bar: relative L2 difference per level <= 1e-12 after every compared step, with
+the same PCG iteration counts; where a count differs by a near-tie at the
+stopping threshold both sides are re-run with the larger count and tol = 0.
+"""
+import numpy as np
+import pytest
+import scipy.fft
+
+from _util import align, oracle_from_problem
+import oracle as ora
+from synth.configs import config_heat_gaussian, config_tiny, config_uniform
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"dirichlet": ora.DIRICHLET, "neumann": ora.NEUMANN, "robin": ora.ROBIN}
+
+
+def _gpu():
+    import torch
+    from paper_1401_1112_amd import solver as S
+    return torch, S
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def _compare_levels(s, o, levels, tol=1e-12, label=""):
+    torch, S = _gpu()
+    worst = 0.0
+    for lvl in levels:
+        g = S.to_numpy(s.E(lvl))
+        e = align(lvl, o.cells(lvl), o.E[lvl], s.cells(lvl))
+        r = _rel(g, e)
+        worst = max(worst, r)
+        assert r <= tol, f"{label} level {lvl}: relative L2 {r:.3e}"
+    return worst
+
+
+def _iters_gpu(s):
+    return [(st["level"], st["iters"]) for st in s.stats()]
+
+
+def _iters_oracle(o, start):
+    return [(h["level"], h["iters"]) for h in o.history[start:]]
+
+
+@pytest.mark.parametrize("level,dtfac", [(4, 4.0), (5, 16.0), (6, 4.0)])
+def test_uniform_level_closed_form(level, dtfac):
+    torch, S = _gpu()
+    p = config_uniform(level, kmode="const", seed=level)
+    dx = 1.0 / (1 << level)
+    dt = dtfac * dx * dx
+    s = S.solver_from_problem(p, abs_floor=1e-16)
+    c = s.cells(level)
+    n = 1 << level
+    b = np.zeros((n, n, n))
+    b[c[:, 0], c[:, 1], c[:, 2]] = p.E(level, c)
+    s.solve_level(level, dt, 0, 1e-14)
+    x = S.to_numpy(s.E(level))
+    lam1 = 2.0 - 2.0 * np.cos(np.pi * np.arange(n) / n)
+    lam = lam1[:, None, None] + lam1[None, :, None] + lam1[None, None, :]
+    ref = scipy.fft.idctn(scipy.fft.dctn(b, type=2, norm="ortho") / (1 + dt / dx ** 2 * lam),
+                          type=2, norm="ortho")[c[:, 0], c[:, 1], c[:, 2]]
+    assert _rel(x, ref) < 1e-13
+    o = oracle_from_problem(p, abs_floor=1e-16)
+    o.solve_level(level, dt, ora.DIRICHLET, 1e-14)
+    assert s.stats()[0]["iters"] == o.history[-1]["iters"]
+    _compare_levels(s, o, [level])
+    s.close()
+
+
+def _spd_start(p, o):
+    """The level systems are SPD when K > 0: always for constant K, and in LP mode while
+    every energy is positive.  Neumann interfaces can drive energies negative (the
+    failure mode of Sect. 3.3.5); steps from such a state are outside the parity gate."""
+    return p.kmode == "const" or all(np.all(o.E[l] > 0) for l in o.lev)
+
+
+def _run_pair(p, mode, steps, tol, max_iter):
+    """Advance GPU and oracle side by side over the steps that start from an SPD state;
+    returns per-step iteration lists and the largest per-level relative L2 difference."""
+    torch, S = _gpu()
+    s = S.solver_from_problem(p, max_iter=max_iter)
+    o = oracle_from_problem(p, max_iter=max_iter)
+    counts, diffs = [], []
+    for _ in range(steps):
+        if not _spd_start(p, o):
+            break
+        start = len(o.history)
+        s.advance(p.dt_coarse, mode, tol, raise_on_error=False)
+        o.advance_subcycled(p.dt_coarse, mode, tol)
+        counts.append((_iters_gpu(s), _iters_oracle(o, start)))
+        diffs.append(_compare_levels(s, o, p.hierarchy.levels, tol=np.inf))
+    s.close()
+    return counts, diffs
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", ["dirichlet", "neumann", "robin"])
+@pytest.mark.parametrize("kmode", ["lp", "const"])
+def test_tiny_amr_advance_parity(seed, mode, kmode):
+    p = config_tiny(seed, base_level=3, max_level=5, p_refine=0.5, kmode=kmode, tol=1e-12)
+    how = _parity_protocol(p, MODES[mode], steps=2)
+    print(f"seed {seed} {mode} {kmode}: {how}")
+
+
+def test_heat_gaussian_parity_every_step():
+    p = config_heat_gaussian()
+    how = _parity_protocol(p, ora.DIRICHLET, steps=p.n_coarse_steps)
+    print(f"heat gaussian: {how}")
+
+
+def _leaf_mask(p, lvl, cells):
+    if lvl + 1 not in p.hierarchy.octs:
+        return np.ones(len(cells), dtype=bool)
+    n = np.int64(1) << lvl
+    par = p.hierarchy.octs[lvl + 1].astype(np.int64)
+    keys = set(((par[:, 0] * n + par[:, 1]) * n + par[:, 2]).tolist())
+    k = (cells[:, 0].astype(np.int64) * n + cells[:, 1]) * n + cells[:, 2]
+    return np.array([kk not in keys for kk in k.tolist()])
+
+
+def _total_energy(s, p):
+    torch, S = _gpu()
+    tot = 0.0
+    for lvl in p.hierarchy.levels:
+        c = s.cells(lvl)
+        e = S.to_numpy(s.E(lvl))
+        tot += np.sum(e[_leaf_mask(p, lvl, c)]) / float(1 << lvl) ** 3
+    return tot
+
+
+def test_neumann_conserves_dirichlet_drifts_on_gpu():
+    torch, S = _gpu()
+    out = {}
+    for mode in (ora.NEUMANN, ora.DIRICHLET):
+        p = config_tiny(2, base_level=3, max_level=5, p_refine=0.5, tol=1e-13)
+        s = S.solver_from_problem(p)
+        e0 = _total_energy(s, p)
+        s.advance(p.dt_coarse, mode, p.tol)
+        out[mode] = abs(_total_energy(s, p) - e0) / e0
+        s.close()
+    assert out[ora.NEUMANN] < 1e-12
+    assert out[ora.DIRICHLET] > 1e-6
+
+
+def test_negative_energy_reported_like_oracle():
+    # Neumann interfaces on a steep field: the coarse solve ends with negative energies
+    # (Sect. 3.3.5, Fig. 2); the GPU stats report the same minimum as the oracle.
+    torch, S = _gpu()
+    p = config_tiny(0, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-12)
+    s = S.solver_from_problem(p)
+    o = oracle_from_problem(p)
+    s.advance(p.dt_coarse, ora.NEUMANN, p.tol)
+    o.advance_subcycled(p.dt_coarse, ora.NEUMANN, p.tol)
+    g = [st["min_E"] for st in s.stats()]
+    r = [h["min_E"] for h in o.history]
+    assert min(r) < 0 and min(g) < 0
+    assert np.allclose(g, r, rtol=1e-10, atol=1e-12)
+    s.close()
+
+
+def test_noconv_returns_status_and_iterate():
+    torch, S = _gpu()
+    from paper_1401_1112_amd import E_NOCONV
+    p = config_tiny(0, base_level=3, max_level=4, tol=1e-12)
+    s = S.solver_from_problem(p, max_iter=1)
+    st = s.solve_level(3, p.dt_coarse, 0, 1e-12, raise_on_error=False)
+    assert st == E_NOCONV
+    assert s.stats()[0]["iters"] == 1 and s.stats()[0]["converged"] == 0
+    o = oracle_from_problem(p, max_iter=1)
+    o.solve_level(3, p.dt_coarse, ora.DIRICHLET, 1e-12)
+    _compare_levels(s, o, [3])
+    s.close()
+
+
+def test_nan_density_is_nonfinite():
+    torch, S = _gpu()
+    from paper_1401_1112_amd import E_NONFINITE
+    p = config_uniform(3, kmode="lp")
+    s = S.solver_from_problem(p)
+    c = s.cells(3)
+    rho = p.rho(3, c)
+    rho[5] = np.nan
+    s.set_fields(3, rho, p.E(3, c))
+    assert s.solve_level(3, p.dt_coarse, 0, 1e-10, raise_on_error=False) == E_NONFINITE
+    s.close()
+
+
+def test_unbalanced_level_rejected():
+    torch, S = _gpu()
+    from paper_1401_1112_amd import AmrfldError
+    octs = {2: np.array([[i, j, k] for i in range(2) for j in range(2) for k in range(2)], dtype=np.int32),
+            3: np.array([[0, 0, 0]], dtype=np.int32),
+            4: np.array([[0, 0, 0], [1, 0, 0]], dtype=np.int32)}
+    # oct (1,0,0) at level 4 has parent cell (1,0,0) at level 3, which exists; its +x
+    # neighbour cell (2,0,0) at level 3 is absent -> unbalanced
+    with pytest.raises(AmrfldError):
+        S.HierarchySolver(2, octs)
+
+
+def test_constant_state_zero_iterations():
+    torch, S = _gpu()
+    p = config_tiny(4, base_level=2, max_level=4, p_refine=0.5)
+    s = S.solver_from_problem(p)
+    for lvl in p.hierarchy.levels:
+        ns, _ = s.info(lvl)
+        s.set_fields(lvl, np.linspace(0.5, 2.0, ns), np.full(ns, 3.25))
+    for mode in (0, 1, 2):
+        s.advance(0.05, mode, 1e-10)
+        assert all(st["iters"] == 0 for st in s.stats())
+    for lvl in p.hierarchy.levels:
+        assert np.all(S.to_numpy(s.E(lvl)) == 3.25)
+    s.close()
+
+
+def test_deterministic_bitwise():
+    torch, S = _gpu()
+    res = []
+    for _ in range(2):
+        p = config_tiny(3, base_level=3, max_level=5, p_refine=0.5)
+        s = S.solver_from_problem(p)
+        s.advance(p.dt_coarse, 2, 1e-12)
+        res.append([S.to_numpy(s.E(l)).copy() for l in p.hierarchy.levels])
+        s.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_coupled_temperature_parity():
+    torch, S = _gpu()
+    p = config_tiny(5, base_level=3, max_level=4, p_refine=0.5, tol=1e-12)
+    p.T = lambda lvl, c: (p.E(lvl, c) ** 0.25) * 1.05
+    p.kappa_P = 2.0
+    s = S.solver_from_problem(p)
+    o = oracle_from_problem(p)
+    s.advance(p.dt_coarse, 0, p.tol)
+    o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, p.tol)
+    _compare_levels(s, o, p.hierarchy.levels)
+    for lvl in p.hierarchy.levels:
+        _, t = s.E(lvl, with_T=True)
+        tt = align(lvl, o.cells(lvl), o.T[lvl], s.cells(lvl))
+        assert _rel(S.to_numpy(t), tt) < 1e-12
+    s.close()
