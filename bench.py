@@ -38,6 +38,23 @@ PASS_B_BYTES = 5 * 8 + 2 * 8
 METRIC = "PCG cell-iterations/s + HBM GB/s vs peak; FP64 vs mixed+batched at 1e-10"
 
 
+def _measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "fld_lognormal_L6-9_fp64_hbm_counters.txt")
+    src = os.path.join(ROOT, "paper_1401_1112_amd", "csrc", "pcg.hip")
+    try:
+        kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
+                  if line.startswith("traffic_"))
+    except OSError:
+        return None
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("traffic_kernel") != kernel or kv.get("traffic_source_sha256_prefix") != cur:
+        return None
+    return float(kv["traffic_kib_per_dispatch"]) * 1024.0
+
+
 def _problem():
     from synth.configs import config_fld_lognormal
     return config_fld_lognormal()
@@ -91,9 +108,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-time-sweeps", action="store_true",
-                    help="do not bracket the PCG sweeps with HIP events")
+    ap.add_argument("--time-period", type=int, default=16,
+                    help="bracket the two sweeps of every N-th PCG iteration with HIP events (0: off)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--max-blocks", type=int, default=0, help="blocks per PCG sweep (0: library default)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -108,7 +126,7 @@ def main(argv=None):
     t_gen = time.perf_counter()
     p = _problem()
     t_gen = time.perf_counter() - t_gen
-    s = solver_from_problem(p, time_sweeps=not args.no_time_sweeps)
+    s = solver_from_problem(p, time_sweeps=args.time_period, max_blocks=args.max_blocks)
     init = {lvl: (s._fields[lvl][0].clone(), s._fields[lvl][1].clone()) for lvl in s.levels}
     kmode = 1
 
@@ -145,10 +163,16 @@ def main(argv=None):
     roofline = None
     if a_ms > 0:
         achieved = a_bytes / (a_ms * 1e-3) / 1e9
+        traffic = _measured_traffic("k_pass_a<double>")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else round(traffic),
+                    "traffic_note": "measured HBM bytes per pass-A dispatch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
+                                    "copy-calibrated), profiles/fld_lognormal_L6-9_fp64_hbm_counters.txt",
+                    "alg_bytes_per_launch": round(a_bytes / max(n_a, 1)),
                     "kernel": "k_pass_a (p update + 7-point operator + (p,q) partials)",
-                    "bytes_per_slot": PASS_A_BYTES, "launches": n_a,
+                    "bytes_per_slot": PASS_A_BYTES, "timed_launches": n_a,
+                    "timing": f"HIP events around the sweeps of every {args.time_period}th PCG iteration",
                     "avg_launch_us": round(a_ms * 1e3 / max(n_a, 1), 2),
                     "pass_b_GBs": round(b_bytes / (b_ms * 1e-3) / 1e9, 1) if b_ms > 0 else None,
                     "pass_b_bytes_per_slot": PASS_B_BYTES}

@@ -74,7 +74,10 @@ typedef struct {
   int nsub[32];          /* substeps of level l per step of level l-1; 0 means 2 */
   int check_every;       /* PCG iterations between host convergence checks; 0 = auto */
   int true_residual;     /* 1: compute ||b - A x|| after each solve for the stats */
-  int time_sweeps;       /* 1: time every PCG sweep with HIP events (stats pass_a_ms, pass_b_ms) */
+  int time_sweeps;       /* N > 0: time the two sweeps of every N-th PCG iteration with HIP events */
+  double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner solve; default 1e-4 */
+  int max_outer;         /* AMRFLD_MIXED: refinement sweeps cap; default 30 */
+  int max_blocks;        /* blocks per PCG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
   void* stream;          /* hipStream_t */
 } amrfld_opts;
 
@@ -89,7 +92,7 @@ typedef struct {
   double pcg_ms;         /* device time of the PCG iterations only */
   double dt;
   int outer_iters;       /* refinement sweeps (mixed precision), else 0 */
-  int n_timed;           /* sweeps of each kind timed (time_sweeps), else 0 */
+  int n_timed;           /* iterations whose sweeps were timed (time_sweeps), else 0 */
   double pass_a_ms;      /* summed device time of the timed operator sweeps (pass A) */
   double pass_b_ms;      /* summed device time of the timed update sweeps (pass B) */
 } amrfld_stats;

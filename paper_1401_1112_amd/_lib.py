@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libamrfld.so")
+LIB_PATH = os.environ.get("AMRFLD_LIB") or os.path.join(_HERE, "libamrfld.so")
 
 OK, E_INVALID, E_STATE, E_NOMEM, E_DEVICE, E_NOCONV, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_DEVICE",
@@ -30,6 +30,7 @@ class amrfld_opts(ctypes.Structure):
         ("abs_floor", ctypes.c_double), ("a_rad", ctypes.c_double), ("c_v", ctypes.c_double),
         ("nsub", ctypes.c_int * 32), ("check_every", ctypes.c_int),
         ("true_residual", ctypes.c_int), ("time_sweeps", ctypes.c_int),
+        ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_blocks", ctypes.c_int),
         ("stream", ctypes.c_void_p),
     ]
 

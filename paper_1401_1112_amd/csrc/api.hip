@@ -86,8 +86,13 @@ struct amrfld_ctx {
   int64_t ws_n = 0;
   double *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *partials = nullptr;
   int64_t partial_n = 0;
-  PcgScalars* sc = nullptr;
-  PcgScalars* h_sc = nullptr;  // pinned
+  // mixed-precision workspace
+  int64_t ws32_n = 0;
+  float *Cp32 = nullptr, *diag32 = nullptr, *r32 = nullptr, *d32 = nullptr, *p32[2] = {nullptr, nullptr},
+        *q32 = nullptr;
+  double* x_alt = nullptr;
+  PcgScalars* sc = nullptr;     // [2]: outer / plain solve, inner solve
+  PcgScalars* h_sc = nullptr;   // pinned [2]
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> sweep_ev;  // 4 per iteration when sweeps are timed
   std::vector<amrfld_stats> stats;
@@ -137,13 +142,32 @@ void ensure_workspace(amrfld_ctx* c, int64_t n) {
     c->q = dalloc<double>(n, "workspace q");
     c->ws_n = n;
   }
-  const int64_t g = int64_t(grid_for(n)) * 4;
+  const int64_t g = int64_t(tiles_of(n)) * 4;
   if (g > c->partial_n) {
     dfree(c->partials);
     c->partials = nullptr;
     c->partials = dalloc<double>(g, "partials");
     c->partial_n = g;
   }
+}
+
+void ensure_workspace32(amrfld_ctx* c, int64_t n) {
+  if (n <= c->ws32_n) return;
+  for (void* p : {(void*)c->Cp32, (void*)c->diag32, (void*)c->r32, (void*)c->d32, (void*)c->p32[0],
+                  (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
+    dfree(p);
+  c->Cp32 = c->diag32 = c->r32 = c->d32 = c->p32[0] = c->p32[1] = c->q32 = nullptr;
+  c->x_alt = nullptr;
+  c->ws32_n = 0;
+  c->Cp32 = dalloc<float>(3 * n, "workspace fp32");
+  c->diag32 = dalloc<float>(n, "workspace fp32");
+  c->r32 = dalloc<float>(n, "workspace fp32");
+  c->d32 = dalloc<float>(n, "workspace fp32");
+  c->p32[0] = dalloc<float>(n, "workspace fp32");
+  c->p32[1] = dalloc<float>(n, "workspace fp32");
+  c->q32 = dalloc<float>(n, "workspace fp32");
+  c->x_alt = dalloc<double>(n, "workspace x");
+  c->ws32_n = n;
 }
 
 void upload_tables(amrfld_ctx* c, LevelState& L) {
@@ -203,6 +227,138 @@ amrfld_status check_level_ready(amrfld_ctx* c, int level) {
   return AMRFLD_OK;
 }
 
+struct LoopStats {
+  int inner_iters = 0;
+  int n_timed = 0;
+  double a_ms = 0.0, b_ms = 0.0;
+};
+
+void read_scalars(amrfld_ctx* c, int count) {
+  const hipStream_t s = c->stream();
+  check(hipMemcpyAsync(c->h_sc, c->sc, count * sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
+  check(hipStreamSynchronize(s), "sync");
+}
+
+// Iterations of one PCG solve whose start sweeps already ran: batches of
+// (operator sweep, update sweep) pairs, a stopping check after each batch, the
+// next batch size predicted from the observed convergence rate.
+template <typename T>
+void pcg_iterations(amrfld_ctx* c, const DevLevel& D, int G, const T* Cp, const T* diag, T* x, T* r, T* const* p,
+                    T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int sc_index, int max_iter, LoopStats* ls) {
+  const hipStream_t s = c->stream();
+  int launched = 0;
+  int chunk = c->o.check_every > 0 ? c->o.check_every : 8;
+  const bool autochunk = c->o.check_every <= 0;
+  read_scalars(c, 2);
+  while (!sc_host->done && launched < max_iter) {
+    const int k = std::min(chunk, max_iter - launched);
+    const int period = c->o.time_sweeps;
+    if (period > 0) {
+      while (int(c->sweep_ev.size()) < 3 * ((launched + k) / period + 1)) {
+        hipEvent_t e;
+        check(hipEventCreate(&e), "event");
+        c->sweep_ev.push_back(e);
+      }
+    }
+    for (int t = 0; t < k; ++t) {
+      const int it = launched + t + 1;
+      T* pn = p[it & 1];
+      const T* po = p[(it & 1) ^ 1];
+      hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[3 * (it / period - 1)] : nullptr;
+      if (e) check(hipEventRecord(e[0], s), "event");
+      launch_pass_a<T>(s, D, G, it, Cp, diag, r, po, pn, q, sc_dev, c->partials);
+      if (e) check(hipEventRecord(e[1], s), "event");
+      launch_pass_b<T>(s, D, G, it, diag, pn, q, x, r, sc_dev, c->partials);
+      if (e) check(hipEventRecord(e[2], s), "event");
+    }
+    launched += k;
+    launch_check(s, G, launched, sc_dev, c->partials);
+    check(hipGetLastError(), "launch");
+    read_scalars(c, 2);
+    if (autochunk && !sc_host->done) {
+      const PcgScalars& h = *sc_host;
+      const double ratio = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 1.0;
+      int est = 2 * chunk;
+      if (h.iter > 0 && ratio > 0 && ratio < 1 && h.rnorm > h.thresh) {
+        const double rate = std::log(ratio) / h.iter;  // log reduction per iteration (< 0)
+        const double need = std::log(h.thresh / h.rnorm) / rate;
+        est = int(std::ceil(need)) + 1;
+      }
+      chunk = std::max(2, std::min(256, est));
+    }
+  }
+  (void)sc_index;
+  const int done_iters = sc_host->iter;
+  const int period = c->o.time_sweeps;
+  if (period > 0) {
+    // timed iterations that did work (launches after convergence returned at once)
+    for (int it = period; it <= done_iters && 3 * (it / period) <= int(c->sweep_ev.size()); it += period) {
+      const int k = it / period - 1;
+      float ta = 0.f, tb = 0.f;
+      check(hipEventElapsedTime(&ta, c->sweep_ev[3 * k], c->sweep_ev[3 * k + 1]), "event");
+      check(hipEventElapsedTime(&tb, c->sweep_ev[3 * k + 1], c->sweep_ev[3 * k + 2]), "event");
+      ls->a_ms += ta;
+      ls->b_ms += tb;
+      ls->n_timed += 1;
+    }
+  }
+  ls->inner_iters += done_iters;
+}
+
+void init_scalars(amrfld_ctx* c, PcgScalars* host, double tol, double abs_floor, int max_iter, int linf_test) {
+  PcgScalars init{};
+  init.tol = tol;
+  init.abs_floor = abs_floor;
+  init.max_iter = max_iter;
+  init.linf_test = linf_test;
+  *host = init;
+}
+
+void pcg_fp64(amrfld_ctx* c, const DevLevel& D, LevelState& L, int G, double tol, LoopStats* ls) {
+  const hipStream_t s = c->stream();
+  init_scalars(c, &c->h_sc[0], tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
+  check(hipMemcpyAsync(c->sc, c->h_sc, sizeof(PcgScalars), hipMemcpyHostToDevice, s), "scalars");
+  launch_pcg_init<double>(s, D, G, L.Cp, L.diag, L.b, L.E, c->r, c->p[0], c->partials);
+  launch_init_finish(s, G, c->partials, c->sc);
+  check(hipEventRecord(c->ev[1], s), "event");
+  pcg_iterations<double>(c, D, G, L.Cp, L.diag, L.E, c->r, c->p, c->q, c->sc, &c->h_sc[0], 0,
+                         c->o.max_iter, ls);
+}
+
+// FP32 inner PCG on A d = r inside an FP64 iterative-refinement loop: the FP64
+// sweep applies x += d and forms the true residual r = b - A x; the inner solve
+// uses FP32 coefficients, vectors and operator arithmetic with FP64 dot products.
+void pcg_mixed(amrfld_ctx* c, const DevLevel& D, LevelState& L, int G, double tol, LoopStats* ls) {
+  const hipStream_t s = c->stream();
+  const int64_t n = D.n_slots;
+  ensure_workspace32(c, n);
+  launch_to_f32(s, n, L.Cp, L.diag, c->Cp32, c->diag32);
+  init_scalars(c, &c->h_sc[0], tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
+  init_scalars(c, &c->h_sc[1], c->o.inner_tol, 0.0, c->o.max_iter, 0);
+  check(hipMemcpyAsync(c->sc, c->h_sc, 2 * sizeof(PcgScalars), hipMemcpyHostToDevice, s), "scalars");
+  check(hipEventRecord(c->ev[1], s), "event");
+  double* x_cur = L.E;
+  double* x_nxt = c->x_alt;
+  const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
+  int budget = c->o.max_iter;
+  for (int outer = 0; outer <= max_outer; ++outer) {
+    launch_ir_sweep(s, D, G, L.Cp, L.diag, L.b, x_cur, outer == 0 ? nullptr : c->d32, x_nxt, c->r32,
+                    c->partials);
+    std::swap(x_cur, x_nxt);
+    launch_ir_finish(s, G, outer == 0 ? 1 : 0, c->o.inner_tol, std::max(1, budget), &c->sc[0], &c->sc[1],
+                     c->partials);
+    read_scalars(c, 2);
+    if (c->h_sc[0].done || outer == max_outer || budget <= 0) break;
+    launch_inner_init(s, D, G, c->diag32, c->r32, c->d32, c->p32[0], c->partials);
+    launch_init_finish(s, G, c->partials, &c->sc[1]);
+    const int before = ls->inner_iters;
+    pcg_iterations<float>(c, D, G, c->Cp32, c->diag32, c->d32, c->r32, c->p32, c->q32, &c->sc[1], &c->h_sc[1],
+                          1, std::max(1, budget), ls);
+    budget -= ls->inner_iters - before;
+  }
+  if (x_cur != L.E) check(hipMemcpyAsync(L.E, x_cur, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy x");
+}
+
 // One backward-Euler step of one level (Sect. 3.3.4).
 amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double tol) {
   const hipStream_t s = c->stream();
@@ -225,61 +381,17 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   launch_assemble(s, D, L.K, Lc ? Lc->K : nullptr, L.E, Lc ? Lc->E : nullptr, L.rho, L.reg, dt, w,
                   cp, L.Cp, L.diag, L.b);
 
-  PcgScalars init{};
-  init.tol = tol;
-  init.abs_floor = c->o.abs_floor;
-  init.max_iter = c->o.max_iter;
-  init.linf_test = c->o.linf_test;
-  *c->h_sc = init;
-  check(hipMemcpyAsync(c->sc, c->h_sc, sizeof(PcgScalars), hipMemcpyHostToDevice, s), "scalars");
-  launch_pcg_init(s, D, L.Cp, L.diag, L.b, L.E, c->r, c->p[0], c->sc, c->partials);
-  check(hipEventRecord(c->ev[1], s), "event");
-
-  int launched = 0;
-  int chunk = c->o.check_every > 0 ? c->o.check_every : 8;
-  const bool autochunk = c->o.check_every <= 0;
-  check(hipMemcpyAsync(c->h_sc, c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
-  check(hipStreamSynchronize(s), "sync");
-  while (!c->h_sc->done && launched < c->o.max_iter) {
-    const int k = std::min(chunk, c->o.max_iter - launched);
-    if (c->o.time_sweeps) {
-      while (int(c->sweep_ev.size()) < 4 * (launched + k)) {
-        hipEvent_t e;
-        check(hipEventCreate(&e), "event");
-        c->sweep_ev.push_back(e);
-      }
-    }
-    for (int t = 0; t < k; ++t) {
-      const int it = launched + t + 1;
-      double* pn = c->p[it & 1];
-      const double* po = c->p[(it & 1) ^ 1];
-      hipEvent_t* e = c->o.time_sweeps ? &c->sweep_ev[4 * (it - 1)] : nullptr;
-      if (e) check(hipEventRecord(e[0], s), "event");
-      launch_pass_a(s, D, L.Cp, L.diag, c->r, po, pn, c->q, c->sc, c->partials);
-      if (e) check(hipEventRecord(e[1], s), "event");
-      launch_pass_b(s, D, L.diag, pn, c->q, L.E, c->r, c->sc, c->partials);
-      if (e) check(hipEventRecord(e[2], s), "event");
-    }
-    launched += k;
-    check(hipGetLastError(), "launch");
-    check(hipMemcpyAsync(c->h_sc, c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
-    check(hipStreamSynchronize(s), "sync");
-    if (autochunk && !c->h_sc->done) {
-      const PcgScalars& h = *c->h_sc;
-      const double ratio = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 1.0;
-      int est = 2 * chunk;
-      if (h.iter > 0 && ratio > 0 && ratio < 1 && h.rnorm > h.thresh) {
-        const double rate = std::log(ratio) / h.iter;  // log reduction per iteration (< 0)
-        const double need = std::log(h.thresh / h.rnorm) / rate;
-        est = int(std::ceil(need)) + 2;
-      }
-      chunk = std::max(2, std::min(256, est));
-    }
+  const int G = sweep_blocks(tiles_of(D.n_slots), c->o.max_blocks > 0 ? c->o.max_blocks : 1024);
+  LoopStats ls;
+  if (c->o.precision == AMRFLD_MIXED) {
+    pcg_mixed(c, D, L, G, tol, &ls);
+  } else {
+    pcg_fp64(c, D, L, G, tol, &ls);
   }
   check(hipEventRecord(c->ev[2], s), "event");
-  if (c->o.true_residual)
-    launch_true_residual(s, D, L.Cp, L.diag, L.b, L.E, c->sc, c->partials);
-  launch_post_solve(s, D, L.E, L.rho, cp, dt, L.T, c->sc, c->partials);
+  if (c->o.true_residual && c->o.precision != AMRFLD_MIXED)
+    launch_true_residual(s, D, G, L.Cp, L.diag, L.b, L.E, c->sc, c->partials);
+  launch_post_solve(s, D, G, L.E, L.rho, cp, dt, L.T, c->sc, c->partials);
   if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN)) {
     double* reg = ensure_reg(c, *Lc);
     launch_flux_register(s, D, L.K, Lc->K, L.E, Lc->E, dt, reg, int(Lc->t.n_slots()));
@@ -297,7 +409,13 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   st.converged = h.converged;
   st.n_leaf = L.t.n_leaf;
   st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
-  st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+  if (c->o.precision == AMRFLD_MIXED) {
+    st.iters = ls.inner_iters;
+    st.outer_iters = h.iter;
+    st.true_rel_res = st.rel_res;  // the outer residual is the FP64 true residual
+  } else {
+    st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+  }
   st.linf_change = h.linf;
   st.min_E = h.min_E;
   st.dt = dt;
@@ -306,20 +424,9 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
   st.ms = ms;
   st.pcg_ms = pms;
-  if (c->o.time_sweeps) {
-    // the sweeps that did work: iterations 1..iter (later launches returned at once)
-    double a = 0.0, bsum = 0.0;
-    for (int it = 1; it <= h.iter && 4 * it <= int(c->sweep_ev.size()); ++it) {
-      float ta = 0.f, tb = 0.f;
-      check(hipEventElapsedTime(&ta, c->sweep_ev[4 * (it - 1)], c->sweep_ev[4 * (it - 1) + 1]), "event");
-      check(hipEventElapsedTime(&tb, c->sweep_ev[4 * (it - 1) + 1], c->sweep_ev[4 * (it - 1) + 2]), "event");
-      a += ta;
-      bsum += tb;
-    }
-    st.n_timed = h.iter;
-    st.pass_a_ms = a;
-    st.pass_b_ms = bsum;
-  }
+  st.n_timed = ls.n_timed;
+  st.pass_a_ms = ls.a_ms;
+  st.pass_b_ms = ls.b_ms;
   amrfld_status status = AMRFLD_OK;
   if (h.nonfinite) status = AMRFLD_E_NONFINITE;
   else if (!h.converged) status = AMRFLD_E_NOCONV;
@@ -366,6 +473,9 @@ void amrfld_default_opts(amrfld_opts* o) {
   o->c_v = 1.0;
   o->check_every = 0;
   o->true_residual = 1;
+  o->inner_tol = 1e-4;
+  o->max_outer = 30;
+  o->max_blocks = 0;
   o->stream = nullptr;
 }
 
@@ -395,8 +505,8 @@ amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
     c = new amrfld_ctx();
     c->o = *o;
     c->lev.resize(o->max_level - o->base_level + 1);
-    c->sc = dalloc<PcgScalars>(1, "scalars");
-    check(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(PcgScalars), 0), "pinned scalars");
+    c->sc = dalloc<PcgScalars>(2, "scalars");
+    check(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), 2 * sizeof(PcgScalars), 0), "pinned scalars");
     for (auto& e : c->ev) check(hipEventCreate(&e), "event");
   } catch (const std::exception& e) {
     g_create_error = e.what();
@@ -412,7 +522,8 @@ void amrfld_destroy(amrfld_ctx* c) {
   (void)hipStreamSynchronize(c->stream());
   for (auto& L : c->lev) L.release();
   for (void* p : {(void*)c->r, (void*)c->p[0], (void*)c->p[1], (void*)c->q, (void*)c->partials,
-                  (void*)c->sc})
+                  (void*)c->sc, (void*)c->Cp32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
+                  (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
     dfree(p);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   for (auto& e : c->ev)

@@ -1,0 +1,132 @@
+// Device helpers shared by the setup and PCG kernels.
+//
+// Layout: a level's cells are "slots", 8 per oct, octs in Morton order, x
+// fastest inside an oct, so slot i lives in oct i >> 3 at position i & 7 and
+// its in-oct face neighbour along axis a is slot i ^ (1 << a).  A 64-wide
+// wavefront therefore holds 8 whole octs and in-oct neighbours are exchanged
+// with cross-lane shuffles; the three faces of a cell that leave its oct go
+// through the per-oct neighbour table.
+//
+// The operator is stored symmetric: Cp[a][i] is the coefficient of the face
+// between slot i and its +a neighbour when both are leaves of the level and
+// zero otherwise; the -a face of slot i is Cp[a] of the -a neighbour.  Refined
+// slots carry an identity row (diag 1, all coefficients 0, r = 0), so sweeps run
+// over every slot without branching on the cell type.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "device.h"
+
+namespace amrfld {
+namespace dev {
+
+__device__ __forceinline__ int same_level_nb(const int32_t* __restrict__ nbr, int i, int dir) {
+  const int pos = i & 7, axis = dir >> 1, side = dir & 1, bit = 1 << axis;
+  if (((pos >> axis) & 1) != side) return i ^ bit;
+  const int n = nbr[(i >> 3) * 6 + dir];
+  return n < 0 ? -1 : ((n << 3) | (pos ^ bit));
+}
+
+__device__ __forceinline__ double harmonic(double a, double b) {
+  const double s = a + b;
+  return s != 0.0 ? (2.0 * a * b) / s : 0.0;
+}
+
+// Block-wide reduction; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV], double* lds) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_down(v[k], off, 64);
+      v[k] = is_max[k] ? fmax(v[k], o) : v[k] + o;
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double t = lds[k];
+      for (int w = 1; w < kBlock / 64; ++w) t = is_max[k] ? fmax(t, lds[w * NV + k]) : t + lds[w * NV + k];
+      v[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// Sum (or max) of the NV-wide partials of the G blocks of the previous sweep,
+// in a fixed order, made available to every thread of the block.  Every block
+// computes the same bits, so the scalars derived from it agree everywhere.
+template <int NV>
+__device__ __forceinline__ void reduce_partials_all(const double* __restrict__ part, int G,
+                                                    const bool (&is_max)[NV], double (&out)[NV],
+                                                    double* lds) {
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = is_max[k] ? -DBL_MAX : 0.0;
+  for (int g = threadIdx.x; g < G; g += kBlock) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double t = part[g * NV + k];
+      v[k] = is_max[k] ? fmax(v[k], t) : v[k] + t;
+    }
+  }
+  block_reduce<NV>(v, is_max, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = lds[k];
+  __syncthreads();
+}
+
+// Contiguous range of 256-slot tiles of this block.  Blocks are dealt to the
+// XCDs round-robin, so block b is mapped to chunk (b % 8) * (G / 8) + b / 8:
+// each XCD then sweeps one contiguous eighth of the Morton order and the
+// neighbour octs it gathers are mostly in its own L2.
+__device__ __forceinline__ void tile_range(int n_tiles, int& t0, int& t1) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int c = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  t0 = int((int64_t(n_tiles) * c) / G);
+  t1 = int((int64_t(n_tiles) * (c + 1)) / G);
+}
+
+// The 7-point operator at slot ii applied to a vector whose value at ii is pi
+// and at other slots is get(j).  T is the storage and arithmetic type.
+template <typename T, class Get>
+__device__ __forceinline__ T apply_stencil(int ii, const int32_t* __restrict__ nbr,
+                                           const T* __restrict__ Cp, int n, T di, T pi, Get get) {
+  const int pos = ii & 7, o = ii >> 3;
+  T acc = di * pi;
+#pragma unroll
+  for (int axis = 0; axis < 3; ++axis) {
+    const int bit = 1 << axis;
+    const T* __restrict__ Ca = Cp + size_t(axis) * n;
+    const T c_own = Ca[ii];
+    const T p_sib = __shfl_xor(pi, bit, 64);
+    const T c_sib = __shfl_xor(c_own, bit, 64);
+    const int my = (pos >> axis) & 1;
+    acc -= (my ? c_sib : c_own) * p_sib;
+    const int nb = nbr[o * 6 + 2 * axis + my];
+    if (nb >= 0) {
+      const int j = (nb << 3) | (pos ^ bit);
+      const T c_out = my ? c_own : Ca[j];
+      if (c_out != T(0)) acc -= c_out * get(j);
+    }
+  }
+  return acc;
+}
+
+}  // namespace dev
+}  // namespace amrfld

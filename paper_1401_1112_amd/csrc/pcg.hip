@@ -1,0 +1,600 @@
+// Jacobi-preconditioned conjugate gradient on one level (Sect. 3.3.4) as two
+// fused sweeps per iteration, plus the FP64 iterative-refinement sweeps of the
+// mixed-precision form.
+//
+// Reductions without atomics: every sweep runs G blocks, each block sweeps a
+// contiguous range of 256-slot tiles and writes one partial per reduced
+// quantity.  The NEXT sweep reduces all G partials at its head, in the same
+// fixed order in every block, and derives alpha, beta and the stopping
+// decision itself; the kernel boundary makes the partials visible.  Runs are
+// therefore bitwise reproducible.  Scalars that a sweep writes and later
+// sweeps read are double-buffered by iteration parity.
+//
+// Partial buffer: [0, G) operator-sweep partial (p, q); [G, 4G) update-sweep
+// partials (r, z), ||r||^2, max relative change (also used by the start sweeps).
+#include <algorithm>
+
+#include "common.h"
+
+namespace amrfld {
+
+// At most kMaxTilesPerBlock tiles per block: the operator sweep stages the
+// block's whole range of the new p in LDS (16 tiles = 32 KB in FP64).
+int sweep_blocks(int n_tiles, int max_blocks) {
+  const int g = std::max(1, std::min(n_tiles, max_blocks));
+  return std::max(g, (n_tiles + kMaxTilesPerBlock - 1) / kMaxTilesPerBlock);
+}
+
+namespace {
+
+using dev::apply_stencil;
+using dev::block_reduce;
+using dev::reduce_partials_all;
+using dev::tile_range;
+
+constexpr int kLds = (kBlock / 64) * 3 + 4;
+
+template <typename T>
+__device__ __forceinline__ T rel_change(T x, T dx) {
+  const T ax = fabs(x);
+  return ax > T(0) ? fabs(dx) / ax : fabs(dx);
+}
+
+// Stopping test of Sect. 3.3.4 for the iterate completed by the previous update
+// sweep: ||r|| <= thresh AND (optionally) the largest relative change < tol.
+struct StopTest {
+  double rz, rn, linf;
+  bool fin, conv, stop;
+};
+
+__device__ __forceinline__ StopTest stop_test(const PcgScalars* sc, const double* part, int G, int it_done,
+                                              double* lds) {
+  double v[3];
+  const bool mx[3] = {false, false, true};
+  reduce_partials_all<3>(part + G, G, mx, v, lds);
+  StopTest s;
+  s.rz = v[0];
+  s.rn = sqrt(v[1]);
+  s.linf = v[2];
+  s.fin = isfinite(s.rn) && isfinite(s.rz);
+  s.conv = s.fin && ((s.rn <= sc->thresh && (!sc->linf_test || s.linf < sc->tol)) || s.rn == 0.0);
+  s.stop = !s.fin || s.conv || it_done >= sc->max_iter;
+  return s;
+}
+
+__device__ __forceinline__ void record_stop(PcgScalars* sc, const StopTest& s, int it_done) {
+  sc->rnorm = s.rn;
+  sc->linf = s.linf;
+  sc->iter = it_done;
+  if (s.stop) {
+    sc->converged = s.conv ? 1 : 0;
+    sc->nonfinite = s.fin ? 0 : 1;
+    sc->done = 1;
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&v)[NV], const bool (&mx)[NV], double* dst, double* lds) {
+  block_reduce<NV>(v, mx, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) dst[blockIdx.x * NV + k] = v[k];
+  }
+}
+
+// r0 = b - A x0, p = 0; partials (r, r / d), ||r||^2, ||b||^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, int n_tiles, const T* __restrict__ Cp,
+                                                     const T* __restrict__ diag, const T* __restrict__ b,
+                                                     const T* __restrict__ x, T* __restrict__ r,
+                                                     T* __restrict__ p_clear, double* part) {
+  __shared__ double lds[kLds];
+  const int n = L.n_slots;
+  int t0, t1;
+  tile_range(n_tiles, t0, t1);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + int(threadIdx.x);
+    const bool valid = i < n;
+    const int ii = valid ? i : n - 1;
+    const T di = diag[ii];
+    const T ax = apply_stencil<T>(ii, L.nbr, Cp, n, di, x[ii], [&](int j) { return x[j]; });
+    if (valid) {
+      const T ri = b[i] - ax;
+      r[i] = ri;
+      p_clear[i] = T(0);
+      const double rd = double(ri);
+      v[0] += rd * double(ri / di);
+      v[1] += rd * rd;
+      v[2] += double(b[i]) * double(b[i]);
+    }
+  }
+  const bool mx[3] = {false, false, false};
+  write_partials<3>(v, mx, part + gridDim.x, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_finish(int G, const double* part, PcgScalars* sc) {
+  __shared__ double lds[kLds];
+  double v[3];
+  const bool mx[3] = {false, false, false};
+  reduce_partials_all<3>(part + G, G, mx, v, lds);
+  if (threadIdx.x == 0) {
+    const double r0 = sqrt(v[1]), bn = sqrt(v[2]);
+    const double floor_b = sc->abs_floor * bn;
+    sc->rho[0] = v[0];
+    sc->rho[1] = v[0];
+    sc->rnorm0 = r0;
+    sc->rnorm = r0;
+    sc->bnorm = bn;
+    sc->thresh = fmax(sc->tol * r0, floor_b);
+    sc->iter = 0;
+    sc->linf = 0.0;
+    const bool fin = isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]);
+    sc->nonfinite = fin ? 0 : 1;
+    // ||r_0|| <= abs_floor ||b||: x_0 is returned after 0 iterations
+    sc->converged = (fin && r0 <= floor_b) ? 1 : 0;
+    sc->done = (!fin || r0 <= floor_b) ? 1 : 0;
+  }
+}
+
+// Operator sweep of iteration `it`: p_it = z + beta p_{it-1} with z = r / d formed
+// on the fly (p_1 = z), q = A p_it, partial (p, q).
+//
+// Two phases over the block's contiguous slot range: (1) p_it of every slot of
+// the range into LDS (and to p_new); (2) the operator, with in-oct neighbours by
+// cross-lane shuffle, out-of-oct neighbours inside the range from LDS, and the
+// rest recomputed from r, d and p_{it-1} in global memory (the two p buffers
+// alternate, so p_{it-1} is never overwritten during the sweep).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, int n_tiles, int it,
+                                                   const T* __restrict__ Cp, const T* __restrict__ diag,
+                                                   const T* __restrict__ r, const T* __restrict__ p_old,
+                                                   T* __restrict__ p_new, T* __restrict__ q,
+                                                   PcgScalars* sc, double* part) {
+  __shared__ double lds[kLds];
+  extern __shared__ unsigned char dyn_lds[];
+  T* pl = reinterpret_cast<T*>(dyn_lds);
+  if (sc->done) return;
+  const int G = gridDim.x;
+  const bool first = it == 1;
+  const int n = L.n_slots;
+  int t0, t1;
+  tile_range(n_tiles, t0, t1);
+  const int s0 = t0 * kBlock;
+  const int s1 = min(t1 * kBlock, n);
+  // phase 1 loads: U1 slots per thread and trip, the first batch issued before
+  // the head reduction (it does not depend on beta) and each next batch before
+  // the current one is used
+  constexpr int U1 = 4;
+  T rv[U1], dv[U1], pv[U1];
+  auto load1 = [&](int base) {
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int i = min(base + u * kBlock, s1 - 1);
+      rv[u] = r[i];
+      dv[u] = diag[i];
+      pv[u] = p_old[i];
+    }
+  };
+  int base = s0 + int(threadIdx.x);
+  load1(min(base, s1 - 1));
+  double beta = 0.0;
+  if (!first) {
+    const StopTest s = stop_test(sc, part, G, it - 1, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      record_stop(sc, s, it - 1);
+      if (!s.stop) sc->rho[it & 1] = s.rz;
+    }
+    if (s.stop) return;
+    beta = s.rz / sc->rho[(it - 1) & 1];
+  }
+  const T tb = T(beta);
+  for (; base < s1; base += U1 * kBlock) {
+    T pi[U1];
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const T z = rv[u] / dv[u];
+      pi[u] = first ? z : fma(tb, pv[u], z);
+    }
+    if (base + U1 * kBlock < s1) load1(base + U1 * kBlock);
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int i = base + u * kBlock;
+      if (i < s1) {
+        pl[i - s0] = pi[u];
+        p_new[i] = pi[u];
+      }
+    }
+  }
+  __syncthreads();
+  // phase 2: the operator, U2 tiles per trip
+  constexpr int U2 = 2;
+  double v[1] = {0.0};
+  for (int tb0 = t0; tb0 < t1; tb0 += U2) {
+    int ii[U2], nbv[U2][3];
+    T dg[U2], cown[U2][3];
+    bool valid[U2];
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const int i = (tb0 + u) * kBlock + int(threadIdx.x);
+      valid[u] = (tb0 + u < t1) && i < n;
+      ii[u] = valid[u] ? i : s1 - 1;
+      const int pos = ii[u] & 7, o = ii[u] >> 3;
+      dg[u] = diag[ii[u]];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cown[u][a] = Cp[size_t(a) * n + ii[u]];
+        nbv[u][a] = L.nbr[o * 6 + 2 * a + ((pos >> a) & 1)];
+      }
+    }
+    // gathers of the out-of-oct neighbours: coefficient of a -face, and the
+    // inputs of p at neighbours outside the block's range
+    int jv[U2][3];
+    T cj[U2][3], rj[U2][3], dj[U2][3], pj[U2][3];
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const int pos = ii[u] & 7;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int nb = nbv[u][a];
+        const int j = nb >= 0 ? ((nb << 3) | (pos ^ (1 << a))) : ii[u];
+        jv[u][a] = j;
+        const bool inr = j >= s0 && j < s1;
+        const int jo = inr ? ii[u] : j;  // no gather needed inside the range
+        cj[u][a] = Cp[size_t(a) * n + j];
+        rj[u][a] = r[jo];
+        dj[u][a] = diag[jo];
+        pj[u][a] = p_old[jo];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const int pos = ii[u] & 7;
+      const T pi = valid[u] ? pl[ii[u] - s0] : T(0);
+      T acc = dg[u] * pi;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int bit = 1 << a;
+        const T c_own = cown[u][a];
+        const T p_sib = __shfl_xor(pi, bit, 64);
+        const T c_sib = __shfl_xor(c_own, bit, 64);
+        const int my = (pos >> a) & 1;
+        acc -= (my ? c_sib : c_own) * p_sib;
+        if (nbv[u][a] >= 0) {
+          const int j = jv[u][a];
+          const T c_out = my ? c_own : cj[u][a];
+          T pn;
+          if (j >= s0 && j < s1) {
+            pn = pl[j - s0];
+          } else {
+            const T z = rj[u][a] / dj[u][a];
+            pn = first ? z : fma(tb, pj[u][a], z);
+          }
+          acc -= c_out * pn;
+        }
+      }
+      if (valid[u]) {
+        q[ii[u]] = acc;
+        v[0] += double(pi) * double(acc);
+      }
+    }
+  }
+  const bool mx[1] = {false};
+  write_partials<1>(v, mx, part, lds);
+}
+
+// Update sweep of iteration `it`: alpha = rho / (p, q); x += alpha p; r -= alpha q;
+// partials (r, z), ||r||^2 and max |alpha p| / |x|.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, int n_tiles, int it,
+                                                   const T* __restrict__ diag, const T* __restrict__ p,
+                                                   const T* __restrict__ q, T* __restrict__ x,
+                                                   T* __restrict__ r, PcgScalars* sc, double* part) {
+  __shared__ double lds[kLds];
+  if (sc->done) return;
+  const int G = gridDim.x;
+  const int n = L.n_slots;
+  int t0, t1;
+  tile_range(n_tiles, t0, t1);
+  const int s1 = min(t1 * kBlock, n);
+  // U slots per thread and trip; the first batch is loaded before the head
+  // reduction (it does not depend on alpha), each next one before the current is used
+  constexpr int U = 4;
+  T xv[U], pv[U], rv[U], qv[U], dv[U];
+  auto load = [&](int base) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(base + u * kBlock, s1 - 1);
+      xv[u] = x[i];
+      pv[u] = p[i];
+      rv[u] = r[i];
+      qv[u] = q[i];
+      dv[u] = diag[i];
+    }
+  };
+  int base = t0 * kBlock + int(threadIdx.x);
+  load(min(base, s1 - 1));
+  double pq[1];
+  const bool mx1[1] = {false};
+  reduce_partials_all<1>(part, G, mx1, pq, lds);
+  const double alpha = sc->rho[it & 1] / pq[0];
+  if (!isfinite(alpha)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->nonfinite = 1;
+      sc->iter = it - 1;
+      sc->done = 1;
+    }
+    return;
+  }
+  const T ta = T(alpha);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (; base < s1; base += U * kBlock) {
+    T xn[U], rn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T dx = ta * pv[u];
+      xn[u] = xv[u] + dx;
+      rn[u] = rv[u] - ta * qv[u];
+      if (base + u * kBlock < s1) {
+        v[2] = fmax(v[2], double(rel_change(xv[u], dx)));
+        const T z = rn[u] / dv[u];
+        v[0] += double(rn[u]) * double(z);
+        v[1] += double(rn[u]) * double(rn[u]);
+      }
+    }
+    if (base + U * kBlock < s1) load(base + U * kBlock);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * kBlock;
+      if (i < s1) {
+        x[i] = xn[u];
+        r[i] = rn[u];
+      }
+    }
+  }
+  const bool mx[3] = {false, false, true};
+  write_partials<3>(v, mx, part + G, lds);
+}
+
+// Applies the stopping test after the update sweep of iteration it_last (the
+// test the next operator sweep would make) so that the host sees convergence.
+__global__ __launch_bounds__(kBlock) void k_check(int G, int it_last, PcgScalars* sc, const double* part) {
+  __shared__ double lds[kLds];
+  if (sc->done) return;
+  const StopTest s = stop_test(sc, part, G, it_last, lds);
+  if (threadIdx.x == 0) record_stop(sc, s, it_last);
+}
+
+__global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, int n_tiles, const double* __restrict__ Cp,
+                                                          const double* __restrict__ diag,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ x, double* part) {
+  __shared__ double lds[kLds];
+  const int n = L.n_slots;
+  int t0, t1;
+  tile_range(n_tiles, t0, t1);
+  double v[1] = {0.0};
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + int(threadIdx.x);
+    const bool valid = i < n;
+    const int ii = valid ? i : n - 1;
+    const double ax = apply_stencil<double>(ii, L.nbr, Cp, n, diag[ii], x[ii], [&](int j) { return x[j]; });
+    if (valid) {
+      const double ri = b[i] - ax;
+      v[0] += ri * ri;
+    }
+  }
+  const bool mx[1] = {false};
+  write_partials<1>(v, mx, part, lds);
+}
+
+// T update of the coupling term (linearised emission) and smallest leaf energy.
+__global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, int n_tiles, const double* __restrict__ E,
+                                                       const double* __restrict__ rho, CouplingParams cp,
+                                                       double dt, double* __restrict__ T_out, double* part) {
+  __shared__ double lds[kLds];
+  int t0, t1;
+  tile_range(n_tiles, t0, t1);
+  double v[1] = {-DBL_MAX};
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + int(threadIdx.x);
+    if (i < L.n_slots && L.child[i] < 0) {
+      const double e = E[i];
+      v[0] = fmax(v[0], -e);
+      if (cp.T) {
+        const double T = cp.T[i], r = rho[i];
+        const double eta = cp.kappa_P * r * cp.c_light * dt;
+        const double bT = 4.0 * cp.a_rad * T * T * T;
+        const double den = r * cp.c_v + eta * bT;
+        T_out[i] = T + eta * (e - cp.a_rad * (T * T * T * T)) / den;
+      }
+    }
+  }
+  const bool mx[1] = {true};
+  write_partials<1>(v, mx, part, lds);
+}
+
+// kind 0: true residual norm; kind 1: smallest leaf energy.
+__global__ __launch_bounds__(kBlock) void k_finish(int G, int kind, const double* part, PcgScalars* sc) {
+  __shared__ double lds[kLds];
+  double v[1];
+  const bool mx[1] = {kind == 1};
+  reduce_partials_all<1>(part, G, mx, v, lds);
+  if (threadIdx.x == 0) {
+    if (kind == 0) sc->true_rnorm = sqrt(v[0]);
+    else sc->min_E = -v[0];
+  }
+}
+
+// ------------------------------------------------------------ mixed precision
+__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, int n_tiles, const double* __restrict__ Cp,
+                                                     const double* __restrict__ diag,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ x_old,
+                                                     const float* __restrict__ d, double* __restrict__ x_new,
+                                                     float* __restrict__ r32, double* part) {
+  __shared__ double lds[kLds];
+  const int n = L.n_slots;
+  auto xv = [&](int j) -> double { return d ? x_old[j] + double(d[j]) : x_old[j]; };
+  int t0, t1;
+  tile_range(n_tiles, t0, t1);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + int(threadIdx.x);
+    const bool valid = i < n;
+    const int ii = valid ? i : n - 1;
+    const double xi = xv(ii);
+    const double ax = apply_stencil<double>(ii, L.nbr, Cp, n, diag[ii], xi, xv);
+    if (valid) {
+      const double ri = b[i] - ax;
+      x_new[i] = xi;
+      r32[i] = float(ri);
+      v[0] += ri * ri;
+      v[1] += b[i] * b[i];
+      if (d) v[2] = fmax(v[2], rel_change(x_old[i], double(d[i])));
+    }
+  }
+  const bool mx[3] = {false, false, true};
+  write_partials<3>(v, mx, part + gridDim.x, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ir_finish(int G, int first, double inner_tol, int inner_max,
+                                                      PcgScalars* out, PcgScalars* in, const double* part) {
+  __shared__ double lds[kLds];
+  double v[3];
+  const bool mx[3] = {false, false, true};
+  reduce_partials_all<3>(part + G, G, mx, v, lds);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(v[0]), bn = sqrt(v[1]), linf = v[2];
+  const bool fin = isfinite(rn) && isfinite(bn);
+  bool conv;
+  if (first) {
+    const double floor_b = out->abs_floor * bn;
+    out->rnorm0 = rn;
+    out->bnorm = bn;
+    out->thresh = fmax(out->tol * rn, floor_b);
+    out->iter = 0;
+    out->linf = 0.0;
+    conv = fin && rn <= floor_b;
+  } else {
+    out->iter += 1;
+    out->linf = linf;
+    conv = fin && ((rn <= out->thresh && (!out->linf_test || linf < out->tol)) || rn == 0.0);
+  }
+  out->rnorm = rn;
+  out->nonfinite = fin ? 0 : 1;
+  out->converged = conv ? 1 : 0;
+  out->done = (!fin || conv) ? 1 : 0;
+  // the inner solve A d = r stops at a reduction inner_tol of its own residual
+  in->tol = inner_tol;
+  in->abs_floor = 0.0;
+  in->max_iter = inner_max;
+  in->linf_test = 0;
+  in->done = 0;
+  in->converged = 0;
+  in->nonfinite = 0;
+  in->iter = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, int n_tiles, const float* __restrict__ diag32,
+                                                       const float* __restrict__ r32, float* __restrict__ d,
+                                                       float* __restrict__ p_clear, double* part) {
+  __shared__ double lds[kLds];
+  int t0, t1;
+  tile_range(n_tiles, t0, t1);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + int(threadIdx.x);
+    if (i < L.n_slots) {
+      d[i] = 0.0f;
+      p_clear[i] = 0.0f;
+      const float ri = r32[i];
+      const double rd = double(ri);
+      v[0] += rd * double(ri / diag32[i]);
+      v[1] += rd * rd;
+      v[2] += rd * rd;
+    }
+  }
+  const bool mx[3] = {false, false, false};
+  write_partials<3>(v, mx, part + gridDim.x, lds);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+void launch_pcg_init(hipStream_t s, const DevLevel& L, int G, const T* Cp, const T* diag, const T* b,
+                     const T* x, T* r, T* p_clear, double* part) {
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), Cp, diag, b, x,
+                     r, p_clear, part);
+}
+
+void launch_init_finish(hipStream_t s, int G, const double* part, PcgScalars* sc) {
+  hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kBlock), 0, s, G, part, sc);
+}
+
+template <typename T>
+void launch_pass_a(hipStream_t s, const DevLevel& L, int G, int it, const T* Cp, const T* diag, const T* r,
+                   const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part) {
+  const int n_tiles = tiles_of(L.n_slots);
+  const size_t lds = size_t((n_tiles + G - 1) / G) * kBlock * sizeof(T);
+  hipLaunchKernelGGL(k_pass_a<T>, dim3(G), dim3(kBlock), lds, s, L, n_tiles, it, Cp, diag, r, p_old, p_new,
+                     q, sc, part);
+}
+
+template <typename T>
+void launch_pass_b(hipStream_t s, const DevLevel& L, int G, int it, const T* diag, const T* p, const T* q,
+                   T* x, T* r, PcgScalars* sc, double* part) {
+  hipLaunchKernelGGL(k_pass_b<T>, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), it, diag, p, q, x,
+                     r, sc, part);
+}
+
+void launch_check(hipStream_t s, int G, int it_last, PcgScalars* sc, const double* part) {
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, G, it_last, sc, part);
+}
+
+void launch_true_residual(hipStream_t s, const DevLevel& L, int G, const double* Cp, const double* diag,
+                          const double* b, const double* x, PcgScalars* sc, double* part) {
+  hipLaunchKernelGGL(k_true_residual, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), Cp, diag, b,
+                     x, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, G, 0, part, sc);
+}
+
+void launch_post_solve(hipStream_t s, const DevLevel& L, int G, const double* E, const double* rho,
+                       const CouplingParams& cp, double dt, double* T_out, PcgScalars* sc, double* part) {
+  hipLaunchKernelGGL(k_post_solve, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), E, rho, cp, dt,
+                     T_out, part);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, G, 1, part, sc);
+}
+
+void launch_ir_sweep(hipStream_t s, const DevLevel& L, int G, const double* Cp, const double* diag,
+                     const double* b, const double* x_old, const float* d, double* x_new, float* r32,
+                     double* part) {
+  hipLaunchKernelGGL(k_ir_sweep, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), Cp, diag, b, x_old,
+                     d, x_new, r32, part);
+}
+
+void launch_ir_finish(hipStream_t s, int G, int first, double inner_tol, int inner_max, PcgScalars* outer,
+                      PcgScalars* inner, const double* part) {
+  hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, G, first, inner_tol, inner_max, outer, inner,
+                     part);
+}
+
+void launch_inner_init(hipStream_t s, const DevLevel& L, int G, const float* diag32, const float* r32,
+                       float* d, float* p_clear, double* part) {
+  hipLaunchKernelGGL(k_inner_init, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), diag32, r32, d,
+                     p_clear, part);
+}
+
+template void launch_pcg_init<double>(hipStream_t, const DevLevel&, int, const double*, const double*,
+                                      const double*, const double*, double*, double*, double*);
+template void launch_pass_a<double>(hipStream_t, const DevLevel&, int, int, const double*, const double*,
+                                    const double*, const double*, double*, double*, PcgScalars*, double*);
+template void launch_pass_b<double>(hipStream_t, const DevLevel&, int, int, const double*, const double*,
+                                    const double*, double*, double*, PcgScalars*, double*);
+template void launch_pass_a<float>(hipStream_t, const DevLevel&, int, int, const float*, const float*,
+                                   const float*, const float*, float*, float*, PcgScalars*, double*);
+template void launch_pass_b<float>(hipStream_t, const DevLevel&, int, int, const float*, const float*,
+                                   const float*, float*, float*, PcgScalars*, double*);
+
+}  // namespace amrfld

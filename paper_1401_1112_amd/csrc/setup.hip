@@ -1,0 +1,215 @@
+// Setup kernels of a level solve (once per solve): cell diffusivity, face
+// coefficients with the interface rows, right-hand side; and the level-coupling
+// kernels: flux register and restriction.
+#include "common.h"
+
+namespace amrfld {
+
+int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+namespace {
+
+using dev::harmonic;
+using dev::same_level_nb;
+
+// ----------------------------------------------------------- setup kernels
+__global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __restrict__ E,
+                                                   const double* __restrict__ rho,
+                                                   const double* __restrict__ Ec, CellKParams kp,
+                                                   double* __restrict__ K) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.n_slots) return;
+  if (kp.kmode == 0) {
+    K[i] = kp.K_const;
+    return;
+  }
+  const double Ei = E[i];
+  double g2 = 0.0;
+#pragma unroll
+  for (int axis = 0; axis < 3; ++axis) {
+    double v[2], h[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int dir = 2 * axis + side;
+      const int j = same_level_nb(L.nbr, i, dir);
+      if (j >= 0) {
+        v[side] = E[j];
+        h[side] = L.dx;
+      } else {
+        const int c = L.cnb[(i >> 3) * 6 + dir];
+        if (c >= 0) {
+          v[side] = Ec[c];
+          h[side] = 1.5 * L.dx;
+        } else {
+          v[side] = Ei;
+          h[side] = L.dx;
+        }
+      }
+    }
+    const double g = (v[1] - v[0]) / (h[0] + h[1]);
+    g2 += g * g;
+  }
+  const double rk = rho[i] * kp.kappa_R;
+  const double R = sqrt(g2) / (rk * Ei);
+  const double lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+  K[i] = kp.c_light * lam / rk;
+}
+
+__global__ __launch_bounds__(kBlock) void k_assemble(
+    DevLevel L, const double* __restrict__ K, const double* __restrict__ Kc,
+    const double* __restrict__ E, const double* __restrict__ Ec, const double* __restrict__ rho,
+    const double* __restrict__ reg, double coef, double w, CouplingParams cp, double dt,
+    double* __restrict__ Cp, double* __restrict__ diag, double* __restrict__ b) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int n = L.n_slots;
+  if (i >= n) return;
+  if (L.child[i] >= 0) {  // refined slot: identity row, r stays 0
+    Cp[i] = 0.0;
+    Cp[size_t(n) + i] = 0.0;
+    Cp[2 * size_t(n) + i] = 0.0;
+    diag[i] = 1.0;
+    b[i] = E[i];
+    return;
+  }
+  const double Ki = K[i];
+  double d = 1.0, bb = E[i];
+  double cplus[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int dir = 0; dir < 6; ++dir) {
+    const int j = same_level_nb(L.nbr, i, dir);
+    if (j >= 0) {
+      const double C = harmonic(Ki, K[j]) * coef;
+      if (L.child[j] >= 0) {  // coarse-to-fine face: D / N / R (Sect. 3.2)
+        const double Fin = reg ? -reg[size_t(dir) * n + i] / L.vol : 0.0;
+        d += w * C;
+        bb += w * C * E[j] + (1.0 - w) * Fin;
+      } else {
+        d += C;
+        if (dir & 1) cplus[dir >> 1] = C;
+      }
+    } else {
+      const int c = L.cnb[(i >> 3) * 6 + dir];
+      if (c >= 0) {  // fine-to-coarse face: Dirichlet, centre distance 3 dx / 2
+        const double C = (2.0 / 3.0) * harmonic(Ki, Kc[c]) * coef;
+        d += C;
+        bb += C * Ec[c];
+      }
+    }
+  }
+  if (cp.T) {  // linearised coupling term kappa_P rho c (a T^4 - E)
+    const double T = cp.T[i], r = rho[i];
+    const double eta = cp.kappa_P * r * cp.c_light * dt;
+    const double bT = 4.0 * cp.a_rad * T * T * T;
+    const double den = r * cp.c_v + eta * bT;
+    const double f = eta * bT / den;
+    d += eta * (1.0 - f);
+    bb += eta * (1.0 - f) * cp.a_rad * (T * T * T * T);
+  }
+  Cp[i] = cplus[0];
+  Cp[size_t(n) + i] = cplus[1];
+  Cp[2 * size_t(n) + i] = cplus[2];
+  diag[i] = d;
+  b[i] = bb;
+}
+
+// One thread per (fine oct, direction): the four cells of that oct face that
+// see a coarser leaf add their energy gain V C (E_c - E_i) (eq. mean_flux with
+// dt inside C) to the register of that coarse cell, on its face looking back.
+__global__ __launch_bounds__(kBlock) void k_flux_register(DevLevel F, const double* __restrict__ Kf,
+                                                          const double* __restrict__ Kc,
+                                                          const double* __restrict__ Ef,
+                                                          const double* __restrict__ Ec,
+                                                          double coef, double* __restrict__ reg_c,
+                                                          int n_slots_c) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= F.n_oct * 6) return;
+  const int o = t / 6, dir = t % 6;
+  if (F.nbr[o * 6 + dir] >= 0) return;
+  const int c = F.cnb[o * 6 + dir];
+  if (c < 0) return;
+  const int axis = dir >> 1, side = dir & 1;
+  double sum = 0.0;
+  for (int pos = 0; pos < 8; ++pos) {
+    if (((pos >> axis) & 1) != side) continue;
+    const int i = (o << 3) | pos;
+    if (F.child[i] >= 0) continue;
+    const double C = (2.0 / 3.0) * harmonic(Kf[i], Kc[c]) * coef;
+    sum += F.vol * C * (Ec[c] - Ef[i]);
+  }
+  const size_t k = size_t(dir ^ 1) * n_slots_c + c;
+  reg_c[k] += sum;
+}
+
+__global__ __launch_bounds__(kBlock) void k_restrict(DevLevel F, const double* __restrict__ Ef,
+                                                     double* __restrict__ Ec) {
+  const int o = blockIdx.x * kBlock + threadIdx.x;
+  if (o >= F.n_oct) return;
+  const double* e = Ef + size_t(o) * 8;
+  const double s = ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
+  Ec[F.parent[o]] = s * 0.125;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* p, int64_t n, T v) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// FP32 copies of the operator for the inner solve of the mixed-precision form.
+__global__ __launch_bounds__(kBlock) void k_to_f32(int64_t n, const double* __restrict__ Cp,
+                                                   const double* __restrict__ diag,
+                                                   float* __restrict__ Cp32,
+                                                   float* __restrict__ diag32) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  Cp32[i] = float(Cp[i]);
+  Cp32[n + i] = float(Cp[n + i]);
+  Cp32[2 * n + i] = float(Cp[2 * n + i]);
+  diag32[i] = float(diag[i]);
+}
+
+}  // namespace
+
+void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const double* rho,
+                   const double* E_coarse, const CellKParams& kp, double* K) {
+  hipLaunchKernelGGL(k_cell_K, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, E, rho, E_coarse,
+                     kp, K);
+}
+
+void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const double* K_coarse,
+                     const double* E, const double* E_coarse, const double* rho, const double* reg,
+                     double dt, double w, const CouplingParams& cp, double* Cp, double* diag,
+                     double* b) {
+  const double coef = dt / (L.dx * L.dx);
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, K, K_coarse, E,
+                     E_coarse, rho, reg, coef, w, cp, dt, Cp, diag, b);
+}
+
+void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, const double* K_c,
+                          const double* E_f, const double* E_c, double dt, double* reg_c,
+                          int n_slots_c) {
+  const double coef = dt / (F.dx * F.dx);
+  hipLaunchKernelGGL(k_flux_register, dim3(grid_for(int64_t(F.n_oct) * 6)), dim3(kBlock), 0, s, F,
+                     K_f, K_c, E_f, E_c, coef, reg_c, n_slots_c);
+}
+
+void launch_restrict(hipStream_t s, const DevLevel& F, const double* E_f, double* E_c) {
+  hipLaunchKernelGGL(k_restrict, dim3(grid_for(F.n_oct)), dim3(kBlock), 0, s, F, E_f, E_c);
+}
+
+void launch_fill(hipStream_t s, double* p, int64_t n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
+}
+
+void launch_fill_f32(hipStream_t s, float* p, int64_t n, float v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
+}
+
+void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* diag, float* Cp32,
+                   float* diag32) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, Cp, diag, Cp32, diag32);
+}
+
+}  // namespace amrfld

@@ -1,0 +1,90 @@
+"""Helpers for counter runs under rocprofv3.
+
+``python -m paper_1401_1112_amd.profiling copy --mib 1024 --reps 4`` runs a plain
+device-to-device copy of a known size, whose FETCH_SIZE / WRITE_SIZE readings
+calibrate the per-dispatch HBM byte counters of the solver kernels.
+
+``python -m paper_1401_1112_amd.profiling summarize DIR`` prints a per-kernel
+summary (count, average duration, and the averages of any counters) from the
+CSV files rocprofv3 writes with ``--output-format csv``.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import os
+import sys
+from collections import defaultdict
+
+
+def run_copy(mib: int, reps: int) -> None:
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {mib} MiB x {reps}", flush=True)
+
+
+def _short(name: str) -> str:
+    for pre in ("amrfld::(anonymous namespace)::", "void "):
+        name = name.replace(pre, "")
+    return name.split("(")[0][:60]
+
+
+def summarize(d: str) -> str:
+    lines = []
+    kt = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    if kt:
+        agg = defaultdict(lambda: [0, 0.0])
+        for path in kt:
+            with open(path) as f:
+                for row in csv.DictReader(f):
+                    k = _short(row.get("Kernel_Name", ""))
+                    dur = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3
+                    agg[k][0] += 1
+                    agg[k][1] += dur
+        lines.append("kernel trace (durations in us):")
+        lines.append(f"{'kernel':60s} {'calls':>7s} {'total_us':>12s} {'avg_us':>10s}")
+        for k, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+            lines.append(f"{k:60s} {c:7d} {t:12.1f} {t / c:10.2f}")
+    cc = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if cc:
+        vals = defaultdict(lambda: defaultdict(list))
+        for path in cc:
+            with open(path) as f:
+                for row in csv.DictReader(f):
+                    k = _short(row.get("Kernel_Name", ""))
+                    vals[k][row["Counter_Name"]].append((int(row.get("Dispatch_Id", 0)), float(row["Counter_Value"])))
+        lines.append("counters (per dispatch: sum over the dispatch's records, then averaged over dispatches):")
+        for k in sorted(vals):
+            for cn, recs in sorted(vals[k].items()):
+                per = defaultdict(float)
+                for disp, v in recs:
+                    per[disp] += v
+                avg = sum(per.values()) / max(len(per), 1)
+                lines.append(f"{k:60s} {cn:20s} dispatches {len(per):6d} avg {avg:14.1f}")
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=1024)
+    c.add_argument("--reps", type=int, default=4)
+    s = sub.add_parser("summarize")
+    s.add_argument("dir")
+    a = ap.parse_args(argv)
+    if a.cmd == "copy":
+        run_copy(a.mib, a.reps)
+    else:
+        print(summarize(a.dir))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

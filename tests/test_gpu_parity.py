@@ -99,6 +99,22 @@ def _run_pair(p, mode, steps, tol, max_iter):
     return counts, diffs
 
 
+def _parity_protocol(p, mode, steps, tol=1e-12):
+    """Gate: same iteration counts and <= 1e-12 relative L2 per level and step.  Where a
+    count differs (a near-tie at the stopping threshold) both sides are re-run with the
+    largest count fixed and tol = 0, and that comparison is gated at 1e-12."""
+    counts, diffs = _run_pair(p, mode, steps, p.tol, p.max_iter)
+    assert counts, "no step started from an SPD state"
+    if all(g == o for g, o in counts):
+        assert max(diffs) <= tol, diffs
+        return "same-count"
+    n_fix = max(it for g, o in counts for _, it in g + o)
+    counts2, diffs2 = _run_pair(p, mode, steps, 0.0, n_fix)
+    assert all(g == o for g, o in counts2)
+    assert max(diffs2) <= tol, diffs2
+    return "fixed-count"
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 @pytest.mark.parametrize("mode", ["dirichlet", "neumann", "robin"])
 @pytest.mark.parametrize("kmode", ["lp", "const"])
@@ -245,4 +261,50 @@ def test_coupled_temperature_parity():
         _, t = s.E(lvl, with_T=True)
         tt = align(lvl, o.cells(lvl), o.T[lvl], s.cells(lvl))
         assert _rel(S.to_numpy(t), tt) < 1e-12
+    s.close()
+
+
+# ------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("mode", ["dirichlet", "robin"])
+def test_mixed_precision_refinement_reaches_fp64_tolerance(seed, mode):
+    # FP32 inner PCG + FP64 refinement: every solve must reach a true FP64 relative
+    # residual <= tol; lambda_min(A) >= 1 then bounds the error by the residual.
+    torch, S = _gpu()
+    from paper_1401_1112_amd import MIXED
+    p = config_tiny(seed, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-10)
+    s = S.solver_from_problem(p, precision=MIXED)
+    o = oracle_from_problem(p)
+    s.advance(p.dt_coarse, MODES[mode], p.tol)
+    o.advance_subcycled(p.dt_coarse, MODES[mode], 1e-13)
+    for st in s.stats():
+        assert st["converged"] == 1
+        assert st["true_rel_res"] <= p.tol * (1 + 1e-6), st
+        assert st["outer_iters"] >= 1
+    worst = _compare_levels(s, o, p.hierarchy.levels, tol=1e-8)
+    print(f"mixed seed {seed} {mode}: max relative L2 vs FP64 oracle {worst:.2e}")
+    s.close()
+
+
+def test_mixed_precision_uniform_closed_form():
+    torch, S = _gpu()
+    from paper_1401_1112_amd import MIXED
+    level = 5
+    p = config_uniform(level, kmode="const", seed=level)
+    dx = 1.0 / (1 << level)
+    dt = 16.0 * dx * dx
+    s = S.solver_from_problem(p, precision=MIXED, abs_floor=0.0)
+    c = s.cells(level)
+    n = 1 << level
+    b = np.zeros((n, n, n))
+    b[c[:, 0], c[:, 1], c[:, 2]] = p.E(level, c)
+    s.solve_level(level, dt, 0, 1e-12)
+    x = S.to_numpy(s.E(level))
+    lam1 = 2.0 - 2.0 * np.cos(np.pi * np.arange(n) / n)
+    lam = lam1[:, None, None] + lam1[None, :, None] + lam1[None, None, :]
+    ref = scipy.fft.idctn(scipy.fft.dctn(b, type=2, norm="ortho") / (1 + dt / dx ** 2 * lam),
+                          type=2, norm="ortho")[c[:, 0], c[:, 1], c[:, 2]]
+    st = s.stats()[0]
+    assert st["true_rel_res"] <= 1e-12 * (1 + 1e-6)
+    assert _rel(x, ref) < 1e-11
     s.close()
