@@ -147,6 +147,38 @@ amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mod
  * solve_level(l, dt) }.  Returns the first non-OK status of its solves. */
 amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_mode, double tol);
 
+/* One independent patch of the batch form: a box of n^3 cells of size dx whose
+ * interior faces are same-level faces (eq. Er_imp1) and whose six boundary
+ * faces carry the interface rows of Sect. 3.2 with a given outside energy and
+ * inflow: Dirichlet diag += C, b += C ghost; Neumann b += flux; Robin
+ * diag += alpha C, b += alpha C ghost + (1 - alpha) flux, with C = K_i dt / dx^2
+ * (the ghost cell has the boundary cell's diffusivity) and alpha = robin_alpha.
+ * rho and E are DEVICE float64 arrays of n^3 values, x fastest (index
+ * i + n (j + n k)); they are read during the call only. */
+typedef struct {
+  int n;                 /* cells per axis: even, 2 <= n <= 1024 */
+  double dx;             /* cell size */
+  double dt;             /* backward-Euler step */
+  const double* rho;
+  const double* E;       /* energy at the start of the first step */
+  int kmode;             /* amrfld_kmode */
+  double K_const, kappa_R, c_light;
+  int face_mode[6];      /* -x, +x, -y, +y, -z, +z: amrfld_bc */
+  double face_ghost[6];  /* outside energy of Dirichlet / Robin faces */
+  double face_flux[6];   /* inflow into each boundary cell per step, E units */
+} amrfld_patch;
+
+/* Advance n_prob independent patches by n_steps backward-Euler steps each, all
+ * patches in the same sweeps: every PCG sweep covers the tiles of all patches,
+ * with per-patch reductions, scalars and convergence (a converged patch's
+ * blocks return at once).  precision: AMRFLD_FP64 or AMRFLD_MIXED; tol as in
+ * amrfld_solve_level.  E_out: DEVICE float64 array receiving the final energies
+ * of all patches concatenated in patch order (sum of n^3 values, x fastest).
+ * Stats: one entry per (step, patch), the patch index in the `level` field.
+ * The batch layout is kept in the context and reused while the sizes repeat. */
+amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* patches, int n_steps,
+                                 double tol, int precision, double* E_out);
+
 /* Copy a level's E (and T when T_out is not NULL) to DEVICE arrays of n_slots
  * float64 in slot order (stream-ordered). */
 amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double* T_out);

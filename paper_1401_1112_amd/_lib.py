@@ -49,6 +49,16 @@ class amrfld_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class amrfld_patch(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+        ("rho", ctypes.c_void_p), ("E", ctypes.c_void_p), ("kmode", ctypes.c_int),
+        ("K_const", ctypes.c_double), ("kappa_R", ctypes.c_double), ("c_light", ctypes.c_double),
+        ("face_mode", ctypes.c_int * 6), ("face_ghost", ctypes.c_double * 6),
+        ("face_flux", ctypes.c_double * 6),
+    ]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point of include/amrfld.h
@@ -64,6 +74,7 @@ SIGNATURES = [
     ("amrfld_set_coeffs", _I, [_P, _I, _P, _P, _P, _D, _D, _D, _I, _D]),
     ("amrfld_solve_level", _I, [_P, _I, _D, _I, _D]),
     ("amrfld_advance_subcycled", _I, [_P, _D, _I, _D]),
+    ("amrfld_solve_batch", _I, [_P, _I, ctypes.POINTER(amrfld_patch), _I, _D, _I, _P]),
     ("amrfld_get_E", _I, [_P, _I, _P, _P]),
     ("amrfld_last_stats", _I, [_P, ctypes.POINTER(amrfld_stats), _I, ctypes.POINTER(_I)]),
     ("amrfld_last_error", ctypes.c_char_p, [_P]),
@@ -157,15 +168,24 @@ def amrfld_advance_subcycled(ctx, dt, bc_mode, tol):
     return load().amrfld_advance_subcycled(ctx, float(dt), int(bc_mode), float(tol))
 
 
+def amrfld_solve_batch(ctx, patches, n_steps, tol, precision, E_out):
+    """patches: list of amrfld_patch (device pointers already filled in)."""
+    arr = (amrfld_patch * len(patches))(*patches)
+    return load().amrfld_solve_batch(ctx, len(patches), arr, int(n_steps), float(tol), int(precision),
+                                     _ptr(E_out))
+
+
 def amrfld_get_E(ctx, level, E_out, T_out=None):
     return load().amrfld_get_E(ctx, int(level), _ptr(E_out), _ptr(T_out))
 
 
-def amrfld_last_stats(ctx, max_n=4096):
-    arr = (amrfld_stats * max_n)()
+def amrfld_last_stats(ctx, max_n=None):
     n = ctypes.c_int()
-    load().amrfld_last_stats(ctx, arr, max_n, ctypes.byref(n))
-    return [arr[k].as_dict() for k in range(min(n.value, max_n))]
+    load().amrfld_last_stats(ctx, None, 0, ctypes.byref(n))
+    count = n.value if max_n is None else min(n.value, max_n)
+    arr = (amrfld_stats * max(count, 1))()
+    load().amrfld_last_stats(ctx, arr, count, ctypes.byref(n))
+    return [arr[k].as_dict() for k in range(count)]
 
 
 def amrfld_last_error(ctx):

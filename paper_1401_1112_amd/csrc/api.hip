@@ -63,6 +63,8 @@ struct LevelState {
     d.parent = parent;
     d.dx = 1.0 / double(int64_t(1) << t.level);
     d.vol = d.dx * d.dx * d.dx;
+    d.oct_prob = nullptr;
+    d.pp = nullptr;
     return d;
   }
   void release() {
@@ -78,6 +80,58 @@ std::string g_create_error;
 
 }  // namespace
 
+// Concatenated slot layout of a batch of patches (cached while the sizes repeat).
+struct BatchState {
+  std::vector<int> sizes;
+  int n_prob = 0;
+  int64_t n_slots = 0, n_oct = 0;
+  int G = 0, tpb_max = 1;
+  std::vector<int64_t> out_off;  // host copy: first output value of each patch
+  int32_t *nbr = nullptr, *cnb = nullptr, *child = nullptr, *oct_prob = nullptr, *idx = nullptr;
+  int32_t *blk_prob = nullptr, *blk0 = nullptr, *tile0 = nullptr;
+  int64_t* d_out_off = nullptr;
+  double *E = nullptr, *rho = nullptr, *K = nullptr, *Cp = nullptr, *diag = nullptr, *b = nullptr;
+  PatchParams* pp = nullptr;
+  const double** src = nullptr;  // device array of n_prob pointers
+
+  void release() {
+    for (void* p : {(void*)nbr, (void*)cnb, (void*)child, (void*)oct_prob, (void*)idx, (void*)blk_prob,
+                    (void*)blk0, (void*)tile0, (void*)d_out_off, (void*)E, (void*)rho, (void*)K, (void*)Cp,
+                    (void*)diag, (void*)b, (void*)pp, (void*)src})
+      if (p) (void)hipFree(p);
+    nbr = cnb = child = oct_prob = idx = blk_prob = blk0 = tile0 = nullptr;
+    d_out_off = nullptr;
+    E = rho = K = Cp = diag = b = nullptr;
+    pp = nullptr;
+    src = nullptr;
+  }
+  DevLevel dev() const {
+    DevLevel d;
+    d.n_slots = int(n_slots);
+    d.n_oct = int(n_oct);
+    d.nbr = nbr;
+    d.cnb = cnb;
+    d.child = child;
+    d.parent = nullptr;
+    d.dx = 1.0;
+    d.vol = 1.0;
+    d.oct_prob = oct_prob;
+    d.pp = pp;
+    return d;
+  }
+  SweepPlan plan() const {
+    SweepPlan p;
+    p.n_prob = n_prob;
+    p.G = G;
+    p.n_tiles = tiles_of(n_slots);
+    p.tpb_max = tpb_max;
+    p.blk_prob = blk_prob;
+    p.blk0 = blk0;
+    p.tile0 = tile0;
+    return p;
+  }
+};
+
 struct amrfld_ctx {
   amrfld_opts o{};
   std::string err;
@@ -91,8 +145,10 @@ struct amrfld_ctx {
   float *Cp32 = nullptr, *diag32 = nullptr, *r32 = nullptr, *d32 = nullptr, *p32[2] = {nullptr, nullptr},
         *q32 = nullptr;
   double* x_alt = nullptr;
-  PcgScalars* sc = nullptr;     // [2]: outer / plain solve, inner solve
-  PcgScalars* h_sc = nullptr;   // pinned [2]
+  PcgScalars* sc = nullptr;     // [2 sc_cap]: outer (or plain) solves, then inner solves
+  PcgScalars* h_sc = nullptr;   // pinned mirror
+  int sc_cap = 0;
+  struct BatchState* batch = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> sweep_ev;  // 4 per iteration when sweeps are timed
   std::vector<amrfld_stats> stats;
@@ -228,31 +284,56 @@ amrfld_status check_level_ready(amrfld_ctx* c, int level) {
 }
 
 struct LoopStats {
-  int inner_iters = 0;
+  std::vector<int> iters;  // per problem: PCG iterations (inner iterations in mixed precision)
   int n_timed = 0;
   double a_ms = 0.0, b_ms = 0.0;
 };
 
-void read_scalars(amrfld_ctx* c, int count) {
+void ensure_scalars(amrfld_ctx* c, int n_prob) {
+  if (n_prob <= c->sc_cap) return;
+  dfree(c->sc);
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
+  c->sc = nullptr;
+  c->h_sc = nullptr;
+  c->sc_cap = 0;
+  c->sc = dalloc<PcgScalars>(2 * int64_t(n_prob), "scalars");
+  check(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), 2 * size_t(n_prob) * sizeof(PcgScalars), 0),
+        "pinned scalars");
+  c->sc_cap = n_prob;
+}
+
+void read_scalars(amrfld_ctx* c, PcgScalars* host, const PcgScalars* dev, int count) {
   const hipStream_t s = c->stream();
-  check(hipMemcpyAsync(c->h_sc, c->sc, count * sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
+  check(hipMemcpyAsync(host, dev, count * sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
   check(hipStreamSynchronize(s), "sync");
 }
 
-// Iterations of one PCG solve whose start sweeps already ran: batches of
-// (operator sweep, update sweep) pairs, a stopping check after each batch, the
-// next batch size predicted from the observed convergence rate.
+void write_scalars(amrfld_ctx* c, PcgScalars* dev, const PcgScalars* host, int count) {
+  check(hipMemcpyAsync(dev, host, count * sizeof(PcgScalars), hipMemcpyHostToDevice, c->stream()), "scalars");
+}
+
+bool all_done(const PcgScalars* h, int n) {
+  for (int q = 0; q < n; ++q)
+    if (!h[q].done) return false;
+  return true;
+}
+
+// Iterations of the PCG solves of all problems of a plan, whose start sweeps
+// already ran: batches of (operator sweep, update sweep) pairs, a stopping check
+// after each batch, the next batch size predicted from the slowest problem's
+// observed convergence rate.  Launches after a problem converged return at once.
 template <typename T>
-void pcg_iterations(amrfld_ctx* c, const DevLevel& D, int G, const T* Cp, const T* diag, T* x, T* r, T* const* p,
-                    T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int sc_index, int max_iter, LoopStats* ls) {
+void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const T* Cp, const T* diag, T* x, T* r,
+                    T* const* p, T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls) {
   const hipStream_t s = c->stream();
+  const int np = P.n_prob;
   int launched = 0;
   int chunk = c->o.check_every > 0 ? c->o.check_every : 8;
   const bool autochunk = c->o.check_every <= 0;
-  read_scalars(c, 2);
-  while (!sc_host->done && launched < max_iter) {
+  const int period = c->o.time_sweeps;
+  read_scalars(c, sc_host, sc_dev, np);
+  while (!all_done(sc_host, np) && launched < max_iter) {
     const int k = std::min(chunk, max_iter - launched);
-    const int period = c->o.time_sweeps;
     if (period > 0) {
       while (int(c->sweep_ev.size()) < 3 * ((launched + k) / period + 1)) {
         hipEvent_t e;
@@ -266,97 +347,121 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, int G, const T* Cp, const 
       const T* po = p[(it & 1) ^ 1];
       hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[3 * (it / period - 1)] : nullptr;
       if (e) check(hipEventRecord(e[0], s), "event");
-      launch_pass_a<T>(s, D, G, it, Cp, diag, r, po, pn, q, sc_dev, c->partials);
+      launch_pass_a<T>(s, D, P, it, Cp, diag, r, po, pn, q, sc_dev, c->partials);
       if (e) check(hipEventRecord(e[1], s), "event");
-      launch_pass_b<T>(s, D, G, it, diag, pn, q, x, r, sc_dev, c->partials);
+      launch_pass_b<T>(s, D, P, it, diag, pn, q, x, r, sc_dev, c->partials);
       if (e) check(hipEventRecord(e[2], s), "event");
     }
     launched += k;
-    launch_check(s, G, launched, sc_dev, c->partials);
+    launch_check(s, P, launched, sc_dev, c->partials);
     check(hipGetLastError(), "launch");
-    read_scalars(c, 2);
-    if (autochunk && !sc_host->done) {
-      const PcgScalars& h = *sc_host;
-      const double ratio = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 1.0;
-      int est = 2 * chunk;
-      if (h.iter > 0 && ratio > 0 && ratio < 1 && h.rnorm > h.thresh) {
-        const double rate = std::log(ratio) / h.iter;  // log reduction per iteration (< 0)
-        const double need = std::log(h.thresh / h.rnorm) / rate;
-        est = int(std::ceil(need)) + 1;
+    read_scalars(c, sc_host, sc_dev, np);
+    if (autochunk && !all_done(sc_host, np)) {
+      int est = 2;
+      for (int qq = 0; qq < np; ++qq) {
+        const PcgScalars& h = sc_host[qq];
+        if (h.done) continue;
+        const double ratio = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 1.0;
+        int e = 2 * chunk;
+        if (h.iter > 0 && ratio > 0 && ratio < 1 && h.rnorm > h.thresh) {
+          const double rate = std::log(ratio) / h.iter;  // log reduction per iteration (< 0)
+          e = int(std::ceil(std::log(h.thresh / h.rnorm) / rate)) + 1;
+        }
+        est = std::max(est, e);
       }
       chunk = std::max(2, std::min(256, est));
     }
   }
-  (void)sc_index;
-  const int done_iters = sc_host->iter;
-  const int period = c->o.time_sweeps;
+  int max_done = 0;
+  for (int qq = 0; qq < np; ++qq) {
+    ls->iters[qq] += sc_host[qq].iter;
+    max_done = std::max(max_done, sc_host[qq].iter);
+  }
   if (period > 0) {
-    // timed iterations that did work (launches after convergence returned at once)
-    for (int it = period; it <= done_iters && 3 * (it / period) <= int(c->sweep_ev.size()); it += period) {
-      const int k = it / period - 1;
+    // timed iterations that did work for at least one problem
+    for (int it = period; it <= max_done && 3 * (it / period) <= int(c->sweep_ev.size()); it += period) {
+      const int kk = it / period - 1;
       float ta = 0.f, tb = 0.f;
-      check(hipEventElapsedTime(&ta, c->sweep_ev[3 * k], c->sweep_ev[3 * k + 1]), "event");
-      check(hipEventElapsedTime(&tb, c->sweep_ev[3 * k + 1], c->sweep_ev[3 * k + 2]), "event");
+      check(hipEventElapsedTime(&ta, c->sweep_ev[3 * kk], c->sweep_ev[3 * kk + 1]), "event");
+      check(hipEventElapsedTime(&tb, c->sweep_ev[3 * kk + 1], c->sweep_ev[3 * kk + 2]), "event");
       ls->a_ms += ta;
       ls->b_ms += tb;
       ls->n_timed += 1;
     }
   }
-  ls->inner_iters += done_iters;
 }
 
-void init_scalars(amrfld_ctx* c, PcgScalars* host, double tol, double abs_floor, int max_iter, int linf_test) {
+PcgScalars make_scalars(double tol, double abs_floor, int max_iter, int linf_test) {
   PcgScalars init{};
   init.tol = tol;
   init.abs_floor = abs_floor;
   init.max_iter = max_iter;
   init.linf_test = linf_test;
-  *host = init;
+  return init;
 }
 
-void pcg_fp64(amrfld_ctx* c, const DevLevel& D, LevelState& L, int G, double tol, LoopStats* ls) {
+// Operator arrays of one solve (a level or a whole batch), slot order.
+struct SolveArrays {
+  const double* Cp;
+  const double* diag;
+  const double* b;
+  double* x;  // x_0 on entry (the energy, updated in place)
+  int64_t n;
+};
+
+void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
+              LoopStats* ls) {
   const hipStream_t s = c->stream();
-  init_scalars(c, &c->h_sc[0], tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
-  check(hipMemcpyAsync(c->sc, c->h_sc, sizeof(PcgScalars), hipMemcpyHostToDevice, s), "scalars");
-  launch_pcg_init<double>(s, D, G, L.Cp, L.diag, L.b, L.E, c->r, c->p[0], c->partials);
-  launch_init_finish(s, G, c->partials, c->sc);
+  const int np = P.n_prob;
+  for (int q = 0; q < np; ++q) c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
+  write_scalars(c, c->sc, c->h_sc, np);
+  launch_pcg_init<double>(s, D, P, A.Cp, A.diag, A.b, A.x, c->r, c->p[0], c->partials);
+  launch_init_finish(s, P, c->partials, c->sc);
   check(hipEventRecord(c->ev[1], s), "event");
-  pcg_iterations<double>(c, D, G, L.Cp, L.diag, L.E, c->r, c->p, c->q, c->sc, &c->h_sc[0], 0,
-                         c->o.max_iter, ls);
+  pcg_iterations<double>(c, D, P, A.Cp, A.diag, A.x, c->r, c->p, c->q, c->sc, c->h_sc, c->o.max_iter, ls);
 }
 
 // FP32 inner PCG on A d = r inside an FP64 iterative-refinement loop: the FP64
 // sweep applies x += d and forms the true residual r = b - A x; the inner solve
 // uses FP32 coefficients, vectors and operator arithmetic with FP64 dot products.
-void pcg_mixed(amrfld_ctx* c, const DevLevel& D, LevelState& L, int G, double tol, LoopStats* ls) {
+// Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].
+void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
+               LoopStats* ls, std::vector<int>* outer_iters) {
   const hipStream_t s = c->stream();
-  const int64_t n = D.n_slots;
-  ensure_workspace32(c, n);
-  launch_to_f32(s, n, L.Cp, L.diag, c->Cp32, c->diag32);
-  init_scalars(c, &c->h_sc[0], tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
-  init_scalars(c, &c->h_sc[1], c->o.inner_tol, 0.0, c->o.max_iter, 0);
-  check(hipMemcpyAsync(c->sc, c->h_sc, 2 * sizeof(PcgScalars), hipMemcpyHostToDevice, s), "scalars");
+  const int np = P.n_prob;
+  ensure_workspace32(c, A.n);
+  launch_to_f32(s, A.n, A.Cp, A.diag, c->Cp32, c->diag32);
+  for (int q = 0; q < np; ++q) {
+    c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
+    c->h_sc[np + q] = make_scalars(c->o.inner_tol, 0.0, c->o.max_iter, 0);
+  }
+  write_scalars(c, c->sc, c->h_sc, 2 * np);
   check(hipEventRecord(c->ev[1], s), "event");
-  double* x_cur = L.E;
+  PcgScalars* out = c->sc;
+  PcgScalars* in = c->sc + np;
+  double* x_cur = A.x;
   double* x_nxt = c->x_alt;
   const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
   int budget = c->o.max_iter;
   for (int outer = 0; outer <= max_outer; ++outer) {
-    launch_ir_sweep(s, D, G, L.Cp, L.diag, L.b, x_cur, outer == 0 ? nullptr : c->d32, x_nxt, c->r32,
+    launch_ir_sweep(s, D, P, A.Cp, A.diag, A.b, x_cur, outer == 0 ? nullptr : c->d32, x_nxt, c->r32, out,
                     c->partials);
     std::swap(x_cur, x_nxt);
-    launch_ir_finish(s, G, outer == 0 ? 1 : 0, c->o.inner_tol, std::max(1, budget), &c->sc[0], &c->sc[1],
-                     c->partials);
-    read_scalars(c, 2);
-    if (c->h_sc[0].done || outer == max_outer || budget <= 0) break;
-    launch_inner_init(s, D, G, c->diag32, c->r32, c->d32, c->p32[0], c->partials);
-    launch_init_finish(s, G, c->partials, &c->sc[1]);
-    const int before = ls->inner_iters;
-    pcg_iterations<float>(c, D, G, c->Cp32, c->diag32, c->d32, c->r32, c->p32, c->q32, &c->sc[1], &c->h_sc[1],
-                          1, std::max(1, budget), ls);
-    budget -= ls->inner_iters - before;
+    launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, std::max(1, budget), out, in, c->partials);
+    read_scalars(c, c->h_sc, out, np);
+    if (all_done(c->h_sc, np) || outer == max_outer || budget <= 0) break;
+    launch_inner_init(s, D, P, c->diag32, c->r32, c->d32, c->p32[0], out, c->partials);
+    launch_init_finish(s, P, c->partials, in);
+    int before = 0;
+    for (int v : ls->iters) before = std::max(before, v);
+    pcg_iterations<float>(c, D, P, c->Cp32, c->diag32, c->d32, c->r32, c->p32, c->q32, in, c->h_sc + np,
+                          std::max(1, budget), ls);
+    int after = 0;
+    for (int v : ls->iters) after = std::max(after, v);
+    budget -= std::max(1, after - before);
   }
-  if (x_cur != L.E) check(hipMemcpyAsync(L.E, x_cur, n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy x");
+  for (int q = 0; q < np; ++q) (*outer_iters)[q] = c->h_sc[q].iter;
+  if (x_cur != A.x) check(hipMemcpyAsync(A.x, x_cur, A.n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy x");
 }
 
 // One backward-Euler step of one level (Sect. 3.3.4).
@@ -379,19 +484,24 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   const double w = mode == AMRFLD_BC_DIRICHLET ? 1.0 : mode == AMRFLD_BC_NEUMANN ? 0.0 : c->o.robin_alpha;
   const CouplingParams cp = cparams(c, L);
   launch_assemble(s, D, L.K, Lc ? Lc->K : nullptr, L.E, Lc ? Lc->E : nullptr, L.rho, L.reg, dt, w,
-                  cp, L.Cp, L.diag, L.b);
+                  c->o.robin_alpha, cp, L.Cp, L.diag, L.b);
 
-  const int G = sweep_blocks(tiles_of(D.n_slots), c->o.max_blocks > 0 ? c->o.max_blocks : 1024);
+  const int n_tiles = tiles_of(D.n_slots);
+  const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
+  ensure_scalars(c, 1);
   LoopStats ls;
+  ls.iters.assign(1, 0);
+  std::vector<int> outer_iters(1, 0);
+  const SolveArrays A{L.Cp, L.diag, L.b, L.E, D.n_slots};
   if (c->o.precision == AMRFLD_MIXED) {
-    pcg_mixed(c, D, L, G, tol, &ls);
+    pcg_mixed(c, D, P, A, tol, &ls, &outer_iters);
   } else {
-    pcg_fp64(c, D, L, G, tol, &ls);
+    pcg_fp64(c, D, P, A, tol, &ls);
   }
   check(hipEventRecord(c->ev[2], s), "event");
   if (c->o.true_residual && c->o.precision != AMRFLD_MIXED)
-    launch_true_residual(s, D, G, L.Cp, L.diag, L.b, L.E, c->sc, c->partials);
-  launch_post_solve(s, D, G, L.E, L.rho, cp, dt, L.T, c->sc, c->partials);
+    launch_true_residual(s, D, P, L.Cp, L.diag, L.b, L.E, c->sc, c->partials);
+  launch_post_solve(s, D, P, L.E, L.rho, cp, dt, L.T, c->sc, c->partials);
   if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN)) {
     double* reg = ensure_reg(c, *Lc);
     launch_flux_register(s, D, L.K, Lc->K, L.E, Lc->E, dt, reg, int(Lc->t.n_slots()));
@@ -410,8 +520,8 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   st.n_leaf = L.t.n_leaf;
   st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
   if (c->o.precision == AMRFLD_MIXED) {
-    st.iters = ls.inner_iters;
-    st.outer_iters = h.iter;
+    st.iters = ls.iters[0];
+    st.outer_iters = outer_iters[0];
     st.true_rel_res = st.rel_res;  // the outer residual is the FP64 true residual
   } else {
     st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
@@ -453,6 +563,214 @@ amrfld_status step(amrfld_ctx* c, int level, double dt, int mode, double tol) {
   }
   const amrfld_status s = solve_one(c, level, dt, mode, tol);
   return worst != AMRFLD_OK ? worst : s;
+}
+
+}  // namespace
+
+namespace {
+
+template <class T>
+void upload(amrfld_ctx* c, T** dst, const std::vector<T>& v, const char* what) {
+  *dst = dalloc<T>(int64_t(v.size()), what);
+  check(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream()), what);
+}
+
+// Morton-ordered octs of each patch, tile-aligned slot ranges (padding slots are
+// identity rows), neighbour tables within each patch, and the block plan: each
+// patch gets enough blocks for at most `tpb` tiles per block.
+void build_batch(amrfld_ctx* c, const std::vector<int>& sizes) {
+  BatchState* B = c->batch;
+  if (B && B->sizes == sizes) return;
+  if (B) {
+    B->release();
+  } else {
+    B = c->batch = new BatchState();
+  }
+  B->sizes = sizes;
+  B->n_prob = int(sizes.size());
+  std::vector<int64_t> oct0(B->n_prob + 1, 0), tile0(B->n_prob + 1, 0);
+  B->out_off.assign(B->n_prob + 1, 0);
+  for (int q = 0; q < B->n_prob; ++q) {
+    const int64_t m = sizes[q] / 2;
+    const int64_t slots = 8 * m * m * m;
+    const int64_t tiles = (slots + kBlock - 1) / kBlock;
+    tile0[q + 1] = tile0[q] + tiles;
+    oct0[q + 1] = tile0[q + 1] * (kBlock / 8);
+    B->out_off[q + 1] = B->out_off[q] + int64_t(sizes[q]) * sizes[q] * sizes[q];
+  }
+  B->n_oct = oct0[B->n_prob];
+  B->n_slots = 8 * B->n_oct;
+  if (B->n_slots > int64_t(0x7fffffff)) throw std::invalid_argument("batch too large for 32-bit slot indices");
+  std::vector<int32_t> nbr(6 * B->n_oct, -1), child(B->n_slots, -2), oct_prob(B->n_oct), idx(B->n_slots, -1);
+  const int kOff[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+  for (int q = 0; q < B->n_prob; ++q) {
+    const int n = sizes[q];
+    const int m = n / 2;
+    const int64_t mo = int64_t(m) * m * m;
+    std::vector<int64_t> order(mo);
+    std::vector<uint64_t> key(mo);
+    for (int64_t k = 0; k < mo; ++k) {
+      order[k] = k;
+      key[k] = morton3(uint32_t(k % m), uint32_t((k / m) % m), uint32_t(k / (int64_t(m) * m)));
+    }
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b2) { return key[a] < key[b2]; });
+    std::vector<int32_t> local_of(mo);  // position -> local oct index
+    for (int64_t o = 0; o < mo; ++o) local_of[order[o]] = int32_t(o);
+    for (int64_t o = 0; o < oct0[q + 1] - oct0[q]; ++o) oct_prob[oct0[q] + o] = q;
+    for (int64_t o = 0; o < mo; ++o) {
+      const int64_t lin = order[o];
+      const int I = int(lin % m), J = int((lin / m) % m), K = int(lin / (int64_t(m) * m));
+      const int64_t go = oct0[q] + o;
+      for (int d = 0; d < 6; ++d) {
+        const int a = I + kOff[d][0], b2 = J + kOff[d][1], cc = K + kOff[d][2];
+        if (a < 0 || b2 < 0 || cc < 0 || a >= m || b2 >= m || cc >= m) continue;
+        nbr[6 * go + d] = int32_t(oct0[q] + local_of[a + int64_t(m) * (b2 + int64_t(m) * cc)]);
+      }
+      for (int pos = 0; pos < 8; ++pos) {
+        const int64_t slot = 8 * go + pos;
+        const int x = 2 * I + (pos & 1), y = 2 * J + ((pos >> 1) & 1), z = 2 * K + ((pos >> 2) & 1);
+        child[slot] = -1;
+        idx[slot] = int32_t(x + int64_t(n) * (y + int64_t(n) * z));
+      }
+    }
+  }
+  // blocks: at most tpb tiles per block, about >= 1024 blocks in total
+  const int64_t total_tiles = tile0[B->n_prob];
+  const int max_blocks = c->o.max_blocks > 0 ? c->o.max_blocks : 1024;
+  const int tpb = int(std::max<int64_t>(1, std::min<int64_t>(kMaxTilesPerBlock, total_tiles / max_blocks)));
+  std::vector<int32_t> blk0(B->n_prob + 1, 0), t0v(B->n_prob + 1, 0), blk_prob;
+  int tpb_max = 1;
+  for (int q = 0; q < B->n_prob; ++q) {
+    const int64_t tiles = tile0[q + 1] - tile0[q];
+    const int64_t g = (tiles + tpb - 1) / tpb;
+    blk0[q + 1] = int32_t(blk0[q] + g);
+    t0v[q + 1] = int32_t(tile0[q + 1]);
+    tpb_max = std::max<int>(tpb_max, int((tiles + g - 1) / g));
+    for (int64_t k = 0; k < g; ++k) blk_prob.push_back(q);
+  }
+  B->G = blk0[B->n_prob];
+  B->tpb_max = tpb_max;
+  std::vector<int32_t> cnb(6 * B->n_oct, -1);
+  upload(c, &B->nbr, nbr, "batch tables");
+  upload(c, &B->cnb, cnb, "batch tables");
+  upload(c, &B->child, child, "batch tables");
+  upload(c, &B->oct_prob, oct_prob, "batch tables");
+  upload(c, &B->idx, idx, "batch tables");
+  upload(c, &B->blk_prob, blk_prob, "batch tables");
+  upload(c, &B->blk0, blk0, "batch tables");
+  upload(c, &B->tile0, t0v, "batch tables");
+  upload(c, &B->d_out_off, B->out_off, "batch tables");
+  B->E = dalloc<double>(B->n_slots, "batch fields");
+  B->rho = dalloc<double>(B->n_slots, "batch fields");
+  B->K = dalloc<double>(B->n_slots, "batch fields");
+  B->Cp = dalloc<double>(3 * B->n_slots, "batch fields");
+  B->diag = dalloc<double>(B->n_slots, "batch fields");
+  B->b = dalloc<double>(B->n_slots, "batch fields");
+  B->pp = dalloc<PatchParams>(B->n_prob, "batch params");
+  B->src = reinterpret_cast<const double**>(dalloc<const double*>(B->n_prob, "batch pointers"));
+  check(hipStreamSynchronize(c->stream()), "batch tables");
+}
+
+amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, int n_steps, double tol,
+                          int precision) {
+  const hipStream_t s = c->stream();
+  std::vector<int> sizes(pt.size());
+  for (size_t q = 0; q < pt.size(); ++q) sizes[q] = pt[q].n;
+  build_batch(c, sizes);
+  BatchState& B = *c->batch;
+  const int np = B.n_prob;
+  std::vector<PatchParams> pp(np);
+  for (int q = 0; q < np; ++q) {
+    PatchParams& P = pp[q];
+    P.dx = pt[q].dx;
+    P.vol = pt[q].dx * pt[q].dx * pt[q].dx;
+    P.coef = pt[q].dt / (pt[q].dx * pt[q].dx);
+    P.kappa_R = pt[q].kappa_R;
+    P.c_light = pt[q].c_light;
+    P.K_const = pt[q].K_const;
+    P.kmode = pt[q].kmode;
+    for (int d = 0; d < 6; ++d) {
+      P.mode[d] = pt[q].face_mode[d];
+      P.ghost[d] = pt[q].face_ghost[d];
+      P.flux[d] = pt[q].face_flux[d];
+    }
+  }
+  check(hipMemcpyAsync(B.pp, pp.data(), np * sizeof(PatchParams), hipMemcpyHostToDevice, s), "batch params");
+  const DevLevel D = B.dev();
+  std::vector<const double*> ptr(np);
+  for (int q = 0; q < np; ++q) ptr[q] = pt[q].rho;
+  check(hipMemcpyAsync(B.src, ptr.data(), np * sizeof(void*), hipMemcpyHostToDevice, s), "batch pointers");
+  launch_batch_gather(s, D, B.idx, B.src, 1.0, B.rho);
+  check(hipStreamSynchronize(s), "batch gather");  // the pointer array is reused next
+  for (int q = 0; q < np; ++q) ptr[q] = pt[q].E;
+  check(hipMemcpyAsync(B.src, ptr.data(), np * sizeof(void*), hipMemcpyHostToDevice, s), "batch pointers");
+  launch_batch_gather(s, D, B.idx, B.src, 0.0, B.E);
+  ensure_workspace(c, B.n_slots);
+  ensure_scalars(c, np);
+  const SweepPlan P = B.plan();
+  const int saved_precision = c->o.precision;
+  c->o.precision = precision;
+  amrfld_status worst = AMRFLD_OK;
+  std::string worst_msg;
+  for (int step = 0; step < n_steps; ++step) {
+    check(hipEventRecord(c->ev[0], s), "event");
+    const CellKParams kp{1, 1.0, 1.0, 1.0};
+    launch_cell_K(s, D, B.E, B.rho, nullptr, kp, B.K);
+    CouplingParams cp{};
+    cp.T = nullptr;
+    launch_assemble(s, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, B.Cp,
+                    B.diag, B.b);
+    LoopStats ls;
+    ls.iters.assign(np, 0);
+    std::vector<int> outer_iters(np, 0);
+    const SolveArrays A{B.Cp, B.diag, B.b, B.E, B.n_slots};
+    if (precision == AMRFLD_MIXED) {
+      pcg_mixed(c, D, P, A, tol, &ls, &outer_iters);
+    } else {
+      pcg_fp64(c, D, P, A, tol, &ls);
+    }
+    check(hipEventRecord(c->ev[2], s), "event");
+    if (c->o.true_residual && precision != AMRFLD_MIXED)
+      launch_true_residual(s, D, P, B.Cp, B.diag, B.b, B.E, c->sc, c->partials);
+    launch_post_solve(s, D, P, B.E, B.rho, cp, 0.0, nullptr, c->sc, c->partials);
+    check(hipEventRecord(c->ev[3], s), "event");
+    read_scalars(c, c->h_sc, c->sc, np);
+    check(hipGetLastError(), "kernels");
+    float ms = 0.f, pms = 0.f;
+    check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
+    check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
+    for (int q = 0; q < np; ++q) {
+      const PcgScalars& h = c->h_sc[q];
+      amrfld_stats st{};
+      st.level = q;
+      st.iters = ls.iters[q];
+      st.outer_iters = outer_iters[q];
+      st.converged = h.converged;
+      st.n_leaf = int64_t(sizes[q]) * sizes[q] * sizes[q];
+      st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
+      st.true_rel_res = precision == AMRFLD_MIXED ? st.rel_res
+                        : (c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0);
+      st.linf_change = h.linf;
+      st.min_E = h.min_E;
+      st.dt = pt[q].dt;
+      st.ms = ms;
+      st.pcg_ms = pms;
+      st.n_timed = ls.n_timed;
+      st.pass_a_ms = ls.a_ms;
+      st.pass_b_ms = ls.b_ms;
+      st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
+      if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
+        worst = amrfld_status(st.status);
+        worst_msg = "patch " + std::to_string(q) + " step " + std::to_string(step) +
+                    (st.status == AMRFLD_E_NONFINITE ? ": non-finite residual" : ": no convergence");
+      }
+      c->stats.push_back(st);
+    }
+    if (worst == AMRFLD_E_NONFINITE) break;
+  }
+  c->o.precision = saved_precision;
+  if (worst != AMRFLD_OK) return fail(c, worst, worst_msg);
+  return AMRFLD_OK;
 }
 
 }  // namespace
@@ -505,8 +823,7 @@ amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
     c = new amrfld_ctx();
     c->o = *o;
     c->lev.resize(o->max_level - o->base_level + 1);
-    c->sc = dalloc<PcgScalars>(2, "scalars");
-    check(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), 2 * sizeof(PcgScalars), 0), "pinned scalars");
+    ensure_scalars(c, 1);
     for (auto& e : c->ev) check(hipEventCreate(&e), "event");
   } catch (const std::exception& e) {
     g_create_error = e.what();
@@ -521,6 +838,10 @@ void amrfld_destroy(amrfld_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream());
   for (auto& L : c->lev) L.release();
+  if (c->batch) {
+    c->batch->release();
+    delete c->batch;
+  }
   for (void* p : {(void*)c->r, (void*)c->p[0], (void*)c->p[1], (void*)c->q, (void*)c->partials,
                   (void*)c->sc, (void*)c->Cp32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
                   (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
@@ -647,6 +968,38 @@ amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_m
   }
   c->stats.clear();
   return guarded(c, [&]() { return step(c, c->o.base_level, dt_coarse, bc_mode, tol); });
+}
+
+amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* patches, int n_steps,
+                                 double tol, int precision, double* E_out) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (n_prob < 1 || !patches || !E_out) return fail(c, AMRFLD_E_INVALID, "n_prob >= 1, patches and E_out are required");
+  if (n_steps < 1) return fail(c, AMRFLD_E_INVALID, "n_steps must be >= 1");
+  if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
+  if (precision != AMRFLD_FP64 && precision != AMRFLD_MIXED) return fail(c, AMRFLD_E_INVALID, "unknown precision");
+  std::vector<amrfld_patch> pt(patches, patches + n_prob);
+  for (int q = 0; q < n_prob; ++q) {
+    const amrfld_patch& p = pt[q];
+    const std::string at = "patch " + std::to_string(q) + ": ";
+    if (p.n < 2 || p.n > 1024 || (p.n & 1)) return fail(c, AMRFLD_E_INVALID, at + "n must be even, 2..1024");
+    if (!(p.dx > 0.0) || !(p.dt > 0.0)) return fail(c, AMRFLD_E_INVALID, at + "dx and dt must be positive");
+    if (!p.rho || !p.E) return fail(c, AMRFLD_E_INVALID, at + "rho and E are required");
+    if (p.kmode != AMRFLD_K_CONST && p.kmode != AMRFLD_K_LP) return fail(c, AMRFLD_E_INVALID, at + "unknown kmode");
+    if (p.kmode == AMRFLD_K_LP && !(p.kappa_R > 0.0 && p.c_light > 0.0))
+      return fail(c, AMRFLD_E_INVALID, at + "kappa_R and c_light must be positive");
+    for (int d = 0; d < 6; ++d)
+      if (p.face_mode[d] < 0 || p.face_mode[d] > 2) return fail(c, AMRFLD_E_INVALID, at + "unknown face mode");
+  }
+  c->stats.clear();
+  return guarded(c, [&]() -> amrfld_status {
+    const amrfld_status st = solve_batch(c, pt, n_steps, tol, precision);
+    if (st == AMRFLD_OK || st == AMRFLD_E_NOCONV) {
+      BatchState& B = *c->batch;
+      launch_batch_scatter(c->stream(), B.dev(), B.idx, B.d_out_off, B.E, E_out);
+      check(hipGetLastError(), "scatter");
+    }
+    return st;
+  });
 }
 
 amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double* T_out) {

@@ -91,15 +91,44 @@ __device__ __forceinline__ void reduce_partials_all(const double* __restrict__ p
   __syncthreads();
 }
 
-// Contiguous range of 256-slot tiles of this block.  Blocks are dealt to the
-// XCDs round-robin, so block b is mapped to chunk (b % 8) * (G / 8) + b / 8:
-// each XCD then sweeps one contiguous eighth of the Morton order and the
-// neighbour octs it gathers are mostly in its own L2.
-__device__ __forceinline__ void tile_range(int n_tiles, int& t0, int& t1) {
-  const int G = gridDim.x, b = blockIdx.x;
-  const int c = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
-  t0 = int((int64_t(n_tiles) * c) / G);
-  t1 = int((int64_t(n_tiles) * (c + 1)) / G);
+// This block's problem, its blocks [b0, b0 + Gp) and its contiguous range of
+// 256-slot tiles [t0, t1).  Blocks are dealt to the XCDs round-robin, so for a
+// single problem block b is mapped to chunk (b % 8) * (G / 8) + b / 8: each XCD
+// then sweeps one contiguous eighth of the Morton order and the neighbour octs
+// it gathers are mostly in its own L2.
+struct BlockPlan {
+  int prob, b0, Gp, t0, t1;
+};
+
+__device__ __forceinline__ BlockPlan block_plan(const SweepPlan& P) {
+  BlockPlan bp;
+  const int b = blockIdx.x;
+  int T0, nt;
+  if (P.blk0) {
+    bp.prob = P.blk_prob[b];
+    bp.b0 = P.blk0[bp.prob];
+    bp.Gp = P.blk0[bp.prob + 1] - bp.b0;
+    T0 = P.tile0[bp.prob];
+    nt = P.tile0[bp.prob + 1] - T0;
+  } else {
+    bp.prob = 0;
+    bp.b0 = 0;
+    bp.Gp = P.G;
+    T0 = 0;
+    nt = P.n_tiles;
+  }
+  const int lb = b - bp.b0;
+  const int c = (!P.blk0 && bp.Gp % 8 == 0) ? (lb % 8) * (bp.Gp / 8) + lb / 8 : lb;
+  bp.t0 = T0 + int((int64_t(nt) * c) / bp.Gp);
+  bp.t1 = T0 + int((int64_t(nt) * (c + 1)) / bp.Gp);
+  return bp;
+}
+
+// Problem handled by a one-block-per-problem finisher launch.
+__device__ __forceinline__ void finisher_plan(const SweepPlan& P, int& prob, int& b0, int& Gp) {
+  prob = blockIdx.x;
+  b0 = P.blk0 ? P.blk0[prob] : 0;
+  Gp = P.blk0 ? P.blk0[prob + 1] - b0 : P.G;
 }
 
 // The 7-point operator at slot ii applied to a vector whose value at ii is pi

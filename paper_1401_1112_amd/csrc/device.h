@@ -29,16 +29,55 @@ struct PcgScalars {
   int linf_test;
 };
 
-// One level's (or one batch's) device tables, slot order.
+// Parameters of one independent patch of a batch: a box of cells of size dx
+// whose boundary faces carry a Dirichlet, Neumann or Robin condition (the
+// interface rows of Sect. 3.2 with a given ghost value and inflow).
+struct PatchParams {
+  double dx, vol, coef;  // coef = dt / dx^2
+  double kappa_R, c_light, K_const;
+  double ghost[6], flux[6];
+  int mode[6];
+  int kmode;
+};
+
+// One level's (or one batch's) device tables, slot order.  child: >= 0 child
+// oct (refined slot), -1 leaf, -2 padding slot of a batch (identity row).
 struct DevLevel {
   int n_slots;
   int n_oct;
-  const int32_t* nbr;     // [n_oct*6]
-  const int32_t* cnb;     // [n_oct*6]
-  const int32_t* child;   // [n_slots]
-  const int32_t* parent;  // [n_oct]
+  const int32_t* nbr;       // [n_oct*6]
+  const int32_t* cnb;       // [n_oct*6]
+  const int32_t* child;     // [n_slots]
+  const int32_t* parent;    // [n_oct]
   double dx, vol;
+  const int32_t* oct_prob;  // batch: patch of each oct (nullptr for a level)
+  const PatchParams* pp;    // batch: per-patch parameters (nullptr for a level)
 };
+
+// How the blocks of a sweep are spread over independent problems (a level is
+// one problem).  Problem q owns blocks [blk0[q], blk0[q+1]) and tiles
+// [tile0[q], tile0[q+1]); blocks never straddle problems, so block partials
+// and scalars are per problem.
+struct SweepPlan {
+  int n_prob;
+  int G;                    // total blocks
+  int n_tiles;              // used when the arrays are null (one problem)
+  int tpb_max;              // largest tile count of one block (sizes the LDS of the operator sweep)
+  const int32_t* blk_prob;  // [G] or nullptr
+  const int32_t* blk0;      // [n_prob + 1] or nullptr
+  const int32_t* tile0;     // [n_prob + 1] or nullptr
+};
+inline SweepPlan single_plan(int G, int n_tiles) {
+  SweepPlan p;
+  p.n_prob = 1;
+  p.G = G;
+  p.n_tiles = n_tiles;
+  p.tpb_max = (n_tiles + G - 1) / G;
+  p.blk_prob = nullptr;
+  p.blk0 = nullptr;
+  p.tile0 = nullptr;
+  return p;
+}
 
 struct CellKParams {
   int kmode;  // 0 const, 1 Levermore-Pomraning
@@ -56,10 +95,12 @@ int grid_for(int64_t n);
 // ------------------------------------------------------------ setup kernels
 void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const double* rho,
                    const double* E_coarse, const CellKParams& kp, double* K);
+// w: weight of the coarse-to-fine Dirichlet part (1 D, 0 N, alpha R); alpha: Robin
+// weight of batch patch faces whose mode is Robin.
 void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const double* K_coarse,
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
-                     double dt, double w, const CouplingParams& cp, double* Cp, double* diag,
-                     double* b);
+                     double dt, double w, double alpha, const CouplingParams& cp, double* Cp,
+                     double* diag, double* b);
 void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, const double* K_c,
                           const double* E_f, const double* E_c, double dt, double* reg_c,
                           int n_slots_c);
@@ -74,35 +115,47 @@ void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* dia
 // 4 G doubles: [0, G) for the operator sweep, [G, 4G) for the update sweep.
 int sweep_blocks(int n_tiles, int max_blocks);
 
+// Every launcher below covers all problems of the plan; sc points at n_prob
+// scalar records.
 template <typename T>
-void launch_pcg_init(hipStream_t s, const DevLevel& L, int G, const T* Cp, const T* diag,
+void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const T* Cp, const T* diag,
                      const T* b, const T* x, T* r, T* p_clear, double* part);
-void launch_init_finish(hipStream_t s, int G, const double* part, PcgScalars* sc);
+void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, PcgScalars* sc);
 template <typename T>
-void launch_pass_a(hipStream_t s, const DevLevel& L, int G, int it, const T* Cp, const T* diag,
-                   const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part);
+void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* Cp,
+                   const T* diag, const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc,
+                   double* part);
 template <typename T>
-void launch_pass_b(hipStream_t s, const DevLevel& L, int G, int it, const T* diag, const T* p,
-                   const T* q, T* x, T* r, PcgScalars* sc, double* part);
-void launch_check(hipStream_t s, int G, int it_last, PcgScalars* sc, const double* part);
-void launch_true_residual(hipStream_t s, const DevLevel& L, int G, const double* Cp,
+void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* diag,
+                   const T* p, const T* q, T* x, T* r, PcgScalars* sc, double* part);
+void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part);
+void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp,
                           const double* diag, const double* b, const double* x, PcgScalars* sc,
                           double* part);
-void launch_post_solve(hipStream_t s, const DevLevel& L, int G, const double* E, const double* rho,
-                       const CouplingParams& cp, double dt, double* T_out, PcgScalars* sc,
-                       double* part);
+void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* E,
+                       const double* rho, const CouplingParams& cp, double dt, double* T_out,
+                       PcgScalars* sc, double* part);
 
 // ------------------------------------------- mixed precision (FP32 inner solve)
 // Outer sweep: x_new = x_old + d (d in FP32, may be null), r = b - A x_new in
 // FP64, r32 = (float) r; partials ||r||^2, ||b||^2, max |d| / |x_old|; then the
 // finisher applies the outer stopping test and prepares the inner scalars.
-void launch_ir_sweep(hipStream_t s, const DevLevel& L, int G, const double* Cp, const double* diag,
-                     const double* b, const double* x_old, const float* d, double* x_new,
-                     float* r32, double* part);
-void launch_ir_finish(hipStream_t s, int G, int first, double inner_tol, int inner_max,
+void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp,
+                     const double* diag, const double* b, const double* x_old, const float* d,
+                     double* x_new, float* r32, const PcgScalars* outer, double* part);
+void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int inner_max,
                       PcgScalars* outer, PcgScalars* inner, const double* part);
 // Inner start: d = 0, p = 0; partials (r, r / diag), ||r||^2 of the FP32 residual.
-void launch_inner_init(hipStream_t s, const DevLevel& L, int G, const float* diag32, const float* r32,
-                       float* d, float* p_clear, double* part);
+void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const float* diag32,
+                       const float* r32, float* d, float* p_clear, const PcgScalars* outer,
+                       double* part);
+
+// ------------------------------------------------------------- batch layout
+// dst[i] = src[prob(i)][idx[i]] (idx < 0: padding slot, dst = pad).
+void launch_batch_gather(hipStream_t s, const DevLevel& L, const int32_t* idx, const double* const* src,
+                         double pad, double* dst);
+// out[out_off[prob(i)] + idx[i]] = src[i] for every real slot.
+void launch_batch_scatter(hipStream_t s, const DevLevel& L, const int32_t* idx, const int64_t* out_off,
+                          const double* src, double* out);
 
 }  // namespace amrfld

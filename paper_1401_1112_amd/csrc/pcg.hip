@@ -28,9 +28,11 @@ int sweep_blocks(int n_tiles, int max_blocks) {
 namespace {
 
 using dev::apply_stencil;
+using dev::block_plan;
 using dev::block_reduce;
+using dev::BlockPlan;
+using dev::finisher_plan;
 using dev::reduce_partials_all;
-using dev::tile_range;
 
 constexpr int kLds = (kBlock / 64) * 3 + 4;
 
@@ -47,11 +49,12 @@ struct StopTest {
   bool fin, conv, stop;
 };
 
-__device__ __forceinline__ StopTest stop_test(const PcgScalars* sc, const double* part, int G, int it_done,
+// partB: the problem's update-sweep partials (3 per block, Gp blocks).
+__device__ __forceinline__ StopTest stop_test(const PcgScalars* sc, const double* partB, int Gp, int it_done,
                                               double* lds) {
   double v[3];
   const bool mx[3] = {false, false, true};
-  reduce_partials_all<3>(part + G, G, mx, v, lds);
+  reduce_partials_all<3>(partB, Gp, mx, v, lds);
   StopTest s;
   s.rz = v[0];
   s.rn = sqrt(v[1]);
@@ -84,16 +87,15 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], const bool (&mx)
 
 // r0 = b - A x0, p = 0; partials (r, r / d), ||r||^2, ||b||^2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, int n_tiles, const T* __restrict__ Cp,
+__global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, SweepPlan P, const T* __restrict__ Cp,
                                                      const T* __restrict__ diag, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ p_clear, double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
-  int t0, t1;
-  tile_range(n_tiles, t0, t1);
+  const BlockPlan bp = block_plan(P);
   double v[3] = {0.0, 0.0, 0.0};
-  for (int t = t0; t < t1; ++t) {
+  for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
@@ -110,14 +112,20 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, int n_tiles, co
     }
   }
   const bool mx[3] = {false, false, false};
-  write_partials<3>(v, mx, part + gridDim.x, lds);
+  write_partials<3>(v, mx, part + P.G, lds);
 }
 
-__global__ __launch_bounds__(kBlock) void k_init_finish(int G, const double* part, PcgScalars* sc) {
+// One block per problem.  A problem already marked done (the inner solve of a
+// converged problem in the batched refinement) is left as it is.
+__global__ __launch_bounds__(kBlock) void k_init_finish(SweepPlan P, const double* part, PcgScalars* scs) {
   __shared__ double lds[kLds];
+  int prob, b0, Gp;
+  finisher_plan(P, prob, b0, Gp);
+  PcgScalars* sc = scs + prob;
+  if (sc->done) return;
   double v[3];
   const bool mx[3] = {false, false, false};
-  reduce_partials_all<3>(part + G, G, mx, v, lds);
+  reduce_partials_all<3>(part + P.G + 3 * b0, Gp, mx, v, lds);
   if (threadIdx.x == 0) {
     const double r0 = sqrt(v[1]), bn = sqrt(v[2]);
     const double floor_b = sc->abs_floor * bn;
@@ -146,20 +154,20 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(int G, const double* par
 // rest recomputed from r, d and p_{it-1} in global memory (the two p buffers
 // alternate, so p_{it-1} is never overwritten during the sweep).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, int n_tiles, int it,
+__global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int it,
                                                    const T* __restrict__ Cp, const T* __restrict__ diag,
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
                                                    T* __restrict__ p_new, T* __restrict__ q,
-                                                   PcgScalars* sc, double* part) {
+                                                   PcgScalars* scs, double* part) {
   __shared__ double lds[kLds];
   extern __shared__ unsigned char dyn_lds[];
   T* pl = reinterpret_cast<T*>(dyn_lds);
+  const BlockPlan bp = block_plan(P);
+  PcgScalars* sc = scs + bp.prob;
   if (sc->done) return;
-  const int G = gridDim.x;
   const bool first = it == 1;
   const int n = L.n_slots;
-  int t0, t1;
-  tile_range(n_tiles, t0, t1);
+  const int t0 = bp.t0, t1 = bp.t1;
   const int s0 = t0 * kBlock;
   const int s1 = min(t1 * kBlock, n);
   // phase 1 loads: U1 slots per thread and trip, the first batch issued before
@@ -180,8 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, int n_tiles, int 
   load1(min(base, s1 - 1));
   double beta = 0.0;
   if (!first) {
-    const StopTest s = stop_test(sc, part, G, it - 1, lds);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const StopTest s = stop_test(sc, part + P.G + 3 * bp.b0, bp.Gp, it - 1, lds);
+    if (int(blockIdx.x) == bp.b0 && threadIdx.x == 0) {
       record_stop(sc, s, it - 1);
       if (!s.stop) sc->rho[it & 1] = s.rz;
     }
@@ -286,16 +294,16 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, int n_tiles, int 
 // Update sweep of iteration `it`: alpha = rho / (p, q); x += alpha p; r -= alpha q;
 // partials (r, z), ||r||^2 and max |alpha p| / |x|.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, int n_tiles, int it,
+__global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, SweepPlan P, int it,
                                                    const T* __restrict__ diag, const T* __restrict__ p,
                                                    const T* __restrict__ q, T* __restrict__ x,
-                                                   T* __restrict__ r, PcgScalars* sc, double* part) {
+                                                   T* __restrict__ r, PcgScalars* scs, double* part) {
   __shared__ double lds[kLds];
+  const BlockPlan bp = block_plan(P);
+  PcgScalars* sc = scs + bp.prob;
   if (sc->done) return;
-  const int G = gridDim.x;
   const int n = L.n_slots;
-  int t0, t1;
-  tile_range(n_tiles, t0, t1);
+  const int t0 = bp.t0, t1 = bp.t1;
   const int s1 = min(t1 * kBlock, n);
   // U slots per thread and trip; the first batch is loaded before the head
   // reduction (it does not depend on alpha), each next one before the current is used
@@ -316,10 +324,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, int n_tiles, int 
   load(min(base, s1 - 1));
   double pq[1];
   const bool mx1[1] = {false};
-  reduce_partials_all<1>(part, G, mx1, pq, lds);
+  reduce_partials_all<1>(part + bp.b0, bp.Gp, mx1, pq, lds);
   const double alpha = sc->rho[it & 1] / pq[0];
   if (!isfinite(alpha)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (int(blockIdx.x) == bp.b0 && threadIdx.x == 0) {
       sc->nonfinite = 1;
       sc->iter = it - 1;
       sc->done = 1;
@@ -353,28 +361,30 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, int n_tiles, int 
     }
   }
   const bool mx[3] = {false, false, true};
-  write_partials<3>(v, mx, part + G, lds);
+  write_partials<3>(v, mx, part + P.G, lds);
 }
 
 // Applies the stopping test after the update sweep of iteration it_last (the
 // test the next operator sweep would make) so that the host sees convergence.
-__global__ __launch_bounds__(kBlock) void k_check(int G, int it_last, PcgScalars* sc, const double* part) {
+__global__ __launch_bounds__(kBlock) void k_check(SweepPlan P, int it_last, PcgScalars* scs, const double* part) {
   __shared__ double lds[kLds];
+  int prob, b0, Gp;
+  finisher_plan(P, prob, b0, Gp);
+  PcgScalars* sc = scs + prob;
   if (sc->done) return;
-  const StopTest s = stop_test(sc, part, G, it_last, lds);
+  const StopTest s = stop_test(sc, part + P.G + 3 * b0, Gp, it_last, lds);
   if (threadIdx.x == 0) record_stop(sc, s, it_last);
 }
 
-__global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, int n_tiles, const double* __restrict__ Cp,
+__global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
                                                           const double* __restrict__ diag,
                                                           const double* __restrict__ b,
                                                           const double* __restrict__ x, double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
-  int t0, t1;
-  tile_range(n_tiles, t0, t1);
+  const BlockPlan bp = block_plan(P);
   double v[1] = {0.0};
-  for (int t = t0; t < t1; ++t) {
+  for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
@@ -389,16 +399,15 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, int n_tile
 }
 
 // T update of the coupling term (linearised emission) and smallest leaf energy.
-__global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, int n_tiles, const double* __restrict__ E,
+__global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, const double* __restrict__ E,
                                                        const double* __restrict__ rho, CouplingParams cp,
                                                        double dt, double* __restrict__ T_out, double* part) {
   __shared__ double lds[kLds];
-  int t0, t1;
-  tile_range(n_tiles, t0, t1);
+  const BlockPlan bp = block_plan(P);
   double v[1] = {-DBL_MAX};
-  for (int t = t0; t < t1; ++t) {
+  for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
-    if (i < L.n_slots && L.child[i] < 0) {
+    if (i < L.n_slots && L.child[i] == -1) {
       const double e = E[i];
       v[0] = fmax(v[0], -e);
       if (cp.T) {
@@ -415,11 +424,14 @@ __global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, int n_tiles, 
 }
 
 // kind 0: true residual norm; kind 1: smallest leaf energy.
-__global__ __launch_bounds__(kBlock) void k_finish(int G, int kind, const double* part, PcgScalars* sc) {
+__global__ __launch_bounds__(kBlock) void k_finish(SweepPlan P, int kind, const double* part, PcgScalars* scs) {
   __shared__ double lds[kLds];
+  int prob, b0, Gp;
+  finisher_plan(P, prob, b0, Gp);
+  PcgScalars* sc = scs + prob;
   double v[1];
   const bool mx[1] = {kind == 1};
-  reduce_partials_all<1>(part, G, mx, v, lds);
+  reduce_partials_all<1>(part + b0, Gp, mx, v, lds);
   if (threadIdx.x == 0) {
     if (kind == 0) sc->true_rnorm = sqrt(v[0]);
     else sc->min_E = -v[0];
@@ -427,19 +439,23 @@ __global__ __launch_bounds__(kBlock) void k_finish(int G, int kind, const double
 }
 
 // ------------------------------------------------------------ mixed precision
-__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, int n_tiles, const double* __restrict__ Cp,
+__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
                                                      const double* __restrict__ diag,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x_old,
                                                      const float* __restrict__ d, double* __restrict__ x_new,
-                                                     float* __restrict__ r32, double* part) {
+                                                     float* __restrict__ r32, const PcgScalars* outer,
+                                                     double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
+  const BlockPlan bp = block_plan(P);
+  if (outer[bp.prob].done) {  // converged problem: carry its iterate into the new buffer
+    for (int i = bp.t0 * kBlock + int(threadIdx.x); i < min(bp.t1 * kBlock, n); i += kBlock) x_new[i] = x_old[i];
+    return;
+  }
   auto xv = [&](int j) -> double { return d ? x_old[j] + double(d[j]) : x_old[j]; };
-  int t0, t1;
-  tile_range(n_tiles, t0, t1);
   double v[3] = {0.0, 0.0, 0.0};
-  for (int t = t0; t < t1; ++t) {
+  for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
@@ -455,15 +471,25 @@ __global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, int n_tiles, co
     }
   }
   const bool mx[3] = {false, false, true};
-  write_partials<3>(v, mx, part + gridDim.x, lds);
+  write_partials<3>(v, mx, part + P.G, lds);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_finish(int G, int first, double inner_tol, int inner_max,
-                                                      PcgScalars* out, PcgScalars* in, const double* part) {
+// One block per problem: the outer stopping test, then the inner scalars.  A
+// problem done in an earlier sweep keeps its state and its inner solve is off.
+__global__ __launch_bounds__(kBlock) void k_ir_finish(SweepPlan P, int first, double inner_tol, int inner_max,
+                                                      PcgScalars* outs, PcgScalars* ins, const double* part) {
   __shared__ double lds[kLds];
+  int prob, b0, Gp;
+  finisher_plan(P, prob, b0, Gp);
+  PcgScalars* out = outs + prob;
+  PcgScalars* in = ins + prob;
+  if (out->done) {
+    if (threadIdx.x == 0) in->done = 1;
+    return;
+  }
   double v[3];
   const bool mx[3] = {false, false, true};
-  reduce_partials_all<3>(part + G, G, mx, v, lds);
+  reduce_partials_all<3>(part + P.G + 3 * b0, Gp, mx, v, lds);
   if (threadIdx.x != 0) return;
   const double rn = sqrt(v[0]), bn = sqrt(v[1]), linf = v[2];
   const bool fin = isfinite(rn) && isfinite(bn);
@@ -490,20 +516,21 @@ __global__ __launch_bounds__(kBlock) void k_ir_finish(int G, int first, double i
   in->abs_floor = 0.0;
   in->max_iter = inner_max;
   in->linf_test = 0;
-  in->done = 0;
+  in->done = out->done;
   in->converged = 0;
   in->nonfinite = 0;
   in->iter = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, int n_tiles, const float* __restrict__ diag32,
+__global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, SweepPlan P, const float* __restrict__ diag32,
                                                        const float* __restrict__ r32, float* __restrict__ d,
-                                                       float* __restrict__ p_clear, double* part) {
+                                                       float* __restrict__ p_clear, const PcgScalars* outer,
+                                                       double* part) {
   __shared__ double lds[kLds];
-  int t0, t1;
-  tile_range(n_tiles, t0, t1);
+  const BlockPlan bp = block_plan(P);
+  if (outer[bp.prob].done) return;
   double v[3] = {0.0, 0.0, 0.0};
-  for (int t = t0; t < t1; ++t) {
+  for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
     if (i < L.n_slots) {
       d[i] = 0.0f;
@@ -516,85 +543,82 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, int n_tiles, 
     }
   }
   const bool mx[3] = {false, false, false};
-  write_partials<3>(v, mx, part + gridDim.x, lds);
+  write_partials<3>(v, mx, part + P.G, lds);
 }
 
 }  // namespace
 
 // ------------------------------------------------------------ launchers
 template <typename T>
-void launch_pcg_init(hipStream_t s, const DevLevel& L, int G, const T* Cp, const T* diag, const T* b,
-                     const T* x, T* r, T* p_clear, double* part) {
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), Cp, diag, b, x,
-                     r, p_clear, part);
+void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const T* Cp, const T* diag,
+                     const T* b, const T* x, T* r, T* p_clear, double* part) {
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, Cp, diag, b, x, r, p_clear, part);
 }
 
-void launch_init_finish(hipStream_t s, int G, const double* part, PcgScalars* sc) {
-  hipLaunchKernelGGL(k_init_finish, dim3(1), dim3(kBlock), 0, s, G, part, sc);
-}
-
-template <typename T>
-void launch_pass_a(hipStream_t s, const DevLevel& L, int G, int it, const T* Cp, const T* diag, const T* r,
-                   const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part) {
-  const int n_tiles = tiles_of(L.n_slots);
-  const size_t lds = size_t((n_tiles + G - 1) / G) * kBlock * sizeof(T);
-  hipLaunchKernelGGL(k_pass_a<T>, dim3(G), dim3(kBlock), lds, s, L, n_tiles, it, Cp, diag, r, p_old, p_new,
-                     q, sc, part);
+void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, PcgScalars* sc) {
+  hipLaunchKernelGGL(k_init_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, part, sc);
 }
 
 template <typename T>
-void launch_pass_b(hipStream_t s, const DevLevel& L, int G, int it, const T* diag, const T* p, const T* q,
-                   T* x, T* r, PcgScalars* sc, double* part) {
-  hipLaunchKernelGGL(k_pass_b<T>, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), it, diag, p, q, x,
-                     r, sc, part);
-}
-
-void launch_check(hipStream_t s, int G, int it_last, PcgScalars* sc, const double* part) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, G, it_last, sc, part);
-}
-
-void launch_true_residual(hipStream_t s, const DevLevel& L, int G, const double* Cp, const double* diag,
-                          const double* b, const double* x, PcgScalars* sc, double* part) {
-  hipLaunchKernelGGL(k_true_residual, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), Cp, diag, b,
-                     x, part);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, G, 0, part, sc);
-}
-
-void launch_post_solve(hipStream_t s, const DevLevel& L, int G, const double* E, const double* rho,
-                       const CouplingParams& cp, double dt, double* T_out, PcgScalars* sc, double* part) {
-  hipLaunchKernelGGL(k_post_solve, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), E, rho, cp, dt,
-                     T_out, part);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, s, G, 1, part, sc);
-}
-
-void launch_ir_sweep(hipStream_t s, const DevLevel& L, int G, const double* Cp, const double* diag,
-                     const double* b, const double* x_old, const float* d, double* x_new, float* r32,
-                     double* part) {
-  hipLaunchKernelGGL(k_ir_sweep, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), Cp, diag, b, x_old,
-                     d, x_new, r32, part);
-}
-
-void launch_ir_finish(hipStream_t s, int G, int first, double inner_tol, int inner_max, PcgScalars* outer,
-                      PcgScalars* inner, const double* part) {
-  hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, G, first, inner_tol, inner_max, outer, inner,
+void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* Cp, const T* diag,
+                   const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part) {
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
+  hipLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), lds, s, L, P, it, Cp, diag, r, p_old, p_new, q, sc,
                      part);
 }
 
-void launch_inner_init(hipStream_t s, const DevLevel& L, int G, const float* diag32, const float* r32,
-                       float* d, float* p_clear, double* part) {
-  hipLaunchKernelGGL(k_inner_init, dim3(G), dim3(kBlock), 0, s, L, tiles_of(L.n_slots), diag32, r32, d,
-                     p_clear, part);
+template <typename T>
+void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* diag, const T* p,
+                   const T* q, T* x, T* r, PcgScalars* sc, double* part) {
+  hipLaunchKernelGGL(k_pass_b<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, it, diag, p, q, x, r, sc, part);
 }
 
-template void launch_pcg_init<double>(hipStream_t, const DevLevel&, int, const double*, const double*,
-                                      const double*, const double*, double*, double*, double*);
-template void launch_pass_a<double>(hipStream_t, const DevLevel&, int, int, const double*, const double*,
+void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part) {
+  hipLaunchKernelGGL(k_check, dim3(P.n_prob), dim3(kBlock), 0, s, P, it_last, sc, part);
+}
+
+void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp,
+                          const double* diag, const double* b, const double* x, PcgScalars* sc, double* part) {
+  hipLaunchKernelGGL(k_true_residual, dim3(P.G), dim3(kBlock), 0, s, L, P, Cp, diag, b, x, part);
+  hipLaunchKernelGGL(k_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, 0, part, sc);
+}
+
+void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* E, const double* rho,
+                       const CouplingParams& cp, double dt, double* T_out, PcgScalars* sc, double* part) {
+  hipLaunchKernelGGL(k_post_solve, dim3(P.G), dim3(kBlock), 0, s, L, P, E, rho, cp, dt, T_out, part);
+  hipLaunchKernelGGL(k_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, 1, part, sc);
+}
+
+void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp, const double* diag,
+                     const double* b, const double* x_old, const float* d, double* x_new, float* r32,
+                     const PcgScalars* outer, double* part) {
+  hipLaunchKernelGGL(k_ir_sweep, dim3(P.G), dim3(kBlock), 0, s, L, P, Cp, diag, b, x_old, d, x_new, r32, outer,
+                     part);
+}
+
+void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int inner_max,
+                      PcgScalars* outer, PcgScalars* inner, const double* part) {
+  hipLaunchKernelGGL(k_ir_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, first, inner_tol, inner_max, outer,
+                     inner, part);
+}
+
+void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const float* diag32,
+                       const float* r32, float* d, float* p_clear, const PcgScalars* outer, double* part) {
+  hipLaunchKernelGGL(k_inner_init, dim3(P.G), dim3(kBlock), 0, s, L, P, diag32, r32, d, p_clear, outer, part);
+}
+
+template void launch_pcg_init<double>(hipStream_t, const DevLevel&, const SweepPlan&, const double*,
+                                      const double*, const double*, const double*, double*, double*,
+                                      double*);
+template void launch_pass_a<double>(hipStream_t, const DevLevel&, const SweepPlan&, int, const double*,
+                                    const double*, const double*, const double*, double*, double*,
+                                    PcgScalars*, double*);
+template void launch_pass_b<double>(hipStream_t, const DevLevel&, const SweepPlan&, int, const double*,
                                     const double*, const double*, double*, double*, PcgScalars*, double*);
-template void launch_pass_b<double>(hipStream_t, const DevLevel&, int, int, const double*, const double*,
-                                    const double*, double*, double*, PcgScalars*, double*);
-template void launch_pass_a<float>(hipStream_t, const DevLevel&, int, int, const float*, const float*,
+template void launch_pass_a<float>(hipStream_t, const DevLevel&, const SweepPlan&, int, const float*,
+                                   const float*, const float*, const float*, float*, float*, PcgScalars*,
+                                   double*);
+template void launch_pass_b<float>(hipStream_t, const DevLevel&, const SweepPlan&, int, const float*,
                                    const float*, const float*, float*, float*, PcgScalars*, double*);
-template void launch_pass_b<float>(hipStream_t, const DevLevel&, int, int, const float*, const float*,
-                                   const float*, float*, float*, PcgScalars*, double*);
 
 }  // namespace amrfld

@@ -19,10 +19,19 @@ __global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __r
                                                    double* __restrict__ K) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= L.n_slots) return;
-  if (kp.kmode == 0) {
-    K[i] = kp.K_const;
+  if (L.child[i] == -2) {  // padding slot of a batch
+    K[i] = 0.0;
     return;
   }
+  const PatchParams* pp = L.pp ? &L.pp[L.oct_prob[i >> 3]] : nullptr;
+  const int kmode = pp ? pp->kmode : kp.kmode;
+  if (kmode == 0) {
+    K[i] = pp ? pp->K_const : kp.K_const;
+    return;
+  }
+  const double dx = pp ? pp->dx : L.dx;
+  const double kappa_R = pp ? pp->kappa_R : kp.kappa_R;
+  const double c_light = pp ? pp->c_light : kp.c_light;
   const double Ei = E[i];
   double g2 = 0.0;
 #pragma unroll
@@ -34,36 +43,36 @@ __global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __r
       const int j = same_level_nb(L.nbr, i, dir);
       if (j >= 0) {
         v[side] = E[j];
-        h[side] = L.dx;
+        h[side] = dx;
       } else {
         const int c = L.cnb[(i >> 3) * 6 + dir];
         if (c >= 0) {
           v[side] = Ec[c];
-          h[side] = 1.5 * L.dx;
+          h[side] = 1.5 * dx;
         } else {
           v[side] = Ei;
-          h[side] = L.dx;
+          h[side] = dx;
         }
       }
     }
     const double g = (v[1] - v[0]) / (h[0] + h[1]);
     g2 += g * g;
   }
-  const double rk = rho[i] * kp.kappa_R;
+  const double rk = rho[i] * kappa_R;
   const double R = sqrt(g2) / (rk * Ei);
   const double lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
-  K[i] = kp.c_light * lam / rk;
+  K[i] = c_light * lam / rk;
 }
 
 __global__ __launch_bounds__(kBlock) void k_assemble(
     DevLevel L, const double* __restrict__ K, const double* __restrict__ Kc,
     const double* __restrict__ E, const double* __restrict__ Ec, const double* __restrict__ rho,
-    const double* __restrict__ reg, double coef, double w, CouplingParams cp, double dt,
+    const double* __restrict__ reg, double coef, double w, double alpha, CouplingParams cp, double dt,
     double* __restrict__ Cp, double* __restrict__ diag, double* __restrict__ b) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int n = L.n_slots;
   if (i >= n) return;
-  if (L.child[i] >= 0) {  // refined slot: identity row, r stays 0
+  if (L.child[i] != -1) {  // refined or padding slot: identity row, r stays 0
     Cp[i] = 0.0;
     Cp[size_t(n) + i] = 0.0;
     Cp[2 * size_t(n) + i] = 0.0;
@@ -71,6 +80,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
     b[i] = E[i];
     return;
   }
+  const PatchParams* pp = L.pp ? &L.pp[L.oct_prob[i >> 3]] : nullptr;
+  if (pp) coef = pp->coef;
   const double Ki = K[i];
   double d = 1.0, bb = E[i];
   double cplus[3] = {0.0, 0.0, 0.0};
@@ -93,6 +104,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
         const double C = (2.0 / 3.0) * harmonic(Ki, Kc[c]) * coef;
         d += C;
         bb += C * Ec[c];
+      } else if (pp) {  // patch boundary: D / N / R with a given ghost and inflow
+        const int m = pp->mode[dir];
+        const double wf = m == 0 ? 1.0 : m == 1 ? 0.0 : alpha;
+        const double C = Ki * coef;  // ghost cell with the cell's own diffusivity
+        d += wf * C;
+        bb += wf * C * pp->ghost[dir] + (1.0 - wf) * pp->flux[dir];
       }
     }
   }
@@ -168,7 +185,35 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(int64_t n, const double* __re
   diag32[i] = float(diag[i]);
 }
 
+__global__ __launch_bounds__(kBlock) void k_batch_gather(DevLevel L, const int32_t* __restrict__ idx,
+                                                         const double* const* __restrict__ src, double pad,
+                                                         double* __restrict__ dst) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.n_slots) return;
+  const int k = idx[i];
+  dst[i] = k >= 0 ? src[L.oct_prob[i >> 3]][k] : pad;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_scatter(DevLevel L, const int32_t* __restrict__ idx,
+                                                          const int64_t* __restrict__ out_off,
+                                                          const double* __restrict__ src, double* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.n_slots) return;
+  const int k = idx[i];
+  if (k >= 0) out[out_off[L.oct_prob[i >> 3]] + k] = src[i];
+}
+
 }  // namespace
+
+void launch_batch_gather(hipStream_t s, const DevLevel& L, const int32_t* idx, const double* const* src,
+                         double pad, double* dst) {
+  hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, idx, src, pad, dst);
+}
+
+void launch_batch_scatter(hipStream_t s, const DevLevel& L, const int32_t* idx, const int64_t* out_off,
+                          const double* src, double* out) {
+  hipLaunchKernelGGL(k_batch_scatter, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, idx, out_off, src, out);
+}
 
 void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const double* rho,
                    const double* E_coarse, const CellKParams& kp, double* K) {
@@ -178,11 +223,11 @@ void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const doub
 
 void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const double* K_coarse,
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
-                     double dt, double w, const CouplingParams& cp, double* Cp, double* diag,
+                     double dt, double w, double alpha, const CouplingParams& cp, double* Cp, double* diag,
                      double* b) {
   const double coef = dt / (L.dx * L.dx);
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, K, K_coarse, E,
-                     E_coarse, rho, reg, coef, w, cp, dt, Cp, diag, b);
+                     E_coarse, rho, reg, coef, w, alpha, cp, dt, Cp, diag, b);
 }
 
 void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, const double* K_c,

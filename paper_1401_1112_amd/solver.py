@@ -132,3 +132,76 @@ def solver_from_problem(problem, **over):
 
 def to_numpy(t):
     return t.detach().cpu().numpy() if isinstance(t, torch.Tensor) else np.asarray(t)
+
+
+class BatchSolver:
+    """Independent patches advanced together (amrfld_solve_batch)."""
+
+    def __init__(self, *, robin_alpha=0.5, max_iter=10000, linf_test=True, abs_floor=1e-14,
+                 inner_tol=1e-4, max_outer=30, max_blocks=0, time_sweeps=0, true_residual=True,
+                 check_every=0, device="cuda:0", stream=None):
+        L.load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        o = L.amrfld_default_opts()
+        o.base_level, o.max_level = 1, 1
+        o.robin_alpha = float(robin_alpha)
+        o.max_iter = int(max_iter)
+        o.linf_test = int(bool(linf_test))
+        o.abs_floor = float(abs_floor)
+        o.inner_tol = float(inner_tol)
+        o.max_outer = int(max_outer)
+        o.max_blocks = int(max_blocks)
+        o.time_sweeps = int(time_sweeps)
+        o.true_residual = int(bool(true_residual))
+        o.check_every = int(check_every)
+        o.stream = self.stream.cuda_stream
+        self.ctx = L.amrfld_create(o)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            L.amrfld_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, patches, n_steps, tol, precision=L.FP64, kmode=L.K_LP, kappa_R=1.0, c_light=1.0,
+              K_const=1.0, raise_on_error=True):
+        """patches: objects with n, dx, dt, rho, E ([i, j, k] arrays), face_mode, face_ghost,
+        face_flux.  Returns the final energies as a list of (n, n, n) [i, j, k] arrays and the
+        status."""
+        keep, structs, offs = [], [], [0]
+        for p in patches:
+            n = int(p.n)
+            rho = torch.as_tensor(np.ascontiguousarray(np.asarray(p.rho).transpose(2, 1, 0)).ravel(),
+                                  dtype=torch.float64).to(self.device)
+            E = torch.as_tensor(np.ascontiguousarray(np.asarray(p.E).transpose(2, 1, 0)).ravel(),
+                                dtype=torch.float64).to(self.device)
+            keep += [rho, E]
+            st = L.amrfld_patch()
+            st.n, st.dx, st.dt = n, float(p.dx), float(p.dt)
+            st.rho, st.E = rho.data_ptr(), E.data_ptr()
+            st.kmode, st.K_const, st.kappa_R, st.c_light = int(kmode), float(K_const), float(kappa_R), float(c_light)
+            for d in range(6):
+                st.face_mode[d] = int(p.face_mode[d])
+                st.face_ghost[d] = float(p.face_ghost[d])
+                st.face_flux[d] = float(p.face_flux[d])
+            structs.append(st)
+            offs.append(offs[-1] + n ** 3)
+        out = torch.empty(offs[-1], dtype=torch.float64, device=self.device)
+        status = L.amrfld_solve_batch(self.ctx, structs, n_steps, tol, precision, out)
+        if raise_on_error and status != L.OK:
+            raise L.AmrfldError(status, L.amrfld_last_error(self.ctx))
+        host = out.cpu().numpy()
+        res = []
+        for q, p in enumerate(patches):
+            n = int(p.n)
+            res.append(host[offs[q]:offs[q + 1]].reshape(n, n, n).transpose(2, 1, 0).copy())
+        return res, status
+
+    def stats(self):
+        return L.amrfld_last_stats(self.ctx)
