@@ -78,6 +78,8 @@ typedef struct {
   double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner solve; default 1e-4 */
   int max_outer;         /* AMRFLD_MIXED: refinement sweeps cap; default 30 */
   int max_blocks;        /* blocks per PCG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
+  int persistent;        /* batch form: 1 = all PCG iterations of a step in one cooperative launch */
+  int graph;             /* batch form with persistent: 1 = capture all steps in one hipGraph */
   void* stream;          /* hipStream_t */
 } amrfld_opts;
 
@@ -95,6 +97,7 @@ typedef struct {
   int n_timed;           /* iterations whose sweeps were timed (time_sweeps), else 0 */
   double pass_a_ms;      /* summed device time of the timed operator sweeps (pass A) */
   double pass_b_ms;      /* summed device time of the timed update sweeps (pass B) */
+  int launch_mode;       /* 0 host-polled sweeps, 1 persistent launch, 2 persistent launches in a hipGraph */
 } amrfld_stats;
 
 /* Fill *o with the defaults listed above. */

@@ -31,7 +31,7 @@ class amrfld_opts(ctypes.Structure):
         ("nsub", ctypes.c_int * 32), ("check_every", ctypes.c_int),
         ("true_residual", ctypes.c_int), ("time_sweeps", ctypes.c_int),
         ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_blocks", ctypes.c_int),
-        ("stream", ctypes.c_void_p),
+        ("persistent", ctypes.c_int), ("graph", ctypes.c_int), ("stream", ctypes.c_void_p),
     ]
 
 
@@ -43,6 +43,7 @@ class amrfld_stats(ctypes.Structure):
         ("linf_change", ctypes.c_double), ("min_E", ctypes.c_double), ("ms", ctypes.c_double),
         ("pcg_ms", ctypes.c_double), ("dt", ctypes.c_double), ("outer_iters", ctypes.c_int),
         ("n_timed", ctypes.c_int), ("pass_a_ms", ctypes.c_double), ("pass_b_ms", ctypes.c_double),
+        ("launch_mode", ctypes.c_int),
     ]
 
     def as_dict(self):

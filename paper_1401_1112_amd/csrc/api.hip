@@ -128,6 +128,7 @@ struct BatchState {
     p.blk_prob = blk_prob;
     p.blk0 = blk0;
     p.tile0 = tile0;
+    p.done_count = nullptr;
     return p;
   }
 };
@@ -149,6 +150,9 @@ struct amrfld_ctx {
   PcgScalars* h_sc = nullptr;   // pinned mirror
   int sc_cap = 0;
   struct BatchState* batch = nullptr;
+  unsigned* bar = nullptr;  // grid barrier counter, generation, done counter, abort flag
+  hipStream_t cap_stream = nullptr;  // library stream for graph capture (default priority)
+  hipEvent_t cap_ev[2] = {nullptr, nullptr};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> sweep_ev;  // 4 per iteration when sweeps are timed
   std::vector<amrfld_stats> stats;
@@ -671,6 +675,115 @@ void build_batch(amrfld_ctx* c, const std::vector<int>& sizes) {
   check(hipStreamSynchronize(c->stream()), "batch tables");
 }
 
+// All steps of a batch with one cooperative launch per step for the PCG
+// iterations, optionally captured in one hipGraph.  Returns AMRFLD_E_STATE when
+// the device cannot run the cooperative launch (the caller then polls).
+amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, int n_steps, double tol) {
+  BatchState& B = *c->batch;
+  const int np = B.n_prob;
+  const DevLevel D = B.dev();
+  SweepPlan P = B.plan();
+  if (!c->bar) c->bar = dalloc<unsigned>(4, "barrier");
+  P.done_count = c->bar + 2;
+  int* abort_flag = reinterpret_cast<int*>(c->bar + 3);
+  if (persistent_blocks(P) <= 0) return AMRFLD_E_STATE;
+  ensure_scalars(c, n_steps * np);
+  CouplingParams cp{};
+  cp.T = nullptr;
+  const CellKParams kp{1, 1.0, 1.0, 1.0};
+  auto record = [&](hipStream_t st) -> hipError_t {
+    launch_zero_u32(st, c->bar + 3, 1);
+    for (int step = 0; step < n_steps; ++step) {
+      PcgScalars* sc = c->sc + int64_t(step) * np;
+      launch_cell_K(st, D, B.E, B.rho, nullptr, kp, B.K);
+      launch_assemble(st, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, B.Cp,
+                      B.diag, B.b);
+      launch_init_scalars(st, sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
+      launch_zero_u32(st, c->bar, 3);
+      launch_pcg_init<double>(st, D, P, B.Cp, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
+      launch_init_finish(st, P, c->partials, sc);
+      const hipError_t e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, B.Cp, B.diag, B.E, c->r, c->p,
+                                                         c->q, sc, c->partials, c->bar, abort_flag);
+      if (e != hipSuccess) return e;
+      if (c->o.true_residual) launch_true_residual(st, D, P, B.Cp, B.diag, B.b, B.E, sc, c->partials);
+      launch_post_solve(st, D, P, B.E, B.rho, cp, 0.0, nullptr, sc, c->partials);
+    }
+    return hipGetLastError();
+  };
+  const hipStream_t us = c->stream();
+  int mode = c->o.graph ? 2 : 1;
+  float total_ms = 0.f;
+  if (mode == 2) {
+    if (!c->cap_stream) check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream");
+    for (auto& e : c->cap_ev)
+      if (!e) check(hipEventCreate(&e), "event");
+    check(hipEventRecord(c->cap_ev[0], us), "event");
+    check(hipStreamWaitEvent(c->cap_stream, c->cap_ev[0], 0), "event");
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e_rec = e == hipSuccess ? record(c->cap_stream) : e;
+    hipError_t e_end = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &g) : e;
+    hipGraphExec_t ex = nullptr;
+    if (e_rec == hipSuccess && e_end == hipSuccess && g)
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    else
+      e = hipErrorNotSupported;
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      mode = 1;
+    } else {
+      check(hipEventRecord(c->cap_ev[0], c->cap_stream), "event");
+      check(hipGraphLaunch(ex, c->cap_stream), "graph launch");
+      check(hipEventRecord(c->cap_ev[1], c->cap_stream), "event");
+      check(hipStreamSynchronize(c->cap_stream), "graph");
+      check(hipEventElapsedTime(&total_ms, c->cap_ev[0], c->cap_ev[1]), "event");
+      (void)hipGraphExecDestroy(ex);
+      (void)hipGraphDestroy(g);
+    }
+  }
+  if (mode == 1) {
+    check(hipEventRecord(c->ev[0], us), "event");
+    check(record(us), "persistent launch");
+    check(hipEventRecord(c->ev[3], us), "event");
+    check(hipStreamSynchronize(us), "sync");
+    check(hipEventElapsedTime(&total_ms, c->ev[0], c->ev[3]), "event");
+  }
+  int aborted = 0;
+  check(hipMemcpy(&aborted, abort_flag, sizeof(int), hipMemcpyDeviceToHost), "abort flag");
+  read_scalars(c, c->h_sc, c->sc, n_steps * np);
+  amrfld_status worst = AMRFLD_OK;
+  std::string worst_msg;
+  for (int step = 0; step < n_steps; ++step) {
+    for (int q = 0; q < np; ++q) {
+      const PcgScalars& h = c->h_sc[int64_t(step) * np + q];
+      amrfld_stats st{};
+      st.level = q;
+      st.iters = h.iter;
+      st.converged = h.converged;
+      st.n_leaf = int64_t(B.sizes[q]) * B.sizes[q] * B.sizes[q];
+      st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
+      st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+      st.linf_change = h.linf;
+      st.min_E = h.min_E;
+      st.dt = pt[q].dt;
+      st.ms = total_ms / n_steps;
+      st.pcg_ms = -1.0;
+      st.launch_mode = mode;
+      st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
+      if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
+        worst = amrfld_status(st.status);
+        worst_msg = "patch " + std::to_string(q) + " step " + std::to_string(step) +
+                    (st.status == AMRFLD_E_NONFINITE ? ": non-finite residual" : ": no convergence");
+      }
+      c->stats.push_back(st);
+    }
+  }
+  if (aborted) return fail(c, AMRFLD_E_DEVICE, "persistent sweep: a grid barrier timed out");
+  if (worst != AMRFLD_OK) return fail(c, worst, worst_msg);
+  return AMRFLD_OK;
+}
+
 amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, int n_steps, double tol,
                           int precision) {
   const hipStream_t s = c->stream();
@@ -706,6 +819,11 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
   check(hipMemcpyAsync(B.src, ptr.data(), np * sizeof(void*), hipMemcpyHostToDevice, s), "batch pointers");
   launch_batch_gather(s, D, B.idx, B.src, 0.0, B.E);
   ensure_workspace(c, B.n_slots);
+  if (c->o.persistent && precision == AMRFLD_FP64) {
+    const amrfld_status st = solve_batch_persistent(c, pt, n_steps, tol);
+    if (st != AMRFLD_E_STATE) return st;
+    c->stats.clear();  // the device cannot run it: poll instead
+  }
   ensure_scalars(c, np);
   const SweepPlan P = B.plan();
   const int saved_precision = c->o.precision;
@@ -842,6 +960,10 @@ void amrfld_destroy(amrfld_ctx* c) {
     c->batch->release();
     delete c->batch;
   }
+  dfree(c->bar);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (auto& e : c->cap_ev)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : {(void*)c->r, (void*)c->p[0], (void*)c->p[1], (void*)c->q, (void*)c->partials,
                   (void*)c->sc, (void*)c->Cp32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
                   (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})

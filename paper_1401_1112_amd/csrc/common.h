@@ -100,9 +100,8 @@ struct BlockPlan {
   int prob, b0, Gp, t0, t1;
 };
 
-__device__ __forceinline__ BlockPlan block_plan(const SweepPlan& P) {
+__device__ __forceinline__ BlockPlan block_plan(const SweepPlan& P, int b) {
   BlockPlan bp;
-  const int b = blockIdx.x;
   int T0, nt;
   if (P.blk0) {
     bp.prob = P.blk_prob[b];
@@ -124,11 +123,43 @@ __device__ __forceinline__ BlockPlan block_plan(const SweepPlan& P) {
   return bp;
 }
 
-// Problem handled by a one-block-per-problem finisher launch.
-__device__ __forceinline__ void finisher_plan(const SweepPlan& P, int& prob, int& b0, int& Gp) {
-  prob = blockIdx.x;
+// Blocks of problem `prob` (for the one-block-per-problem finishers).
+__device__ __forceinline__ void problem_blocks(const SweepPlan& P, int prob, int& b0, int& Gp) {
   b0 = P.blk0 ? P.blk0[prob] : 0;
   Gp = P.blk0 ? P.blk0[prob + 1] - b0 : P.G;
+}
+
+// Grid-wide barrier of a cooperative launch (all blocks resident).  Thread 0 of
+// each block releases the block's writes (agent-scope fence), arrives on a
+// counter, and waits for the generation to move; the last arrival resets the
+// counter and moves the generation.  The wait is bounded: after spin_limit
+// polls the block reports failure instead of waiting forever.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned n_blocks, unsigned spin_limit) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    if (arrived == n_blocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned polls = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++polls > spin_limit) {
+          good = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
 }
 
 // The 7-point operator at slot ii applied to a vector whose value at ii is pi

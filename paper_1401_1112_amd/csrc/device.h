@@ -27,6 +27,8 @@ struct PcgScalars {
   int nonfinite;
   int max_iter;
   int linf_test;
+  int counted;      // this problem's stop has been added to the plan's done counter
+  int pad_;
 };
 
 // Parameters of one independent patch of a batch: a box of cells of size dx
@@ -43,15 +45,15 @@ struct PatchParams {
 // One level's (or one batch's) device tables, slot order.  child: >= 0 child
 // oct (refined slot), -1 leaf, -2 padding slot of a batch (identity row).
 struct DevLevel {
-  int n_slots;
-  int n_oct;
-  const int32_t* nbr;       // [n_oct*6]
-  const int32_t* cnb;       // [n_oct*6]
-  const int32_t* child;     // [n_slots]
-  const int32_t* parent;    // [n_oct]
-  double dx, vol;
-  const int32_t* oct_prob;  // batch: patch of each oct (nullptr for a level)
-  const PatchParams* pp;    // batch: per-patch parameters (nullptr for a level)
+  int n_slots = 0;
+  int n_oct = 0;
+  const int32_t* nbr = nullptr;       // [n_oct*6]
+  const int32_t* cnb = nullptr;       // [n_oct*6]
+  const int32_t* child = nullptr;     // [n_slots]
+  const int32_t* parent = nullptr;    // [n_oct]
+  double dx = 1.0, vol = 1.0;
+  const int32_t* oct_prob = nullptr;  // batch: patch of each oct (nullptr for a level)
+  const PatchParams* pp = nullptr;    // batch: per-patch parameters (nullptr for a level)
 };
 
 // How the blocks of a sweep are spread over independent problems (a level is
@@ -59,13 +61,14 @@ struct DevLevel {
 // [tile0[q], tile0[q+1]); blocks never straddle problems, so block partials
 // and scalars are per problem.
 struct SweepPlan {
-  int n_prob;
-  int G;                    // total blocks
-  int n_tiles;              // used when the arrays are null (one problem)
-  int tpb_max;              // largest tile count of one block (sizes the LDS of the operator sweep)
-  const int32_t* blk_prob;  // [G] or nullptr
-  const int32_t* blk0;      // [n_prob + 1] or nullptr
-  const int32_t* tile0;     // [n_prob + 1] or nullptr
+  int n_prob = 1;
+  int G = 1;                          // total blocks
+  int n_tiles = 0;                    // used when the arrays are null (one problem)
+  int tpb_max = 1;                    // largest tile count of one block (sizes the LDS of the operator sweep)
+  const int32_t* blk_prob = nullptr;  // [G] or nullptr
+  const int32_t* blk0 = nullptr;      // [n_prob + 1] or nullptr
+  const int32_t* tile0 = nullptr;     // [n_prob + 1] or nullptr
+  unsigned* done_count = nullptr;     // counts problems that stopped (read by the persistent sweep)
 };
 inline SweepPlan single_plan(int G, int n_tiles) {
   SweepPlan p;
@@ -76,6 +79,7 @@ inline SweepPlan single_plan(int G, int n_tiles) {
   p.blk_prob = nullptr;
   p.blk0 = nullptr;
   p.tile0 = nullptr;
+  p.done_count = nullptr;
   return p;
 }
 
@@ -129,6 +133,18 @@ template <typename T>
 void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* diag,
                    const T* p, const T* q, T* x, T* r, PcgScalars* sc, double* part);
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part);
+// All iterations of all problems in one cooperative launch (grid barrier between
+// sweeps); needs P.done_count, zeroed with bar[0..1] and *abort before the start
+// sweeps.  Returns false if the device cannot run the cooperative launch.
+// *abort becomes 1 if a grid barrier timed out (the launch then returns early).
+int persistent_blocks(const SweepPlan& P);
+template <typename T>
+hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter,
+                                 const T* Cp, const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc,
+                                 double* part, unsigned* bar, int* abort_flag);
+void launch_zero_u32(hipStream_t s, unsigned* p, int n);
+void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, double abs_floor, int max_iter,
+                         int linf_test);
 void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp,
                           const double* diag, const double* b, const double* x, PcgScalars* sc,
                           double* part);

@@ -31,7 +31,8 @@ using dev::apply_stencil;
 using dev::block_plan;
 using dev::block_reduce;
 using dev::BlockPlan;
-using dev::finisher_plan;
+using dev::grid_barrier;
+using dev::problem_blocks;
 using dev::reduce_partials_all;
 
 constexpr int kLds = (kBlock / 64) * 3 + 4;
@@ -65,35 +66,48 @@ __device__ __forceinline__ StopTest stop_test(const PcgScalars* sc, const double
   return s;
 }
 
-__device__ __forceinline__ void record_stop(PcgScalars* sc, const StopTest& s, int it_done) {
+// Marks a problem stopped.  The done counter (which ends the persistent sweep)
+// is only advanced from the start sweeps, the operator sweep and the check, so
+// that every block reads the same count right after a grid barrier; a stop
+// found in the update sweep is counted by the next operator sweep.
+__device__ __forceinline__ void mark_done(PcgScalars* sc, const SweepPlan& P, bool count = true) {
+  sc->done = 1;
+  if (count && P.done_count && !sc->counted) {
+    sc->counted = 1;
+    atomicAdd(P.done_count, 1u);
+  }
+}
+
+__device__ __forceinline__ void record_stop(PcgScalars* sc, const StopTest& s, int it_done, const SweepPlan& P) {
   sc->rnorm = s.rn;
   sc->linf = s.linf;
   sc->iter = it_done;
   if (s.stop) {
     sc->converged = s.conv ? 1 : 0;
     sc->nonfinite = s.fin ? 0 : 1;
-    sc->done = 1;
+    mark_done(sc, P);
   }
 }
 
 template <int NV>
-__device__ __forceinline__ void write_partials(double (&v)[NV], const bool (&mx)[NV], double* dst, double* lds) {
+__device__ __forceinline__ void write_partials(double (&v)[NV], const bool (&mx)[NV], double* dst, double* lds,
+                                               int vb) {
   block_reduce<NV>(v, mx, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) dst[blockIdx.x * NV + k] = v[k];
+    for (int k = 0; k < NV; ++k) dst[vb * NV + k] = v[k];
   }
 }
 
 // r0 = b - A x0, p = 0; partials (r, r / d), ||r||^2, ||b||^2.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, SweepPlan P, const T* __restrict__ Cp,
+__device__ __forceinline__ void body_pcg_init(int vb, DevLevel L, SweepPlan P, const T* __restrict__ Cp,
                                                      const T* __restrict__ diag, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ p_clear, double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
-  const BlockPlan bp = block_plan(P);
+  const BlockPlan bp = block_plan(P, vb);
   double v[3] = {0.0, 0.0, 0.0};
   for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
@@ -112,15 +126,15 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, SweepPlan P, co
     }
   }
   const bool mx[3] = {false, false, false};
-  write_partials<3>(v, mx, part + P.G, lds);
+  write_partials<3>(v, mx, part + P.G, lds, vb);
 }
 
 // One block per problem.  A problem already marked done (the inner solve of a
 // converged problem in the batched refinement) is left as it is.
-__global__ __launch_bounds__(kBlock) void k_init_finish(SweepPlan P, const double* part, PcgScalars* scs) {
+__device__ __forceinline__ void body_init_finish(int prob, SweepPlan P, const double* part, PcgScalars* scs) {
   __shared__ double lds[kLds];
-  int prob, b0, Gp;
-  finisher_plan(P, prob, b0, Gp);
+  int b0, Gp;
+  problem_blocks(P, prob, b0, Gp);
   PcgScalars* sc = scs + prob;
   if (sc->done) return;
   double v[3];
@@ -141,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(SweepPlan P, const doubl
     sc->nonfinite = fin ? 0 : 1;
     // ||r_0|| <= abs_floor ||b||: x_0 is returned after 0 iterations
     sc->converged = (fin && r0 <= floor_b) ? 1 : 0;
-    sc->done = (!fin || r0 <= floor_b) ? 1 : 0;
+    if (!fin || r0 <= floor_b) mark_done(sc, P);
   }
 }
 
@@ -154,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_init_finish(SweepPlan P, const doubl
 // rest recomputed from r, d and p_{it-1} in global memory (the two p buffers
 // alternate, so p_{it-1} is never overwritten during the sweep).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int it,
+__device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int it,
                                                    const T* __restrict__ Cp, const T* __restrict__ diag,
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
                                                    T* __restrict__ p_new, T* __restrict__ q,
@@ -162,9 +176,12 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int 
   __shared__ double lds[kLds];
   extern __shared__ unsigned char dyn_lds[];
   T* pl = reinterpret_cast<T*>(dyn_lds);
-  const BlockPlan bp = block_plan(P);
+  const BlockPlan bp = block_plan(P, vb);
   PcgScalars* sc = scs + bp.prob;
-  if (sc->done) return;
+  if (sc->done) {
+    if (vb == bp.b0 && threadIdx.x == 0) mark_done(sc, P);
+    return;
+  }
   const bool first = it == 1;
   const int n = L.n_slots;
   const int t0 = bp.t0, t1 = bp.t1;
@@ -189,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int 
   double beta = 0.0;
   if (!first) {
     const StopTest s = stop_test(sc, part + P.G + 3 * bp.b0, bp.Gp, it - 1, lds);
-    if (int(blockIdx.x) == bp.b0 && threadIdx.x == 0) {
-      record_stop(sc, s, it - 1);
+    if (vb == bp.b0 && threadIdx.x == 0) {
+      record_stop(sc, s, it - 1, P);
       if (!s.stop) sc->rho[it & 1] = s.rz;
     }
     if (s.stop) return;
@@ -288,18 +305,18 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int 
     }
   }
   const bool mx[1] = {false};
-  write_partials<1>(v, mx, part, lds);
+  write_partials<1>(v, mx, part, lds, vb);
 }
 
 // Update sweep of iteration `it`: alpha = rho / (p, q); x += alpha p; r -= alpha q;
 // partials (r, z), ||r||^2 and max |alpha p| / |x|.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, SweepPlan P, int it,
+__device__ __forceinline__ void body_pass_b(int vb, DevLevel L, SweepPlan P, int it,
                                                    const T* __restrict__ diag, const T* __restrict__ p,
                                                    const T* __restrict__ q, T* __restrict__ x,
                                                    T* __restrict__ r, PcgScalars* scs, double* part) {
   __shared__ double lds[kLds];
-  const BlockPlan bp = block_plan(P);
+  const BlockPlan bp = block_plan(P, vb);
   PcgScalars* sc = scs + bp.prob;
   if (sc->done) return;
   const int n = L.n_slots;
@@ -327,10 +344,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, SweepPlan P, int 
   reduce_partials_all<1>(part + bp.b0, bp.Gp, mx1, pq, lds);
   const double alpha = sc->rho[it & 1] / pq[0];
   if (!isfinite(alpha)) {
-    if (int(blockIdx.x) == bp.b0 && threadIdx.x == 0) {
+    if (vb == bp.b0 && threadIdx.x == 0) {
       sc->nonfinite = 1;
       sc->iter = it - 1;
-      sc->done = 1;
+      mark_done(sc, P, false);
     }
     return;
   }
@@ -361,28 +378,28 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, SweepPlan P, int 
     }
   }
   const bool mx[3] = {false, false, true};
-  write_partials<3>(v, mx, part + P.G, lds);
+  write_partials<3>(v, mx, part + P.G, lds, vb);
 }
 
 // Applies the stopping test after the update sweep of iteration it_last (the
 // test the next operator sweep would make) so that the host sees convergence.
-__global__ __launch_bounds__(kBlock) void k_check(SweepPlan P, int it_last, PcgScalars* scs, const double* part) {
+__device__ __forceinline__ void body_check(int prob, SweepPlan P, int it_last, PcgScalars* scs, const double* part) {
   __shared__ double lds[kLds];
-  int prob, b0, Gp;
-  finisher_plan(P, prob, b0, Gp);
+  int b0, Gp;
+  problem_blocks(P, prob, b0, Gp);
   PcgScalars* sc = scs + prob;
   if (sc->done) return;
   const StopTest s = stop_test(sc, part + P.G + 3 * b0, Gp, it_last, lds);
-  if (threadIdx.x == 0) record_stop(sc, s, it_last);
+  if (threadIdx.x == 0) record_stop(sc, s, it_last, P);
 }
 
-__global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+__device__ __forceinline__ void body_true_residual(int vb, DevLevel L, SweepPlan P, const double* __restrict__ Cp,
                                                           const double* __restrict__ diag,
                                                           const double* __restrict__ b,
                                                           const double* __restrict__ x, double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
-  const BlockPlan bp = block_plan(P);
+  const BlockPlan bp = block_plan(P, vb);
   double v[1] = {0.0};
   for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
@@ -395,15 +412,15 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, SweepPlan 
     }
   }
   const bool mx[1] = {false};
-  write_partials<1>(v, mx, part, lds);
+  write_partials<1>(v, mx, part, lds, vb);
 }
 
 // T update of the coupling term (linearised emission) and smallest leaf energy.
-__global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, const double* __restrict__ E,
+__device__ __forceinline__ void body_post_solve(int vb, DevLevel L, SweepPlan P, const double* __restrict__ E,
                                                        const double* __restrict__ rho, CouplingParams cp,
                                                        double dt, double* __restrict__ T_out, double* part) {
   __shared__ double lds[kLds];
-  const BlockPlan bp = block_plan(P);
+  const BlockPlan bp = block_plan(P, vb);
   double v[1] = {-DBL_MAX};
   for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
@@ -420,14 +437,14 @@ __global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, 
     }
   }
   const bool mx[1] = {true};
-  write_partials<1>(v, mx, part, lds);
+  write_partials<1>(v, mx, part, lds, vb);
 }
 
 // kind 0: true residual norm; kind 1: smallest leaf energy.
-__global__ __launch_bounds__(kBlock) void k_finish(SweepPlan P, int kind, const double* part, PcgScalars* scs) {
+__device__ __forceinline__ void body_finish(int prob, SweepPlan P, int kind, const double* part, PcgScalars* scs) {
   __shared__ double lds[kLds];
-  int prob, b0, Gp;
-  finisher_plan(P, prob, b0, Gp);
+  int b0, Gp;
+  problem_blocks(P, prob, b0, Gp);
   PcgScalars* sc = scs + prob;
   double v[1];
   const bool mx[1] = {kind == 1};
@@ -439,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(SweepPlan P, int kind, const 
 }
 
 // ------------------------------------------------------------ mixed precision
-__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+__device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, const double* __restrict__ Cp,
                                                      const double* __restrict__ diag,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x_old,
@@ -448,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, co
                                                      double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
-  const BlockPlan bp = block_plan(P);
+  const BlockPlan bp = block_plan(P, vb);
   if (outer[bp.prob].done) {  // converged problem: carry its iterate into the new buffer
     for (int i = bp.t0 * kBlock + int(threadIdx.x); i < min(bp.t1 * kBlock, n); i += kBlock) x_new[i] = x_old[i];
     return;
@@ -471,16 +488,16 @@ __global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, co
     }
   }
   const bool mx[3] = {false, false, true};
-  write_partials<3>(v, mx, part + P.G, lds);
+  write_partials<3>(v, mx, part + P.G, lds, vb);
 }
 
 // One block per problem: the outer stopping test, then the inner scalars.  A
 // problem done in an earlier sweep keeps its state and its inner solve is off.
-__global__ __launch_bounds__(kBlock) void k_ir_finish(SweepPlan P, int first, double inner_tol, int inner_max,
+__device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first, double inner_tol, int inner_max,
                                                       PcgScalars* outs, PcgScalars* ins, const double* part) {
   __shared__ double lds[kLds];
-  int prob, b0, Gp;
-  finisher_plan(P, prob, b0, Gp);
+  int b0, Gp;
+  problem_blocks(P, prob, b0, Gp);
   PcgScalars* out = outs + prob;
   PcgScalars* in = ins + prob;
   if (out->done) {
@@ -522,12 +539,12 @@ __global__ __launch_bounds__(kBlock) void k_ir_finish(SweepPlan P, int first, do
   in->iter = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, SweepPlan P, const float* __restrict__ diag32,
+__device__ __forceinline__ void body_inner_init(int vb, DevLevel L, SweepPlan P, const float* __restrict__ diag32,
                                                        const float* __restrict__ r32, float* __restrict__ d,
                                                        float* __restrict__ p_clear, const PcgScalars* outer,
                                                        double* part) {
   __shared__ double lds[kLds];
-  const BlockPlan bp = block_plan(P);
+  const BlockPlan bp = block_plan(P, vb);
   if (outer[bp.prob].done) return;
   double v[3] = {0.0, 0.0, 0.0};
   for (int t = bp.t0; t < bp.t1; ++t) {
@@ -543,7 +560,129 @@ __global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, SweepPlan P, 
     }
   }
   const bool mx[3] = {false, false, false};
-  write_partials<3>(v, mx, part + P.G, lds);
+  write_partials<3>(v, mx, part + P.G, lds, vb);
+}
+
+// ------------------------------------------------------------ kernels
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, SweepPlan P, const T* __restrict__ Cp,
+                                                     const T* __restrict__ diag, const T* __restrict__ b,
+                                                     const T* __restrict__ x, T* __restrict__ r,
+                                                     T* __restrict__ p_clear, double* part) {
+  body_pcg_init<T>(int(blockIdx.x), L, P, Cp, diag, b, x, r, p_clear, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int it,
+                                                   const T* __restrict__ Cp, const T* __restrict__ diag,
+                                                   const T* __restrict__ r, const T* __restrict__ p_old,
+                                                   T* __restrict__ p_new, T* __restrict__ q,
+                                                   PcgScalars* scs, double* part) {
+  body_pass_a<T>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, SweepPlan P, int it,
+                                                   const T* __restrict__ diag, const T* __restrict__ p,
+                                                   const T* __restrict__ q, T* __restrict__ x,
+                                                   T* __restrict__ r, PcgScalars* scs, double* part) {
+  body_pass_b<T>(int(blockIdx.x), L, P, it, diag, p, q, x, r, scs, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+                                                          const double* __restrict__ diag,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ x, double* part) {
+  body_true_residual(int(blockIdx.x), L, P, Cp, diag, b, x, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, const double* __restrict__ E,
+                                                       const double* __restrict__ rho, CouplingParams cp,
+                                                       double dt, double* __restrict__ T_out, double* part) {
+  body_post_solve(int(blockIdx.x), L, P, E, rho, cp, dt, T_out, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+                                                     const double* __restrict__ diag,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ x_old,
+                                                     const float* __restrict__ d, double* __restrict__ x_new,
+                                                     float* __restrict__ r32, const PcgScalars* outer,
+                                                     double* part) {
+  body_ir_sweep(int(blockIdx.x), L, P, Cp, diag, b, x_old, d, x_new, r32, outer, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, SweepPlan P, const float* __restrict__ diag32,
+                                                       const float* __restrict__ r32, float* __restrict__ d,
+                                                       float* __restrict__ p_clear, const PcgScalars* outer,
+                                                       double* part) {
+  body_inner_init(int(blockIdx.x), L, P, diag32, r32, d, p_clear, outer, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_finish(SweepPlan P, const double* part, PcgScalars* scs) {
+  body_init_finish(int(blockIdx.x), P, part, scs);
+}
+
+__global__ __launch_bounds__(kBlock) void k_check(SweepPlan P, int it_last, PcgScalars* scs, const double* part) {
+  body_check(int(blockIdx.x), P, it_last, scs, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish(SweepPlan P, int kind, const double* part, PcgScalars* scs) {
+  body_finish(int(blockIdx.x), P, kind, part, scs);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ir_finish(SweepPlan P, int first, double inner_tol, int inner_max,
+                                                      PcgScalars* outs, PcgScalars* ins, const double* part) {
+  body_ir_finish(int(blockIdx.x), P, first, inner_tol, inner_max, outs, ins, part);
+}
+
+// All PCG iterations of every problem of the plan in one cooperative launch: the
+// G virtual blocks of each sweep are dealt round-robin to the resident blocks,
+// with a grid barrier after each sweep.  The loop ends once every problem has
+// stopped (read right after the barrier that follows the operator sweep, where
+// the stopping tests are made), and in any case after max_iter + 1 operator
+// sweeps.  A barrier that times out sets *abort and the block returns; the
+// others then time out at their next barrier, so the launch always ends.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan P, int max_iter, const T* Cp,
+                                                           const T* diag, T* x, T* r, T* p0, T* p1, T* q,
+                                                           PcgScalars* scs, double* part, unsigned* bar,
+                                                           unsigned spin_limit, int* abort_flag) {
+  const unsigned nb = gridDim.x;
+  for (int it = 1; it <= max_iter + 1; ++it) {
+    T* pn = (it & 1) ? p1 : p0;
+    const T* po = (it & 1) ? p0 : p1;
+    for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
+      body_pass_a<T>(vb, L, P, it, Cp, diag, r, po, pn, q, scs, part);
+    if (!grid_barrier(bar, nb, spin_limit)) {
+      if (threadIdx.x == 0) atomicExch(abort_flag, 1);
+      return;
+    }
+    if (__hip_atomic_load(P.done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= unsigned(P.n_prob)) break;
+    for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
+      body_pass_b<T>(vb, L, P, it, diag, pn, q, x, r, scs, part);
+    if (!grid_barrier(bar, nb, spin_limit)) {
+      if (threadIdx.x == 0) atomicExch(abort_flag, 1);
+      return;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_scalars(PcgScalars* sc, int n, double tol, double abs_floor,
+                                                         int max_iter, int linf_test) {
+  const int i = int(blockIdx.x * kBlock + threadIdx.x);
+  if (i >= n) return;
+  PcgScalars z{};
+  z.tol = tol;
+  z.abs_floor = abs_floor;
+  z.max_iter = max_iter;
+  z.linf_test = linf_test;
+  sc[i] = z;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_u32(unsigned* p, int n) {
+  const int i = int(blockIdx.x * kBlock + threadIdx.x);
+  if (i < n) p[i] = 0u;
 }
 
 }  // namespace
@@ -606,6 +745,56 @@ void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, con
                        const float* r32, float* d, float* p_clear, const PcgScalars* outer, double* part) {
   hipLaunchKernelGGL(k_inner_init, dim3(P.G), dim3(kBlock), 0, s, L, P, diag32, r32, d, p_clear, outer, part);
 }
+
+void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, double abs_floor, int max_iter,
+                         int linf_test) {
+  hipLaunchKernelGGL(k_init_scalars, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, n, tol, abs_floor,
+                     max_iter, linf_test);
+}
+
+void launch_zero_u32(hipStream_t s, unsigned* p, int n) {
+  hipLaunchKernelGGL(k_zero_u32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p, n);
+}
+
+// Resident blocks of the persistent sweep on this device (0 if unknown).
+template <typename T>
+int resident_blocks(const SweepPlan& P) {
+  int dev = 0, cus = 0, per_cu = 0, coop = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_pcg_persistent<T>),
+                                                   kBlock, lds) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+int persistent_blocks(const SweepPlan& P) { return resident_blocks<double>(P); }
+
+template <typename T>
+hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter, const T* Cp,
+                                 const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc, double* part,
+                                 unsigned* bar, int* abort_flag) {
+  const int res = resident_blocks<T>(P);
+  if (res <= 0) return hipErrorNotSupported;
+  const int grid = std::min(P.G, res);
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
+  // bounded barrier wait: ~2^26 polls of ~0.1 us, far above the longest sweep
+  unsigned spin_limit = 1u << 26;
+  DevLevel Lv = L;
+  SweepPlan Pv = P;
+  T* p0 = p[0];
+  T* p1 = p[1];
+  void* args[] = {&Lv, &Pv, &max_iter, (void*)&Cp, (void*)&diag, &x, &r, &p0, &p1, &q, &sc, &part, &bar,
+                  &spin_limit, &abort_flag};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_pcg_persistent<T>), dim3(grid), dim3(kBlock),
+                                    args, unsigned(lds), s);
+}
+
+template hipError_t launch_pcg_persistent<double>(hipStream_t, const DevLevel&, const SweepPlan&, int,
+                                                  const double*, const double*, double*, double*, double* const*,
+                                                  double*, PcgScalars*, double*, unsigned*, int*);
 
 template void launch_pcg_init<double>(hipStream_t, const DevLevel&, const SweepPlan&, const double*,
                                       const double*, const double*, const double*, double*, double*,

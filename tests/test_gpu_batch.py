@@ -120,3 +120,24 @@ def test_batch_rejects_bad_patch():
     with pytest.raises(AmrfldError):
         s.solve(patches, 1, 1e-10)
     s.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_persistent_launch_equals_polled(graph):
+    # one cooperative launch per step (and all steps in one hipGraph) runs the same
+    # sweep bodies over the same block plan: results and counts are bitwise equal
+    patches, alpha = patch_batch(4800, 12, n_min=4, n_max=24)
+    s = _solver(robin_alpha=alpha)
+    a, _ = s.solve(patches, 3, 1e-12)
+    it_a = [x["iters"] for x in s.stats()]
+    s.close()
+    sp = _solver(robin_alpha=alpha, persistent=True, graph=graph)
+    b, st = sp.solve(patches, 3, 1e-12)
+    stats = sp.stats()
+    sp.close()
+    assert {x["launch_mode"] for x in stats} <= {1, 2}
+    if graph:
+        print("launch modes:", {x["launch_mode"] for x in stats})
+    assert [x["iters"] for x in stats] == it_a
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
