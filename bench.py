@@ -102,6 +102,153 @@ def _cpu_baseline(p, budget_s=30.0):
             "seconds": t_solve}
 
 
+def _rel_err(a, b):
+    import numpy as np
+    d = np.abs(a - b)
+    return float(d.max() / max(np.abs(b).max(), 1e-300)), float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _residual_gate(stats, tol, abs_floor=1e-14):
+    """True residuals against the stopping threshold in force, max(tol ||r0||, abs_floor ||b||):
+    the largest ratio (<= 1 means every result meets it; the FP64 stop is on the recursive
+    residual, so its true residual may exceed it by the recursion's rounding drift), the
+    largest ||b - A x|| / ||r0||, and how many solves stopped on the ||b|| floor."""
+    worst, worst_rel, floor = 0.0, 0.0, 0
+    for st in stats:
+        r0, bn = st["rnorm0"], st["bnorm"]
+        thr = max(tol * r0, abs_floor * bn)
+        true = st["true_rel_res"] * r0
+        if thr > 0:
+            worst = max(worst, true / thr)
+        worst_rel = max(worst_rel, st["true_rel_res"])
+        floor += abs_floor * bn > tol * r0
+    return {"max_true_res_over_threshold": worst, "max_true_rel_res": worst_rel, "floor_bound_solves": int(floor),
+            "solves": len(stats)}
+
+
+def _mixed_form(p, s64, init, ms64, args):
+    """The precision form on the same workload: FP32 inner PCG inside FP64 refinement to
+    the same 1e-10 relative residual; error against the FP64 GPU solve of the same step."""
+    import torch
+    from paper_1401_1112_amd import BC_DIRICHLET, MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    s = solver_from_problem(p, precision=MIXED, max_blocks=args.max_blocks)
+
+    def step():
+        for lvl in s.levels:
+            rho, E = init[lvl]
+            s.set_fields(lvl, rho, E, kmode=1)
+        s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+        return s.stats()
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cell_it = sum(st["n_leaf"] * st["iters"] for x in sts for st in x)
+    worst_max, worst_l2 = 0.0, 0.0
+    for lvl in s.levels:
+        a, b = to_numpy(s.E(lvl)), to_numpy(s64.E(lvl))
+        m, l2 = _rel_err(a, b)
+        worst_max, worst_l2 = max(worst_max, m), max(worst_l2, l2)
+    last = sts[-1]
+    out = {"value": cell_it / el, "unit": "inner cell-iterations/s", "ms_per_step": el * 1e3 / args.steps,
+           "speedup_vs_fp64": (ms64 / (el * 1e3 / args.steps)),
+           "inner_iterations_per_step": sum(st["iters"] for st in last),
+           "outer_sweeps_per_step": sum(st["outer_iters"] for st in last),
+           "residual": _residual_gate([st for x in sts for st in x], p.tol),
+           "err_vs_fp64_gpu": {"max_rel": worst_max, "l2_rel": worst_l2},
+           "inner_tol": 1e-4}
+    s.close()
+    return out
+
+
+def _batched_form(args):
+    """The batching form: independent patches with log-uniform sizes 8^3..128^3, own
+    log-normal density, mixed Dirichlet / Neumann / Robin faces, 16 backward-Euler steps,
+    all patches in shared sweeps; against a loop of one-patch launches."""
+    import numpy as np
+    import torch
+    from paper_1401_1112_amd import MIXED
+    from paper_1401_1112_amd.solver import BatchSolver
+    from synth.configs import patch_batch
+    t_gen = time.perf_counter()
+    patches, alpha = patch_batch(4000, args.batch_patches)
+    t_gen = time.perf_counter() - t_gen
+    steps, tol = args.batch_steps, 1e-10
+    cells = sum(int(p.n) ** 3 for p in patches)
+    out = {"workload": f"{len(patches)} patches, n in [{min(p.n for p in patches)}, {max(p.n for p in patches)}], "
+                       f"{cells} cells, {steps} steps, tol 1e-10", "generation_s": round(t_gen, 1)}
+
+    def timed(solver, h, precision):
+        solver.run(h, 1, tol, precision)  # warm-up (layout, allocations)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.run(h, steps, tol, precision)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = solver.stats()
+        ci = sum(x["n_leaf"] * x["iters"] for x in st)
+        return el, ci, st
+
+    from paper_1401_1112_amd import AmrfldError
+    results = {}
+    for name, kw, prec in (("fp64_polled", {}, 0), ("fp64_persistent_graph", {"persistent": True, "graph": True}, 0),
+                           ("mixed_polled", {}, MIXED)):
+        print(f"bench: batched form {name}", file=sys.stderr, flush=True)
+        bs = BatchSolver(robin_alpha=alpha, **kw)
+        h = bs.upload(patches)
+        try:
+            el, ci, st = timed(bs, h, prec)
+        except AmrfldError as e:
+            # report the failing patches instead of dropping the whole line
+            st = bs.stats()
+            bad = [(q, x["status"], x["iters"], x["rel_res"]) for q, x in enumerate(st) if x["status"] != 0]
+            out[name] = {"error": str(e), "n_bad": len(bad), "first_bad": bad[:8]}
+            bs.close()
+            del h
+            torch.cuda.empty_cache()
+            continue
+        results[name] = (bs.result(h), st)
+        out[name] = {"seconds": round(el, 3), "solves_per_s": len(patches) * steps / el,
+                     "cell_iterations_per_s": ci / el,
+                     "residual": _residual_gate(st, tol),
+                     "launch_mode": max(x.get("launch_mode", 0) for x in st)}
+        bs.close()
+        del h
+        torch.cuda.empty_cache()
+    if len(results) < 3:
+        return out
+    # baseline: one patch per launch sequence (each patch its own context, warmed up)
+    singles = []
+    for p in patches:
+        bs = BatchSolver(robin_alpha=alpha)
+        h = bs.upload([p])
+        bs.run(h, 1, tol)
+        singles.append((bs, h))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for bs, h in singles:
+        bs.run(h, steps, tol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    single_res = [bs.result(h)[0] for bs, h in singles]
+    for bs, _ in singles:
+        bs.close()
+    out["fp64_single_patch_loop"] = {"seconds": round(el, 3), "solves_per_s": len(patches) * steps / el}
+    out["batched_speedup_vs_single_loop"] = el / out["fp64_persistent_graph"]["seconds"]
+    a = results["fp64_polled"][0]
+    b = results["fp64_persistent_graph"][0]
+    m = results["mixed_polled"][0]
+    out["persistent_equals_polled_bitwise"] = all(np.array_equal(x, y) for x, y in zip(a, b))
+    out["max_rel_l2_batch_vs_single"] = max(_rel_err(x, y)[1] for x, y in zip(a, single_res))
+    out["mixed_err_vs_fp64_gpu"] = {"max_rel": max(_rel_err(x, y)[0] for x, y in zip(m, a)),
+                                    "l2_rel": max(_rel_err(x, y)[1] for x, y in zip(m, a))}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +259,10 @@ def main(argv=None):
                     help="bracket the two sweeps of every N-th PCG iteration with HIP events (0: off)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--max-blocks", type=int, default=0, help="blocks per PCG sweep (0: library default)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--batch-patches", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=16)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -204,7 +355,14 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    out["forms"] = {}
+    if not args.no_mixed:
+        out["forms"]["mixed"] = _mixed_form(p, s, init, elapsed * 1e3 / args.steps, args)
     s.close()
+    if not args.no_batch:
+        import torch as _t
+        _t.cuda.empty_cache()
+        out["forms"]["batched"] = _batched_form(args)
     if not args.no_cpu_baseline:
         cb = _cpu_baseline(p, args.cpu_budget)
         cb.pop("seconds", None)

@@ -98,6 +98,10 @@ typedef struct {
   double pass_a_ms;      /* summed device time of the timed operator sweeps (pass A) */
   double pass_b_ms;      /* summed device time of the timed update sweeps (pass B) */
   int launch_mode;       /* 0 host-polled sweeps, 1 persistent launch, 2 persistent launches in a hipGraph */
+  double rnorm0;         /* ||r_0|| = ||b - A x_0|| (mixed precision: the first outer residual) */
+  double bnorm;          /* ||b||; the stopping threshold is max(tol ||r_0||, abs_floor ||b||) */
+  int sweep_blocks;      /* blocks (256-slot tile ranges) of every PCG sweep */
+  int launch_blocks;     /* blocks of the launch that runs them (fewer for a persistent launch) */
 } amrfld_stats;
 
 /* Fill *o with the defaults listed above. */

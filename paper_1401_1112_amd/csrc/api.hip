@@ -533,6 +533,10 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   st.linf_change = h.linf;
   st.min_E = h.min_E;
   st.dt = dt;
+  st.rnorm0 = h.rnorm0;
+  st.bnorm = h.bnorm;
+  st.sweep_blocks = P.G;
+  st.launch_blocks = P.G;
   float ms = 0.f, pms = 0.f;
   check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
   check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
@@ -770,6 +774,10 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       st.ms = total_ms / n_steps;
       st.pcg_ms = -1.0;
       st.launch_mode = mode;
+      st.rnorm0 = h.rnorm0;
+      st.bnorm = h.bnorm;
+      st.sweep_blocks = P.G;
+      st.launch_blocks = std::min(P.G, persistent_blocks(P));
       st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
       if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
         worst = amrfld_status(st.status);
@@ -876,6 +884,10 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
       st.n_timed = ls.n_timed;
       st.pass_a_ms = ls.a_ms;
       st.pass_b_ms = ls.b_ms;
+      st.rnorm0 = h.rnorm0;
+      st.bnorm = h.bnorm;
+      st.sweep_blocks = P.G;
+      st.launch_blocks = P.G;
       st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
       if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
         worst = amrfld_status(st.status);

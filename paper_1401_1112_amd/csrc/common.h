@@ -129,13 +129,30 @@ __device__ __forceinline__ void problem_blocks(const SweepPlan& P, int prob, int
   Gp = P.blk0 ? P.blk0[prob + 1] - b0 : P.G;
 }
 
-// Grid-wide barrier of a cooperative launch (all blocks resident).  Thread 0 of
-// each block releases the block's writes (agent-scope fence), arrives on a
-// counter, and waits for the generation to move; the last arrival resets the
-// counter and moves the generation.  The wait is bounded: after spin_limit
-// polls the block reports failure instead of waiting forever.
+// A flag that another block may set while this block runs, read once for the
+// whole block.  Waves that each read it at a different moment could see
+// different values and take different paths around the block barriers that
+// follow; in a persistent launch (waves that return go on to the next virtual
+// block) that would pair unrelated barriers.
+__device__ __forceinline__ bool block_read_flag(const int* f) {
+  __shared__ int v;
+  if (threadIdx.x == 0) v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const bool r = v != 0;
+  __syncthreads();
+  return r;
+}
+
+// Grid-wide barrier of a cooperative launch (all blocks resident).  Every wave
+// first waits until its own stores have reached its XCD's L2 (a block barrier
+// alone does not wait for them), then thread 0 releases the block's writes to
+// the other XCDs (agent-scope fence: L2 write-back), arrives on a counter and
+// waits for the generation to move; the last arrival resets the counter and
+// moves the generation.  The wait is bounded: after spin_limit polls the block
+// reports failure instead of waiting forever.
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned n_blocks, unsigned spin_limit) {
   __shared__ int ok;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);

@@ -29,6 +29,7 @@ namespace {
 
 using dev::apply_stencil;
 using dev::block_plan;
+using dev::block_read_flag;
 using dev::block_reduce;
 using dev::BlockPlan;
 using dev::grid_barrier;
@@ -178,7 +179,8 @@ __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int
   T* pl = reinterpret_cast<T*>(dyn_lds);
   const BlockPlan bp = block_plan(P, vb);
   PcgScalars* sc = scs + bp.prob;
-  if (sc->done) {
+  // the problem's first block may set `done` during this sweep
+  if (block_read_flag(&sc->done)) {
     if (vb == bp.b0 && threadIdx.x == 0) mark_done(sc, P);
     return;
   }
@@ -318,7 +320,7 @@ __device__ __forceinline__ void body_pass_b(int vb, DevLevel L, SweepPlan P, int
   __shared__ double lds[kLds];
   const BlockPlan bp = block_plan(P, vb);
   PcgScalars* sc = scs + bp.prob;
-  if (sc->done) return;
+  if (block_read_flag(&sc->done)) return;
   const int n = L.n_slots;
   const int t0 = bp.t0, t1 = bp.t1;
   const int s1 = min(t1 * kBlock, n);

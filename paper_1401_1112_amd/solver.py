@@ -171,11 +171,8 @@ class BatchSolver:
         except Exception:
             pass
 
-    def solve(self, patches, n_steps, tol, precision=L.FP64, kmode=L.K_LP, kappa_R=1.0, c_light=1.0,
-              K_const=1.0, raise_on_error=True):
-        """patches: objects with n, dx, dt, rho, E ([i, j, k] arrays), face_mode, face_ghost,
-        face_flux.  Returns the final energies as a list of (n, n, n) [i, j, k] arrays and the
-        status."""
+    def upload(self, patches, kmode=L.K_LP, kappa_R=1.0, c_light=1.0, K_const=1.0):
+        """Copy the patches' fields to the device once; returns a handle for run()."""
         keep, structs, offs = [], [], [0]
         for p in patches:
             n = int(p.n)
@@ -195,15 +192,33 @@ class BatchSolver:
             structs.append(st)
             offs.append(offs[-1] + n ** 3)
         out = torch.empty(offs[-1], dtype=torch.float64, device=self.device)
-        status = L.amrfld_solve_batch(self.ctx, structs, n_steps, tol, precision, out)
+        return {"keep": keep, "structs": structs, "offs": offs, "out": out,
+                "sizes": [int(p.n) for p in patches]}
+
+    def run(self, h, n_steps, tol, precision=L.FP64, raise_on_error=True):
+        status = L.amrfld_solve_batch(self.ctx, h["structs"], n_steps, tol, precision, h["out"])
         if raise_on_error and status != L.OK:
             raise L.AmrfldError(status, L.amrfld_last_error(self.ctx))
-        host = out.cpu().numpy()
+        return status
+
+    def result(self, h):
+        host = h["out"].cpu().numpy()
         res = []
-        for q, p in enumerate(patches):
-            n = int(p.n)
-            res.append(host[offs[q]:offs[q + 1]].reshape(n, n, n).transpose(2, 1, 0).copy())
-        return res, status
+        for q, n in enumerate(h["sizes"]):
+            res.append(host[h["offs"][q]:h["offs"][q + 1]].reshape(n, n, n).transpose(2, 1, 0).copy())
+        return res
+
+    def solve(self, patches, n_steps, tol, precision=L.FP64, kmode=L.K_LP, kappa_R=1.0, c_light=1.0,
+              K_const=1.0, raise_on_error=True):
+        """patches: objects with n, dx, dt, rho, E ([i, j, k] arrays), face_mode, face_ghost,
+        face_flux.  Returns the final energies as a list of (n, n, n) [i, j, k] arrays and the
+        status."""
+        h = self.upload(patches, kmode, kappa_R, c_light, K_const)
+        status = self.run(h, n_steps, tol, precision, raise_on_error)
+        return self.result(h), status
 
     def stats(self):
         return L.amrfld_last_stats(self.ctx)
+
+    def last_error(self):
+        return L.amrfld_last_error(self.ctx)

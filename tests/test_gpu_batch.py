@@ -122,11 +122,16 @@ def test_batch_rejects_bad_patch():
     s.close()
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_persistent_launch_equals_polled(graph):
+@pytest.mark.parametrize("graph,big", [(False, False), (True, False), (False, True), (True, True)])
+def test_batch_persistent_launch_equals_polled(graph, big):
     # one cooperative launch per step (and all steps in one hipGraph) runs the same
-    # sweep bodies over the same block plan: results and counts are bitwise equal
-    patches, alpha = patch_batch(4800, 12, n_min=4, n_max=24)
+    # sweep bodies over the same block plan: results and counts are bitwise equal.
+    # The big case spreads each patch over many blocks of up to 16 tiles, so the
+    # grid barrier must make neighbour values visible across XCDs.
+    if big:
+        patches, alpha = patch_batch(4900, 48, n_min=24, n_max=96)
+    else:
+        patches, alpha = patch_batch(4800, 12, n_min=4, n_max=24)
     s = _solver(robin_alpha=alpha)
     a, _ = s.solve(patches, 3, 1e-12)
     it_a = [x["iters"] for x in s.stats()]
