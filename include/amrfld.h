@@ -81,6 +81,7 @@ typedef struct {
   int persistent;        /* batch form: 1 = all PCG iterations of a step in one cooperative launch */
   int graph;             /* batch form with persistent: 1 = capture all steps in one hipGraph */
   void* stream;          /* hipStream_t */
+  int persistent_per_cu; /* persistent launch: resident blocks per compute unit (0 = as many as fit) */
 } amrfld_opts;
 
 typedef struct {

@@ -32,6 +32,7 @@ class amrfld_opts(ctypes.Structure):
         ("true_residual", ctypes.c_int), ("time_sweeps", ctypes.c_int),
         ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_blocks", ctypes.c_int),
         ("persistent", ctypes.c_int), ("graph", ctypes.c_int), ("stream", ctypes.c_void_p),
+        ("persistent_per_cu", ctypes.c_int),
     ]
 
 

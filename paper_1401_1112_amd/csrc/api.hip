@@ -687,27 +687,28 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
   const int np = B.n_prob;
   const DevLevel D = B.dev();
   SweepPlan P = B.plan();
-  if (!c->bar) c->bar = dalloc<unsigned>(4, "barrier");
-  P.done_count = c->bar + 2;
-  int* abort_flag = reinterpret_cast<int*>(c->bar + 3);
-  if (persistent_blocks(P) <= 0) return AMRFLD_E_STATE;
+  if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
+  P.done_count = c->bar + kBarDone;
+  const unsigned* abort_flag = c->bar + kBarAbort;
+  const int per_cu = c->o.persistent_per_cu;
+  if (persistent_blocks(P, per_cu) <= 0) return AMRFLD_E_STATE;
   ensure_scalars(c, n_steps * np);
   CouplingParams cp{};
   cp.T = nullptr;
   const CellKParams kp{1, 1.0, 1.0, 1.0};
   auto record = [&](hipStream_t st) -> hipError_t {
-    launch_zero_u32(st, c->bar + 3, 1);
+    launch_zero_u32(st, c->bar, kBarWords);
     for (int step = 0; step < n_steps; ++step) {
       PcgScalars* sc = c->sc + int64_t(step) * np;
       launch_cell_K(st, D, B.E, B.rho, nullptr, kp, B.K);
       launch_assemble(st, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, B.Cp,
                       B.diag, B.b);
       launch_init_scalars(st, sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
-      launch_zero_u32(st, c->bar, 3);
+      launch_zero_u32(st, c->bar, kBarAbort);
       launch_pcg_init<double>(st, D, P, B.Cp, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
       launch_init_finish(st, P, c->partials, sc);
       const hipError_t e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, B.Cp, B.diag, B.E, c->r, c->p,
-                                                         c->q, sc, c->partials, c->bar, abort_flag);
+                                                         c->q, sc, c->partials, c->bar, per_cu);
       if (e != hipSuccess) return e;
       if (c->o.true_residual) launch_true_residual(st, D, P, B.Cp, B.diag, B.b, B.E, sc, c->partials);
       launch_post_solve(st, D, P, B.E, B.rho, cp, 0.0, nullptr, sc, c->partials);
@@ -753,8 +754,8 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
     check(hipStreamSynchronize(us), "sync");
     check(hipEventElapsedTime(&total_ms, c->ev[0], c->ev[3]), "event");
   }
-  int aborted = 0;
-  check(hipMemcpy(&aborted, abort_flag, sizeof(int), hipMemcpyDeviceToHost), "abort flag");
+  unsigned aborted = 0;
+  check(hipMemcpy(&aborted, abort_flag, sizeof(unsigned), hipMemcpyDeviceToHost), "abort flag");
   read_scalars(c, c->h_sc, c->sc, n_steps * np);
   amrfld_status worst = AMRFLD_OK;
   std::string worst_msg;
@@ -777,7 +778,7 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       st.rnorm0 = h.rnorm0;
       st.bnorm = h.bnorm;
       st.sweep_blocks = P.G;
-      st.launch_blocks = std::min(P.G, persistent_blocks(P));
+      st.launch_blocks = persistent_blocks(P, per_cu);
       st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
       if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
         worst = amrfld_status(st.status);

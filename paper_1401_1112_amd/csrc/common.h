@@ -143,36 +143,41 @@ __device__ __forceinline__ bool block_read_flag(const int* f) {
   return r;
 }
 
-// Grid-wide barrier of a cooperative launch (all blocks resident).  Every wave
-// first waits until its own stores have reached its XCD's L2 (a block barrier
-// alone does not wait for them), then thread 0 releases the block's writes to
-// the other XCDs (agent-scope fence: L2 write-back), arrives on a counter and
-// waits for the generation to move; the last arrival resets the counter and
-// moves the generation.  The wait is bounded: after spin_limit polls the block
-// reports failure instead of waiting forever.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned n_blocks, unsigned spin_limit) {
+// Grid-wide barrier of a cooperative launch (all blocks resident).  The words
+// live at bar[kBarArrive] (arrivals, only ever incremented) and bar[kBarRelease]
+// (barriers completed), on separate 256-byte lines, both zero at the launch.
+// Every wave first waits until its own stores have reached its XCD's L2 (a
+// block barrier alone does not wait for them); thread 0 then releases the
+// block's writes to the other XCDs (agent-scope release fence: one L2
+// write-back) and arrives.  The block that completes barrier number `epoch`
+// (arrivals reach epoch * n_blocks) acquires the others' writes and publishes
+// the epoch; the rest poll the release word with plain atomic loads and acquire
+// once it moves.  The wait is bounded: after spin_limit polls the block reports
+// failure instead of waiting forever.  `epoch` counts this block's barriers.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned n_blocks, unsigned& epoch,
+                                             unsigned spin_limit) {
   __shared__ int ok;
+  ++epoch;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned old = __hip_atomic_fetch_add(bar + kBarArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int good = 1;
-    if (arrived == n_blocks - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u == epoch * n_blocks) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_store(bar + kBarRelease, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned polls = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(bar + kBarRelease, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
         __builtin_amdgcn_s_sleep(2);
         if (++polls > spin_limit) {
           good = 0;
           break;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __threadfence();
     ok = good;
   }
   __syncthreads();

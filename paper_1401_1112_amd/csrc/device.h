@@ -10,6 +10,12 @@ namespace amrfld {
 constexpr int kBlock = 256;  // threads per block = slots per tile
 constexpr int kMaxTilesPerBlock = 16;
 
+// Words of the persistent launch's control buffer (unsigned), each on its own
+// 256-byte line: grid-barrier arrivals and releases, the count of problems that
+// stopped, and the abort flag.  The first kBarAbort words are zeroed before
+// every persistent launch.
+constexpr int kBarArrive = 0, kBarRelease = 64, kBarDone = 128, kBarAbort = 192, kBarWords = 256;
+
 // Scalars of one PCG solve in device memory.  The sweeps derive alpha, beta and
 // the stopping decision themselves from the previous sweep's block partials;
 // the host reads this record only between batches of iterations.
@@ -134,14 +140,16 @@ void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it,
                    const T* p, const T* q, T* x, T* r, PcgScalars* sc, double* part);
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part);
 // All iterations of all problems in one cooperative launch (grid barrier between
-// sweeps); needs P.done_count, zeroed with bar[0..1] and *abort before the start
-// sweeps.  Returns false if the device cannot run the cooperative launch.
-// *abort becomes 1 if a grid barrier timed out (the launch then returns early).
-int persistent_blocks(const SweepPlan& P);
+// sweeps); bar is the control buffer (kBarWords), P.done_count = bar + kBarDone;
+// its first kBarAbort words are zeroed before the start sweeps.  Returns an
+// error if the device cannot run the cooperative launch.  bar[kBarAbort]
+// becomes 1 if a grid barrier timed out (the launch then returns early).
+// per_cu_cap > 0 limits the resident blocks per compute unit (fewer barrier arrivals).
+int persistent_blocks(const SweepPlan& P, int per_cu_cap);
 template <typename T>
 hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter,
                                  const T* Cp, const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc,
-                                 double* part, unsigned* bar, int* abort_flag);
+                                 double* part, unsigned* bar, int per_cu_cap);
 void launch_zero_u32(hipStream_t s, unsigned* p, int n);
 void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, double abs_floor, int max_iter,
                          int linf_test);

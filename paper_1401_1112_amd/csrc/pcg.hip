@@ -649,22 +649,28 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan P, int max_iter, const T* Cp,
                                                            const T* diag, T* x, T* r, T* p0, T* p1, T* q,
                                                            PcgScalars* scs, double* part, unsigned* bar,
-                                                           unsigned spin_limit, int* abort_flag) {
+                                                           unsigned spin_limit) {
+  __shared__ unsigned n_done;
   const unsigned nb = gridDim.x;
+  unsigned epoch = 0;
   for (int it = 1; it <= max_iter + 1; ++it) {
     T* pn = (it & 1) ? p1 : p0;
     const T* po = (it & 1) ? p0 : p1;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
       body_pass_a<T>(vb, L, P, it, Cp, diag, r, po, pn, q, scs, part);
-    if (!grid_barrier(bar, nb, spin_limit)) {
-      if (threadIdx.x == 0) atomicExch(abort_flag, 1);
+    if (!grid_barrier(bar, nb, epoch, spin_limit)) {
+      if (threadIdx.x == 0) __hip_atomic_store(bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    if (__hip_atomic_load(P.done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= unsigned(P.n_prob)) break;
+    // stops are counted only in the operator sweep, so the count is the same for
+    // every block between this barrier and the next
+    if (threadIdx.x == 0) n_done = __hip_atomic_load(P.done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (n_done >= unsigned(P.n_prob)) break;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
       body_pass_b<T>(vb, L, P, it, diag, pn, q, x, r, scs, part);
-    if (!grid_barrier(bar, nb, spin_limit)) {
-      if (threadIdx.x == 0) atomicExch(abort_flag, 1);
+    if (!grid_barrier(bar, nb, epoch, spin_limit)) {
+      if (threadIdx.x == 0) __hip_atomic_store(bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
   }
@@ -760,7 +766,7 @@ void launch_zero_u32(hipStream_t s, unsigned* p, int n) {
 
 // Resident blocks of the persistent sweep on this device (0 if unknown).
 template <typename T>
-int resident_blocks(const SweepPlan& P) {
+int resident_blocks(const SweepPlan& P, int per_cu_cap) {
   int dev = 0, cus = 0, per_cu = 0, coop = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
@@ -769,16 +775,20 @@ int resident_blocks(const SweepPlan& P) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_pcg_persistent<T>),
                                                    kBlock, lds) != hipSuccess)
     return 0;
+  if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
   return per_cu * cus;
 }
 
-int persistent_blocks(const SweepPlan& P) { return resident_blocks<double>(P); }
+int persistent_blocks(const SweepPlan& P, int per_cu_cap) {
+  const int res = resident_blocks<double>(P, per_cu_cap);
+  return res > 0 ? std::min(P.G, res) : 0;
+}
 
 template <typename T>
 hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter, const T* Cp,
                                  const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc, double* part,
-                                 unsigned* bar, int* abort_flag) {
-  const int res = resident_blocks<T>(P);
+                                 unsigned* bar, int per_cu_cap) {
+  const int res = resident_blocks<T>(P, per_cu_cap);
   if (res <= 0) return hipErrorNotSupported;
   const int grid = std::min(P.G, res);
   const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
@@ -789,14 +799,14 @@ hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPl
   T* p0 = p[0];
   T* p1 = p[1];
   void* args[] = {&Lv, &Pv, &max_iter, (void*)&Cp, (void*)&diag, &x, &r, &p0, &p1, &q, &sc, &part, &bar,
-                  &spin_limit, &abort_flag};
+                  &spin_limit};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_pcg_persistent<T>), dim3(grid), dim3(kBlock),
                                     args, unsigned(lds), s);
 }
 
 template hipError_t launch_pcg_persistent<double>(hipStream_t, const DevLevel&, const SweepPlan&, int,
                                                   const double*, const double*, double*, double*, double* const*,
-                                                  double*, PcgScalars*, double*, unsigned*, int*);
+                                                  double*, PcgScalars*, double*, unsigned*, int);
 
 template void launch_pcg_init<double>(hipStream_t, const DevLevel&, const SweepPlan&, const double*,
                                       const double*, const double*, const double*, double*, double*,

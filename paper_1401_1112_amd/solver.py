@@ -139,7 +139,8 @@ class BatchSolver:
 
     def __init__(self, *, robin_alpha=0.5, max_iter=10000, linf_test=True, abs_floor=1e-14,
                  inner_tol=1e-4, max_outer=30, max_blocks=0, time_sweeps=0, true_residual=True,
-                 check_every=0, persistent=False, graph=False, device="cuda:0", stream=None):
+                 check_every=0, persistent=False, graph=False, persistent_per_cu=0, device="cuda:0",
+                 stream=None):
         L.load()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -157,6 +158,7 @@ class BatchSolver:
         o.check_every = int(check_every)
         o.persistent = int(bool(persistent))
         o.graph = int(bool(graph))
+        o.persistent_per_cu = int(persistent_per_cu)
         o.stream = self.stream.cuda_stream
         self.ctx = L.amrfld_create(o)
 
