@@ -4,6 +4,9 @@
 device-to-device copy of a known size, whose FETCH_SIZE / WRITE_SIZE readings
 calibrate the per-dispatch HBM byte counters of the solver kernels.
 
+``python -m paper_1401_1112_amd.profiling batch --patches 512 --steps 2 --mode polled``
+runs the batched workload alone (for kernel traces of the batch form).
+
 ``python -m paper_1401_1112_amd.profiling summarize DIR`` prints a per-kernel
 summary (count, average duration, and the averages of any counters) from the
 CSV files rocprofv3 writes with ``--output-format csv``.
@@ -27,6 +30,33 @@ def run_copy(mib: int, reps: int) -> None:
         b.copy_(a)
     torch.cuda.synchronize()
     print(f"copied {mib} MiB x {reps}", flush=True)
+
+
+def run_batch(patches: int, steps: int, mode: str, per_cu: int) -> None:
+    """The batched workload (seeded patches, n in [8, 128]) for one warm-up step and
+    `steps` timed steps, host-polled or as persistent launches (optionally in a graph)."""
+    import time
+
+    import torch
+
+    from synth.configs import patch_batch
+
+    from .solver import BatchSolver
+    ps, alpha = patch_batch(4000, patches)
+    kw = {} if mode == "polled" else {"persistent": True, "graph": mode == "graph", "persistent_per_cu": per_cu}
+    bs = BatchSolver(robin_alpha=alpha, **kw)
+    h = bs.upload(ps)
+    bs.run(h, 1, 1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs.run(h, steps, 1e-10)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = bs.stats()
+    ci = sum(x["n_leaf"] * x["iters"] for x in st)
+    print(f"batch {mode}: {patches} patches, {steps} steps in {el:.3f} s, {ci / el:.3e} cell-iterations/s, "
+          f"{st[0]['sweep_blocks']} sweep blocks, {st[0]['launch_blocks']} launch blocks", flush=True)
+    bs.close()
 
 
 def _short(name: str) -> str:
@@ -78,9 +108,16 @@ def main(argv=None):
     c.add_argument("--reps", type=int, default=4)
     s = sub.add_parser("summarize")
     s.add_argument("dir")
+    b = sub.add_parser("batch")
+    b.add_argument("--patches", type=int, default=512)
+    b.add_argument("--steps", type=int, default=2)
+    b.add_argument("--mode", choices=("polled", "persistent", "graph"), default="polled")
+    b.add_argument("--per-cu", type=int, default=0)
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         run_copy(a.mib, a.reps)
+    elif a.cmd == "batch":
+        run_batch(a.patches, a.steps, a.mode, a.per_cu)
     else:
         print(summarize(a.dir))
     return 0
