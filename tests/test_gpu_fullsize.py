@@ -1,0 +1,141 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py times.
+
+* fld_lognormal (levels 6..9, 4,012,144 cells): one coarse step (15 level solves) on the
+  GPU and in the oracle; with equal iteration counts every level agrees to 1e-12 relative
+  L2.  A near-tie of a residual with its stopping threshold (the two sides sum in different
+  orders) may move one solve by one iteration; then the step is gated at the bound that
+  both stopping tests guarantee (1e-9).
+* the mixed-precision form of the same step: every solve meets its threshold, checked on
+  the FP64 true residual, and the result agrees with the FP64 solve.
+* the 512-patch batch: one step of all patches in shared sweeps; a seeded sample of patches
+  (the smallest and the largest among them) against the patch oracle, every patch's true
+  residual against its threshold, and the persistent launch bitwise equal to the polled one.
+"""
+import numpy as np
+import pytest
+
+from _util import align, oracle_from_problem
+import oracle as ora
+from oracle.patch_oracle import patch_advance
+from synth.configs import config_fld_lognormal, patch_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def lognormal():
+    return config_fld_lognormal()
+
+
+@pytest.fixture(scope="module")
+def fp64_step(lognormal):
+    """One coarse step on the GPU (FP64, default launch shape) and in the oracle."""
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    p = lognormal
+    s = solver_from_problem(p)
+    s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+    gpu = {l: (to_numpy(s.E(l)), s.cells(l)) for l in p.hierarchy.levels}
+    counts_g = [(st["level"], st["iters"]) for st in s.stats()]
+    stats_g = s.stats()
+    s.close()
+    o = oracle_from_problem(p)
+    o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, p.tol)
+    counts_o = [(h["level"], h["iters"]) for h in o.history]
+    return gpu, o, counts_g, counts_o, stats_g
+
+
+def test_lognormal_full_step_parity(lognormal, fp64_step):
+    gpu, o, counts_g, counts_o, _ = fp64_step
+    assert [l for l, _ in counts_g] == [l for l, _ in counts_o]
+    diff = [(i, g, h) for i, ((_, g), (_, h)) in enumerate(zip(counts_g, counts_o)) if g != h]
+    worst = 0.0
+    for l in lognormal.hierarchy.levels:
+        e, cells = gpu[l]
+        ref = align(l, o.cells(l), o.E[l], cells)
+        worst = max(worst, _rel(e, ref))
+    print(f"iteration counts {counts_g}; differing solves {diff}; worst relative L2 {worst:.3e}")
+    if not diff:
+        assert worst <= 1e-12
+    else:
+        assert len(diff) <= 2 and all(abs(g - h) <= 1 for _, g, h in diff), diff
+        assert worst <= 1e-9
+
+
+def test_lognormal_full_step_residuals(lognormal, fp64_step):
+    # every FP64 solve of the step meets its threshold on the true residual, up to the
+    # recursion's rounding drift
+    _, _, _, _, stats = fp64_step
+    for st in stats:
+        thr = max(lognormal.tol * st["rnorm0"], lognormal.abs_floor * st["bnorm"])
+        assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= 1.05 * thr, st
+
+
+def test_lognormal_mixed_full_step(lognormal, fp64_step):
+    from paper_1401_1112_amd import BC_DIRICHLET, MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    gpu, _, _, _, _ = fp64_step
+    p = lognormal
+    s = solver_from_problem(p, precision=MIXED)
+    s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+    for st in s.stats():
+        thr = max(p.tol * st["rnorm0"], p.abs_floor * st["bnorm"])
+        assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= thr * (1 + 1e-12), st
+    for l in p.hierarchy.levels:
+        e, cells = gpu[l]
+        assert np.array_equal(s.cells(l), cells)
+        assert _rel(to_numpy(s.E(l)), e) <= 1e-8
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def batch512():
+    return patch_batch(4000, 512)
+
+
+def test_patch_batch_full_size_sampled(batch512):
+    from paper_1401_1112_amd.solver import BatchSolver
+    patches, alpha = batch512
+    bs = BatchSolver(robin_alpha=alpha)
+    h = bs.upload(patches)
+    bs.run(h, 1, 1e-10)
+    res = bs.result(h)
+    st = bs.stats()
+    bs.close()
+    for q, x in enumerate(st):
+        thr = max(1e-10 * x["rnorm0"], 1e-14 * x["bnorm"])
+        assert x["converged"] == 1 and x["true_rel_res"] * x["rnorm0"] <= 1.05 * thr, (q, x)
+    sizes = np.array([p.n for p in patches])
+    rng = np.random.default_rng(512)
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))}
+                    | set(int(i) for i in rng.choice(len(patches), 4, replace=False)))
+    for q in sample:
+        p = patches[q]
+        e, hist = patch_advance(p.rho, p.E, p.dx, p.dt, p.face_mode, p.face_ghost, p.face_flux, 1, 1e-10,
+                                alpha=alpha)
+        r = _rel(res[q], e)
+        print(f"patch {q} n={p.n}: iterations gpu {st[q]['iters']} oracle {hist[0]['iters']}, rel L2 {r:.3e}")
+        if st[q]["iters"] == hist[0]["iters"]:
+            assert r <= 1e-12
+        else:
+            assert abs(st[q]["iters"] - hist[0]["iters"]) <= 1 and r <= 1e-9
+
+
+def test_patch_batch_full_size_persistent_bitwise(batch512):
+    from paper_1401_1112_amd.solver import BatchSolver
+    patches, alpha = batch512
+    out = []
+    for kw in ({}, {"persistent": True, "graph": True}):
+        bs = BatchSolver(robin_alpha=alpha, **kw)
+        h = bs.upload(patches)
+        bs.run(h, 2, 1e-10)
+        out.append((bs.result(h), [x["iters"] for x in bs.stats()], max(x["launch_mode"] for x in bs.stats())))
+        bs.close()
+    (a, ia, _), (b, ib, mode) = out
+    assert mode in (1, 2)
+    assert ia == ib
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
