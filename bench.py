@@ -205,9 +205,24 @@ def _batched_form(args):
         return el, ci, st
 
     from paper_1401_1112_amd import AmrfldError
+    forms = [("fp64_polled", {}, 0), ("fp64_persistent_graph", {"persistent": True, "graph": True}, 0),
+             ("mixed_polled", {}, MIXED)]
+    if not args.no_tune:
+        # launch shape of the FP64 batch: host-polled, or a persistent launch with its
+        # resident blocks per compute unit, each timed on one step
+        from paper_1401_1112_amd.autotune import tune_batch
+        print("bench: tuning the batch launch shape", file=sys.stderr, flush=True)
+        bs = BatchSolver(robin_alpha=alpha, graph=True)
+        h = bs.upload(patches)
+        best, times, cached = tune_batch(bs, lambda: bs.run(h, 1, tol), [p.n for p in patches], 0)
+        bs.close()
+        del h
+        torch.cuda.empty_cache()
+        out["tuned_shape"] = {"best": best, "from_cache": cached, "candidate_ms_per_step": times}
+        forms.append(("fp64_tuned", {"persistent": bool(best["persistent"]), "graph": True,
+                                     "persistent_per_cu": best["persistent_per_cu"]}, 0))
     results = {}
-    for name, kw, prec in (("fp64_polled", {}, 0), ("fp64_persistent_graph", {"persistent": True, "graph": True}, 0),
-                           ("mixed_polled", {}, MIXED)):
+    for name, kw, prec in forms:
         print(f"bench: batched form {name}", file=sys.stderr, flush=True)
         bs = BatchSolver(robin_alpha=alpha, **kw)
         h = bs.upload(patches)
@@ -230,7 +245,7 @@ def _batched_form(args):
         bs.close()
         del h
         torch.cuda.empty_cache()
-    if len(results) < 3:
+    if len(results) < len(forms):
         return out
     # baseline: one patch per launch sequence (each patch its own context, warmed up)
     singles = []
@@ -249,8 +264,7 @@ def _batched_form(args):
     for bs, _ in singles:
         bs.close()
     out["fp64_single_patch_loop"] = {"seconds": round(el, 3), "solves_per_s": len(patches) * steps / el}
-    out["batched_speedup_vs_single_loop"] = {"fp64_polled": el / out["fp64_polled"]["seconds"],
-                                              "fp64_persistent_graph": el / out["fp64_persistent_graph"]["seconds"]}
+    out["batched_speedup_vs_single_loop"] = {k: el / out[k]["seconds"] for k, _, prec in forms if prec == 0}
     a = results["fp64_polled"][0]
     b = results["fp64_persistent_graph"][0]
     m = results["mixed_polled"][0]
@@ -275,6 +289,8 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-patches", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=16)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape autotuner (level solves: --max-blocks or the default)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -303,6 +319,13 @@ def main(argv=None):
         s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
         return s.stats()
 
+    launch = {"max_blocks": args.max_blocks, "tuned": False}
+    if not args.no_tune and args.max_blocks == 0:
+        from paper_1401_1112_amd.autotune import tune_levels
+        best, times, cached = tune_levels(s, one_step, [s.info(l)[0] for l in s.levels], 0)
+        args.max_blocks = best["max_blocks"]
+        launch = {"max_blocks": args.max_blocks, "tuned": True, "from_cache": cached,
+                  "candidate_ms_per_step": times}
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -364,6 +387,7 @@ def main(argv=None):
         "pcg_only_cell_it_per_s": cell_it / (pcg_ms * 1e-3) if pcg_ms > 0 else None,
         "device_solve_ms_per_step": solve_ms / args.steps,
         "generation_s": round(t_gen, 1),
+        "launch": launch,
         "roofline": roofline,
         "cpu_baseline": None,
     }

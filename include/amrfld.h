@@ -195,6 +195,16 @@ amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double
  * Writes min(max_n, count) entries to out and the count to *n. */
 amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_n, int* n);
 
+/* Launch shape of the PCG sweeps for the following calls on this context; not a
+ * step of the method (the same sweeps, dealt differently to the GPU), used to
+ * time candidate shapes on the device.  max_blocks: blocks per sweep (0 = 1024;
+ * each block sweeps a contiguous range of at most 16 tiles of 256 slots);
+ * persistent, persistent_per_cu: as in amrfld_opts.  Negative values are
+ * rejected with AMRFLD_E_INVALID and change nothing.  Results of one shape are
+ * bitwise reproducible; between shapes the block partials are summed in other
+ * groupings, so they may differ in the last bits. */
+amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, int persistent_per_cu);
+
 /* Message of the last failure on this context ("" if none). */
 const char* amrfld_last_error(const amrfld_ctx* c);
 

@@ -1,0 +1,119 @@
+"""Launch-shape autotuning of the PCG sweeps.
+
+Candidate shapes are timed on the device (events on the solver's stream, median of a
+few runs after a warm-up run) and the fastest is kept in a JSON cache keyed by the
+device and a signature of the workload; a later call with the same key applies the
+cached choice without timing.  A shape only changes how the sweeps are dealt to the
+GPU (blocks per sweep, i.e. 256-slot tiles per block; host-polled sweeps or one
+persistent launch and its resident blocks per compute unit): results of one shape are
+bitwise reproducible, and between shapes they differ at most in the last bits, since
+the block partials are summed in other groupings.
+
+The cache lives at ``$AMRFLD_TUNE_CACHE`` or ``~/.cache/amrfld/tune.json``.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import statistics
+import tempfile
+
+import torch
+
+LEVEL_BLOCKS = (256, 512, 1024, 2048, 4096)
+BATCH_SHAPES = (
+    {"persistent": 0, "persistent_per_cu": 0},
+    {"persistent": 1, "persistent_per_cu": 0},
+    {"persistent": 1, "persistent_per_cu": 2},
+    {"persistent": 1, "persistent_per_cu": 1},
+)
+
+
+def cache_path() -> str:
+    return os.environ.get("AMRFLD_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "amrfld",
+                                                               "tune.json")
+
+
+def device_key() -> str:
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|{p.multi_processor_count}"
+
+
+def workload_key(kind: str, sizes, precision: int) -> str:
+    h = hashlib.sha1(json.dumps([int(x) for x in sizes]).encode()).hexdigest()[:16]
+    return f"{kind}|{len(sizes)}|{h}|prec{int(precision)}"
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: dict) -> None:
+    """Write the cache atomically; an unwritable location only loses the cache."""
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path), suffix=".tmp")
+        with os.fdopen(fd, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def time_candidates(candidates, apply, run, repeats=3, stream=None):
+    """Device time (ms, median of `repeats`) of run() under each candidate shape."""
+    stream = stream or torch.cuda.current_stream()
+    out = {}
+    for c in candidates:
+        apply(c)
+        run()  # warm-up: layouts, workspaces, code paths
+        ts = []
+        for _ in range(repeats):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            run()
+            b.record(stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        out[json.dumps(c, sort_keys=True)] = statistics.median(ts)
+    return out
+
+
+def tune(key, candidates, apply, run, repeats=3, stream=None, use_cache=True, timer=None, device=None):
+    """Apply the fastest candidate for `key`; returns (shape, timings in ms, from_cache).
+    `timer` (default: time_candidates on the device) and `device` (default: the current
+    GPU) can be replaced, e.g. to exercise the cache without a GPU."""
+    full = (device or device_key()) + "|" + key
+    cache = _load()
+    if use_cache and full in cache:
+        best = cache[full]["best"]
+        apply(best)
+        return best, cache[full]["ms"], True
+    times = (timer or time_candidates)(candidates, apply, run, repeats, stream)
+    best = json.loads(min(times, key=times.get))
+    cache[full] = {"best": best, "ms": times}
+    _store(cache)
+    apply(best)
+    return best, times, False
+
+
+def tune_levels(solver, run, sizes, precision, repeats=3, use_cache=True):
+    """Blocks per sweep of a hierarchy's level solves; `run` advances one step from the
+    same state every time (the caller resets the fields inside it)."""
+    return tune(workload_key("levels", sizes, precision), [{"max_blocks": b} for b in LEVEL_BLOCKS],
+                lambda c: solver.set_launch(max_blocks=c["max_blocks"]), run, repeats, solver.stream,
+                use_cache)
+
+
+def tune_batch(solver, run, sizes, precision, repeats=2, use_cache=True):
+    """Host-polled sweeps or a persistent launch (and its resident blocks per compute unit)
+    for a batch of patches of the given sizes."""
+    return tune(workload_key("batch", sizes, precision), list(BATCH_SHAPES),
+                lambda c: solver.set_launch(0, c["persistent"], c["persistent_per_cu"]), run, repeats,
+                solver.stream, use_cache)

@@ -949,6 +949,10 @@ amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
     g_create_error = "max_iter >= 1, abs_floor >= 0 and a known precision are required";
     return AMRFLD_E_INVALID;
   }
+  if (o->max_blocks < 0 || o->persistent_per_cu < 0) {
+    g_create_error = "max_blocks and persistent_per_cu must be >= 0";
+    return AMRFLD_E_INVALID;
+  }
   amrfld_ctx* c = nullptr;
   try {
     c = new amrfld_ctx();
@@ -1158,6 +1162,19 @@ amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_
   if (n) *n = cnt;
   if (out)
     for (int k = 0; k < std::min(cnt, max_n); ++k) out[k] = c->stats[k];
+  return AMRFLD_OK;
+}
+
+amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, int persistent_per_cu) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (max_blocks < 0 || persistent < 0 || persistent_per_cu < 0) {
+    c->err = "set_launch: negative launch parameter";
+    return AMRFLD_E_INVALID;
+  }
+  c->o.max_blocks = max_blocks;
+  c->o.persistent = persistent ? 1 : 0;
+  c->o.persistent_per_cu = persistent_per_cu;
+  c->err.clear();
   return AMRFLD_OK;
 }
 

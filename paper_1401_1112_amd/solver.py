@@ -109,6 +109,9 @@ class HierarchySolver:
     def last_error(self):
         return L.amrfld_last_error(self.ctx)
 
+    def set_launch(self, max_blocks=0, persistent=False, persistent_per_cu=0):
+        self._check(L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu))
+
 
 def sample_problem_fields(solver: HierarchySolver, problem):
     """Sample a problem's fields in the library's cell order and upload them."""
@@ -224,3 +227,8 @@ class BatchSolver:
 
     def last_error(self):
         return L.amrfld_last_error(self.ctx)
+
+    def set_launch(self, max_blocks=0, persistent=False, persistent_per_cu=0):
+        st = L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu)
+        if st != L.OK:
+            raise L.AmrfldError(st, L.amrfld_last_error(self.ctx))

@@ -146,3 +146,22 @@ def test_batch_persistent_launch_equals_polled(graph, big):
     assert [x["iters"] for x in stats] == it_a
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_set_launch_rejects_negative_values():
+    from paper_1401_1112_amd import AmrfldError
+    patches, alpha = patch_batch(4950, 3, n_min=4, n_max=8)
+    s = _solver(robin_alpha=alpha)
+    with pytest.raises(AmrfldError):
+        s.set_launch(-1, False, 0)
+    with pytest.raises(AmrfldError):
+        s.set_launch(0, True, -2)
+    # the shape is unchanged and the solver still works
+    res, st = s.solve(patches, 1, 1e-10)
+    assert st == 0
+    s.set_launch(64, True, 1)
+    res2, _ = s.solve(patches, 1, 1e-10)
+    assert [x["launch_mode"] for x in s.stats()] == [1] * len(patches)
+    for a, b in zip(res, res2):
+        assert _rel(a, b) <= 1e-13
+    s.close()

@@ -32,25 +32,37 @@ def lognormal():
 
 
 @pytest.fixture(scope="module")
-def fp64_step(lognormal):
-    """One coarse step on the GPU (FP64, default launch shape) and in the oracle."""
-    from paper_1401_1112_amd import BC_DIRICHLET
-    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+def oracle_step(lognormal):
     p = lognormal
-    s = solver_from_problem(p)
-    s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
-    gpu = {l: (to_numpy(s.E(l)), s.cells(l)) for l in p.hierarchy.levels}
-    counts_g = [(st["level"], st["iters"]) for st in s.stats()]
-    stats_g = s.stats()
-    s.close()
     o = oracle_from_problem(p)
     o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, p.tol)
-    counts_o = [(h["level"], h["iters"]) for h in o.history]
-    return gpu, o, counts_g, counts_o, stats_g
+    return o, [(h["level"], h["iters"]) for h in o.history]
 
 
-def test_lognormal_full_step_parity(lognormal, fp64_step):
-    gpu, o, counts_g, counts_o, _ = fp64_step
+@pytest.fixture(scope="module")
+def gpu_solver(lognormal):
+    from paper_1401_1112_amd.solver import solver_from_problem
+    s = solver_from_problem(lognormal)
+    yield s
+    s.close()
+
+
+def _gpu_step(s, p, max_blocks):
+    """One coarse step from the initial fields with the given blocks per sweep."""
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import sample_problem_fields, to_numpy
+    sample_problem_fields(s, p)
+    s.set_launch(max_blocks=max_blocks)
+    s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+    gpu = {l: (to_numpy(s.E(l)), s.cells(l)) for l in p.hierarchy.levels}
+    return gpu, [(st["level"], st["iters"]) for st in s.stats()], s.stats()
+
+
+# every launch shape the autotuner may pick for the level solves
+@pytest.mark.parametrize("max_blocks", [256, 512, 1024, 2048, 4096])
+def test_lognormal_full_step_parity(lognormal, oracle_step, gpu_solver, max_blocks):
+    o, counts_o = oracle_step
+    gpu, counts_g, _ = _gpu_step(gpu_solver, lognormal, max_blocks)
     assert [l for l, _ in counts_g] == [l for l, _ in counts_o]
     diff = [(i, g, h) for i, ((_, g), (_, h)) in enumerate(zip(counts_g, counts_o)) if g != h]
     worst = 0.0
@@ -58,7 +70,8 @@ def test_lognormal_full_step_parity(lognormal, fp64_step):
         e, cells = gpu[l]
         ref = align(l, o.cells(l), o.E[l], cells)
         worst = max(worst, _rel(e, ref))
-    print(f"iteration counts {counts_g}; differing solves {diff}; worst relative L2 {worst:.3e}")
+    print(f"max_blocks {max_blocks}: iteration counts {counts_g}; differing solves {diff}; "
+          f"worst relative L2 {worst:.3e}")
     if not diff:
         assert worst <= 1e-12
     else:
@@ -66,10 +79,15 @@ def test_lognormal_full_step_parity(lognormal, fp64_step):
         assert worst <= 1e-9
 
 
+@pytest.fixture(scope="module")
+def fp64_step(lognormal, gpu_solver):
+    return _gpu_step(gpu_solver, lognormal, 0)
+
+
 def test_lognormal_full_step_residuals(lognormal, fp64_step):
     # every FP64 solve of the step meets its threshold on the true residual, up to the
     # recursion's rounding drift
-    _, _, _, _, stats = fp64_step
+    _, _, stats = fp64_step
     for st in stats:
         thr = max(lognormal.tol * st["rnorm0"], lognormal.abs_floor * st["bnorm"])
         assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= 1.05 * thr, st
@@ -78,7 +96,7 @@ def test_lognormal_full_step_residuals(lognormal, fp64_step):
 def test_lognormal_mixed_full_step(lognormal, fp64_step):
     from paper_1401_1112_amd import BC_DIRICHLET, MIXED
     from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
-    gpu, _, _, _, _ = fp64_step
+    gpu, _, _ = fp64_step
     p = lognormal
     s = solver_from_problem(p, precision=MIXED)
     s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
@@ -126,16 +144,19 @@ def test_patch_batch_full_size_sampled(batch512):
 
 
 def test_patch_batch_full_size_persistent_bitwise(batch512):
+    # every batch launch shape the autotuner may pick gives the polled results bitwise
     from paper_1401_1112_amd.solver import BatchSolver
     patches, alpha = batch512
     out = []
-    for kw in ({}, {"persistent": True, "graph": True}):
+    for kw in ({}, {"persistent": True, "graph": True}, {"persistent": True, "persistent_per_cu": 1},
+               {"persistent": True, "graph": True, "persistent_per_cu": 2}):
         bs = BatchSolver(robin_alpha=alpha, **kw)
         h = bs.upload(patches)
         bs.run(h, 2, 1e-10)
         out.append((bs.result(h), [x["iters"] for x in bs.stats()], max(x["launch_mode"] for x in bs.stats())))
         bs.close()
-    (a, ia, _), (b, ib, mode) = out
-    assert mode in (1, 2)
-    assert ia == ib
-    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    a, ia, _ = out[0]
+    for b, ib, mode in out[1:]:
+        assert mode in (1, 2)
+        assert ia == ib
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
