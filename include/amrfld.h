@@ -78,7 +78,8 @@ typedef struct {
   double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner solve; default 1e-4 */
   int max_outer;         /* AMRFLD_MIXED: refinement sweeps cap; default 30 */
   int max_blocks;        /* blocks per PCG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
-  int persistent;        /* batch form: 1 = all PCG iterations of a step in one cooperative launch */
+  int persistent;        /* 1 = all PCG iterations of a solve (batch form: of a step) in one cooperative
+                            launch, where the device can run it; else host-polled sweeps */
   int graph;             /* batch form with persistent: 1 = capture all steps in one hipGraph */
   void* stream;          /* hipStream_t */
   int persistent_per_cu; /* persistent launch: resident blocks per compute unit (0 = as many as fit) */

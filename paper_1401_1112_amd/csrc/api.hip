@@ -291,6 +291,8 @@ struct LoopStats {
   std::vector<int> iters;  // per problem: PCG iterations (inner iterations in mixed precision)
   int n_timed = 0;
   double a_ms = 0.0, b_ms = 0.0;
+  bool persistent = false;  // iterations ran in persistent launches
+  int launch_blocks = 0;    // blocks of those launches
 };
 
 void ensure_scalars(amrfld_ctx* c, int n_prob) {
@@ -331,6 +333,30 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
                     T* const* p, T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
+  if (c->o.persistent) {
+    // all iterations in one cooperative launch, when the device can run it
+    const int per_cu = c->o.persistent_per_cu;
+    if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
+    SweepPlan Pp = P;
+    Pp.done_count = c->bar + kBarDone;
+    const int blocks = persistent_blocks<T>(Pp, per_cu);
+    if (blocks > 0) {
+      launch_zero_u32(s, c->bar, kBarWords);
+      const hipError_t e = launch_pcg_persistent<T>(s, D, Pp, max_iter, Cp, diag, x, r, p, q, sc_dev, c->partials,
+                                                    c->bar, per_cu);
+      if (e == hipSuccess) {
+        read_scalars(c, sc_host, sc_dev, np);
+        unsigned aborted = 0;
+        check(hipMemcpy(&aborted, c->bar + kBarAbort, sizeof(unsigned), hipMemcpyDeviceToHost), "abort flag");
+        if (aborted) throw std::runtime_error("persistent sweep: a grid barrier timed out");
+        for (int qq = 0; qq < np; ++qq) ls->iters[qq] += sc_host[qq].iter;
+        ls->persistent = true;
+        ls->launch_blocks = blocks;
+        return;
+      }
+      (void)hipGetLastError();  // not launchable here: poll instead
+    }
+  }
   int launched = 0;
   int chunk = c->o.check_every > 0 ? c->o.check_every : 8;
   const bool autochunk = c->o.check_every <= 0;
@@ -536,7 +562,8 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   st.rnorm0 = h.rnorm0;
   st.bnorm = h.bnorm;
   st.sweep_blocks = P.G;
-  st.launch_blocks = P.G;
+  st.launch_blocks = ls.persistent ? ls.launch_blocks : P.G;
+  st.launch_mode = ls.persistent ? 1 : 0;
   float ms = 0.f, pms = 0.f;
   check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
   check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
@@ -691,7 +718,7 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
   P.done_count = c->bar + kBarDone;
   const unsigned* abort_flag = c->bar + kBarAbort;
   const int per_cu = c->o.persistent_per_cu;
-  if (persistent_blocks(P, per_cu) <= 0) return AMRFLD_E_STATE;
+  if (persistent_blocks<double>(P, per_cu) <= 0) return AMRFLD_E_STATE;
   ensure_scalars(c, n_steps * np);
   CouplingParams cp{};
   cp.T = nullptr;
@@ -778,7 +805,7 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       st.rnorm0 = h.rnorm0;
       st.bnorm = h.bnorm;
       st.sweep_blocks = P.G;
-      st.launch_blocks = persistent_blocks(P, per_cu);
+      st.launch_blocks = persistent_blocks<double>(P, per_cu);
       st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
       if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
         worst = amrfld_status(st.status);
@@ -888,7 +915,8 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
       st.rnorm0 = h.rnorm0;
       st.bnorm = h.bnorm;
       st.sweep_blocks = P.G;
-      st.launch_blocks = P.G;
+      st.launch_blocks = ls.persistent ? ls.launch_blocks : P.G;
+      st.launch_mode = ls.persistent ? 1 : 0;
       st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
       if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
         worst = amrfld_status(st.status);

@@ -144,7 +144,9 @@ void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc
 // its first kBarAbort words are zeroed before the start sweeps.  Returns an
 // error if the device cannot run the cooperative launch.  bar[kBarAbort]
 // becomes 1 if a grid barrier timed out (the launch then returns early).
+// Blocks of the persistent launch for this plan (0 if the device cannot run it);
 // per_cu_cap > 0 limits the resident blocks per compute unit (fewer barrier arrivals).
+template <typename T>
 int persistent_blocks(const SweepPlan& P, int per_cu_cap);
 template <typename T>
 hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter,

@@ -503,7 +503,10 @@ __device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first,
   PcgScalars* out = outs + prob;
   PcgScalars* in = ins + prob;
   if (out->done) {
-    if (threadIdx.x == 0) in->done = 1;
+    if (threadIdx.x == 0) {
+      in->done = 1;
+      in->counted = 0;
+    }
     return;
   }
   double v[3];
@@ -539,6 +542,7 @@ __device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first,
   in->converged = 0;
   in->nonfinite = 0;
   in->iter = 0;
+  in->counted = 0;
 }
 
 __device__ __forceinline__ void body_inner_init(int vb, DevLevel L, SweepPlan P, const float* __restrict__ diag32,
@@ -779,10 +783,14 @@ int resident_blocks(const SweepPlan& P, int per_cu_cap) {
   return per_cu * cus;
 }
 
+template <typename T>
 int persistent_blocks(const SweepPlan& P, int per_cu_cap) {
-  const int res = resident_blocks<double>(P, per_cu_cap);
+  const int res = resident_blocks<T>(P, per_cu_cap);
   return res > 0 ? std::min(P.G, res) : 0;
 }
+
+template int persistent_blocks<double>(const SweepPlan&, int);
+template int persistent_blocks<float>(const SweepPlan&, int);
 
 template <typename T>
 hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter, const T* Cp,
@@ -807,6 +815,9 @@ hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPl
 template hipError_t launch_pcg_persistent<double>(hipStream_t, const DevLevel&, const SweepPlan&, int,
                                                   const double*, const double*, double*, double*, double* const*,
                                                   double*, PcgScalars*, double*, unsigned*, int);
+template hipError_t launch_pcg_persistent<float>(hipStream_t, const DevLevel&, const SweepPlan&, int,
+                                                 const float*, const float*, float*, float*, float* const*,
+                                                 float*, PcgScalars*, double*, unsigned*, int);
 
 template void launch_pcg_init<double>(hipStream_t, const DevLevel&, const SweepPlan&, const double*,
                                       const double*, const double*, const double*, double*, double*,

@@ -12,7 +12,7 @@ class HierarchySolver:
     def __init__(self, base_level, octs, *, robin_alpha=0.5, max_iter=10000, precision=L.FP64,
                  linf_test=True, abs_floor=1e-14, a_rad=1.0, c_v=1.0, nsub=None, check_every=0,
                  true_residual=True, time_sweeps=0, inner_tol=1e-4, max_outer=30, max_blocks=0,
-                 device="cuda:0", stream=None):
+                 persistent=False, persistent_per_cu=0, device="cuda:0", stream=None):
         L.load()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -34,6 +34,8 @@ class HierarchySolver:
         o.inner_tol = float(inner_tol)
         o.max_outer = int(max_outer)
         o.max_blocks = int(max_blocks)
+        o.persistent = int(bool(persistent))
+        o.persistent_per_cu = int(persistent_per_cu)
         o.stream = self.stream.cuda_stream
         self.ctx = L.amrfld_create(o)
         self.levels = list(range(int(base_level), int(max(octs)) + 1))

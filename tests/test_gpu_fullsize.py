@@ -110,6 +110,27 @@ def test_lognormal_mixed_full_step(lognormal, fp64_step):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lognormal_persistent_equals_polled(lognormal, precision):
+    # one persistent launch per solve at full size gives the host-polled results bitwise
+    from paper_1401_1112_amd import BC_DIRICHLET, FP64, MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    p = lognormal
+    prec = MIXED if precision == "mixed" else FP64
+    out = []
+    for kw in ({}, {"persistent": True}):
+        s = solver_from_problem(p, precision=prec, **kw)
+        s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+        st = s.stats()
+        out.append(({l: to_numpy(s.E(l)) for l in p.hierarchy.levels}, [x["iters"] for x in st],
+                    {x["launch_mode"] for x in st}))
+        s.close()
+    (a, ia, ma), (b, ib, mb) = out
+    assert ma == {0} and mb == {1}
+    assert ia == ib
+    assert all(np.array_equal(a[l], b[l]) for l in a)
+
+
 @pytest.fixture(scope="module")
 def batch512():
     return patch_batch(4000, 512)

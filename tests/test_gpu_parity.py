@@ -308,3 +308,31 @@ def test_mixed_precision_uniform_closed_form():
     assert st["true_rel_res"] <= 1e-12 * (1 + 1e-6)
     assert _rel(x, ref) < 1e-11
     s.close()
+
+
+# ------------------------------------------------------------- persistent launch
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode", ["dirichlet", "robin"])
+def test_persistent_level_solves_equal_polled(precision, mode):
+    # one cooperative launch per solve (per inner solve in mixed precision) runs the same
+    # sweep bodies over the same block plan as the host-polled sweeps: results and
+    # iteration counts are bitwise equal
+    torch, S = _gpu()
+    from paper_1401_1112_amd import FP64, MIXED
+    prec = MIXED if precision == "mixed" else FP64
+    p = config_tiny(2, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-10)
+    out = []
+    for kw in ({}, {"persistent": True}, {"persistent": True, "persistent_per_cu": 1}):
+        s = S.solver_from_problem(p, precision=prec, **kw)
+        s.advance(p.dt_coarse, MODES[mode], p.tol)
+        s.advance(p.dt_coarse, MODES[mode], p.tol)
+        st = s.stats()
+        out.append(([S.to_numpy(s.E(l)) for l in p.hierarchy.levels],
+                    [(x["iters"], x["outer_iters"]) for x in st], {x["launch_mode"] for x in st}))
+        s.close()
+    base, counts, modes = out[0]
+    assert modes == {0}
+    for e, c, m in out[1:]:
+        assert m == {1}
+        assert c == counts
+        assert all(np.array_equal(a, b) for a, b in zip(e, base))
