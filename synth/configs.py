@@ -120,6 +120,54 @@ def config_fld_lognormal(base_level: int = 6, max_level: int = 9, field_n: int =
                    tol=tol, n_coarse_steps=1, info={"refined_per_level": counts})
 
 
+def _collapse_rho(contrast: float, field_n: int, seed: int, amp: float = 0.05):
+    """Softened singular isothermal sphere at the box centre, rho_e (R_c^2 + eps^2) /
+    (r^2 + eps^2) with rho_e = 1 and R_c = sqrt(3)/2 (centre to corner), eps set so that
+    the centre-to-corner contrast is ``contrast``; times (1 + amp g) with g a clipped
+    unit-variance k^-4 field."""
+    g = _field(field_n, 4.0, seed)
+    rc2 = 0.75
+    eps2 = rc2 / (contrast - 1.0)
+
+    def rho(level, ijk):
+        x = cell_centres(level, ijk)
+        r2 = np.sum((x - 0.5) ** 2, axis=1)
+        return (rc2 + eps2) / (r2 + eps2) * (1.0 + amp * np.clip(g.sample(x), -3.0, 3.0))
+
+    return rho, np.sqrt(rc2)
+
+
+def config_collapse(base_level: int = 6, max_level: int = 13, jeans: float = 0.14, contrast: float = 1e6,
+                    field_n: int = 256, rho_seed: int = 5000, E_seed: int = 5001, shared_dt_levels: int = 4,
+                    tol: float = 1e-10) -> Problem:
+    """Collapse-like hierarchy with coupled radiation and gas energy.
+
+    Density: softened singular isothermal sphere (contrast ``contrast``) with a 5% k^-4
+    perturbation.  A cell of level l is refined while dx_l > lambda_J / 8 with the Jeans
+    length lambda_J = J (rho / rho_e)^(-1/2) R_c (2:1 balance kept), J = ``jeans``.
+    E = 1 + 10% k^-4 perturbation, T = (E / a)^(1/4) (radiation and gas in equilibrium),
+    kappa_R = kappa_P = c = c_v = a = 1, LP limiter, Dirichlet interfaces.  The first
+    ``shared_dt_levels`` levels share the coarse dt (nsub = 1), the finer ones halve it
+    (nsub = 2).  Coarse dt = 4 dx_base^2 / K_thick with K_thick = 1/3."""
+    rho, rc = _collapse_rho(contrast, field_n, rho_seed)
+
+    def criterion(level, ijk):
+        return 8.0 * np.sqrt(rho(level, ijk)) / ((1 << level) * jeans * rc)
+
+    h, counts = budgeted_hierarchy(base_level, max_level, criterion, 1.0, 1 << 62, seed=rho_seed)
+    E = _perturbed_E(field_n, E_seed)
+
+    def T(level, ijk):
+        return E(level, ijk) ** 0.25
+
+    top = max(h.levels)
+    nsub = {l: (1 if l < base_level + shared_dt_levels else 2) for l in range(base_level + 1, top + 1)}
+    dxb = 1.0 / (1 << base_level)
+    return Problem(f"collapse_L{base_level}-{top}", h, rho, E, T=T, kmode="lp", dt_coarse=4.0 * dxb * dxb * 3.0,
+                   bc_mode="dirichlet", tol=tol, n_coarse_steps=1, nsub=nsub,
+                   info={"refined_per_level": counts, "jeans": jeans, "contrast": contrast})
+
+
 def config_tiny(seed: int, base_level: int = 2, max_level: int = 4, kmode: str = "lp",
                 bc_mode: str = "dirichlet", dt_scale: float = 1.0, p_refine: float = 0.35,
                 tol: float = 1e-12, robin_alpha: float = 0.5) -> Problem:

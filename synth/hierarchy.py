@@ -94,6 +94,27 @@ def _eligible(h: Hierarchy, level: int, cells: np.ndarray) -> np.ndarray:
     return ok
 
 
+def _eligible_octwise(h: Hierarchy, level: int) -> np.ndarray:
+    """``_eligible`` for all cells of ``level`` in ``cell_coords_of_octs`` order: a face
+    neighbour outside a cell's oct lies in the neighbouring oct, so one lookup per oct
+    and face decides it for the cells on that side."""
+    octs = np.asarray(h.octs[level], dtype=np.int64)
+    m = 1 << (level - 1)
+    okeys = np.sort(_keys(octs, level - 1))
+    ok = np.ones((len(octs), 8), dtype=bool)
+    pos = np.arange(8)
+    for d, off in enumerate(_FACE_OFFSETS):
+        axis, plus = d // 2, d % 2
+        nb = octs + off
+        inside = (nb[:, axis] >= 0) & (nb[:, axis] < m)
+        nb_ok = ~inside
+        if inside.any():
+            nb_ok[inside] = _exists(okeys, nb[inside], level - 1)
+        outer = ((pos >> axis) & 1) == plus  # cells whose face in this direction leaves the oct
+        ok[:, outer] &= nb_ok[:, None]
+    return ok.reshape(-1)
+
+
 def uniform_hierarchy(level: int, seed: int = 0) -> Hierarchy:
     rng = np.random.default_rng(seed)
     return Hierarchy(level, {level: _shuffled(_full_octs(level), rng)})
@@ -145,7 +166,7 @@ def budgeted_hierarchy(base_level: int, max_level: int, criterion, threshold: fl
     counts = {}
     for level in range(base_level, max_level):
         cells = cell_coords_of_octs(h.octs[level])
-        elig = _eligible(h, level, cells)
+        elig = _eligible_octwise(h, level)
         crit = np.asarray(criterion(level, cells), dtype=np.float64)
         cand = np.nonzero(elig & (crit > threshold))[0]
         order = np.lexsort((_keys(cells[cand], level), -crit[cand]))

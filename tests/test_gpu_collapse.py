@@ -1,0 +1,118 @@
+"""The collapse-like workload against the oracle at reduced size: Jeans-refined levels
+around a softened singular isothermal sphere, radiation coupled to the gas energy, the
+first levels sharing the coarse dt and the finer ones subcycling.
+
+Bar: FP64 E and T per level within 1e-12 relative L2 with equal iteration counts (a
+near-tie of a residual with its threshold falls back to fixed counts, tol = 0); mixed
+precision meets every solve's threshold on the FP64 true residual and agrees with the
+FP64 oracle to 1e-8; a persistent launch per solve gives the host-polled results bitwise.
+"""
+import numpy as np
+import pytest
+
+from _util import align, oracle_from_problem
+import oracle as ora
+from synth.configs import config_collapse
+
+pytestmark = pytest.mark.gpu
+
+
+def _small(J):
+    return config_collapse(base_level=3, max_level=7, jeans=J, contrast=1e4, field_n=64, shared_dt_levels=2)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _gpu_fields(s, levels):
+    from paper_1401_1112_amd.solver import to_numpy
+    out = {}
+    for l in levels:
+        e, t = s.E(l, with_T=True)
+        out[l] = (to_numpy(e), to_numpy(t), s.cells(l))
+    return out
+
+
+def _worst(p, gpu, o):
+    w = 0.0
+    for l in p.hierarchy.levels:
+        e, t, c = gpu[l]
+        w = max(w, _rel(e, align(l, o.cells(l), o.E[l], c)), _rel(t, align(l, o.cells(l), o.T[l], c)))
+    return w
+
+
+def _run_pair(p, steps, tol, max_iter):
+    from paper_1401_1112_amd.solver import solver_from_problem
+    s = solver_from_problem(p, max_iter=max_iter)
+    o = oracle_from_problem(p, max_iter=max_iter)
+    counts = []
+    for _ in range(steps):
+        start = len(o.history)
+        s.advance(p.dt_coarse, 0, tol)
+        o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, tol)
+        counts.append(([(x["level"], x["iters"]) for x in s.stats()],
+                       [(h["level"], h["iters"]) for h in o.history[start:]]))
+    gpu = _gpu_fields(s, p.hierarchy.levels)
+    s.close()
+    return counts, _worst(p, gpu, o)
+
+
+@pytest.mark.parametrize("J,steps", [(1.5, 1), (2.5, 2)])
+def test_collapse_fp64_parity(J, steps):
+    p = _small(J)
+    counts, worst = _run_pair(p, steps, p.tol, p.max_iter)
+    # the schedule: one solve of each shared-dt level, 2^k of the k-th subcycled one
+    assert [l for l, _ in counts[0][0]] == [l for l, _ in counts[0][1]]
+    print(f"J {J}: counts {counts[0][0]}; worst relative L2 (E, T) {worst:.3e}")
+    if all(g == o for g, o in counts):
+        assert worst <= 1e-12
+        return
+    n_fix = max(it for g, o in counts for _, it in g + o)
+    counts2, worst2 = _run_pair(p, steps, 0.0, n_fix)
+    assert all(g == o for g, o in counts2)
+    assert worst2 <= 1e-12
+
+
+def test_collapse_schedule_counts():
+    p = _small(1.5)
+    o = oracle_from_problem(p)
+    o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, p.tol)
+    per = {}
+    for h in o.history:
+        per[h["level"]] = per.get(h["level"], 0) + 1
+    # nsub = 1 on level 4 (shares the coarse dt), 2 on levels 5..7
+    assert per == {3: 1, 4: 1, 5: 2, 6: 4, 7: 8}
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_collapse_mixed_reaches_tolerance(persistent):
+    from paper_1401_1112_amd import MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem
+    p = _small(1.5)
+    s = solver_from_problem(p, precision=MIXED, persistent=persistent)
+    s.advance(p.dt_coarse, 0, p.tol)
+    for st in s.stats():
+        thr = max(p.tol * st["rnorm0"], p.abs_floor * st["bnorm"])
+        assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= thr * (1 + 1e-12), st
+        assert st["launch_mode"] == (1 if persistent else 0)
+    gpu = _gpu_fields(s, p.hierarchy.levels)
+    s.close()
+    o = oracle_from_problem(p)
+    o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, 1e-13)
+    assert _worst(p, gpu, o) <= 1e-8
+
+
+def test_collapse_persistent_equals_polled():
+    from paper_1401_1112_amd.solver import solver_from_problem
+    p = _small(1.5)
+    res = []
+    for kw in ({}, {"persistent": True}):
+        s = solver_from_problem(p, **kw)
+        s.advance(p.dt_coarse, 0, p.tol)
+        res.append((_gpu_fields(s, p.hierarchy.levels), [x["iters"] for x in s.stats()]))
+        s.close()
+    (a, ia), (b, ib) = res
+    assert ia == ib
+    for l in p.hierarchy.levels:
+        assert np.array_equal(a[l][0], b[l][0]) and np.array_equal(a[l][1], b[l][1])

@@ -1,5 +1,6 @@
 """Input generators: balance, sizes and determinism."""
 import numpy as np
+import pytest
 
 from synth.configs import config_heat_gaussian, config_tiny, patch_sizes
 from synth.hierarchy import is_balanced, random_balanced_hierarchy
@@ -41,3 +42,32 @@ def test_tiny_fields_positive():
         from synth.hierarchy import cell_coords_of_octs
         c = cell_coords_of_octs(p.hierarchy.octs[l])
         assert np.all(p.rho(l, c) > 0) and np.all(p.E(l, c) > 0)
+
+
+def test_collapse_config_shape():
+    # Jeans-refined hierarchy around the softened sphere: balanced, nested towards the
+    # centre, every refined cell dense enough, contrast as asked, fields positive
+    from synth.configs import config_collapse
+    from synth.hierarchy import cell_coords_of_octs, is_balanced
+    p = config_collapse(base_level=3, max_level=7, jeans=1.5, contrast=1e4, field_n=64, shared_dt_levels=2)
+    h = p.hierarchy
+    assert is_balanced(h)
+    assert h.levels == [3, 4, 5, 6, 7]
+    assert p.nsub == {4: 1, 5: 2, 6: 2, 7: 2}
+    for l in h.levels[1:]:
+        parents = np.asarray(h.octs[l], dtype=np.int64)
+        rho = p.rho(l - 1, parents)
+        crit = 8.0 * np.sqrt(rho) / ((1 << (l - 1)) * 1.5 * np.sqrt(0.75))
+        assert np.all(crit > 1.0)
+        x = (parents + 0.5) / (1 << (l - 1))
+        assert np.max(np.linalg.norm(x - 0.5, axis=1)) < 0.9 / (1 << (l - 4)) + 0.1
+    c = cell_coords_of_octs(h.octs[7])
+    assert np.all(p.rho(7, c) > 0) and np.all(p.E(7, c) > 0)
+    assert np.allclose(p.T(7, c) ** 4, p.E(7, c))
+    # centre-to-corner contrast without the 5% perturbation
+    from synth.configs import _collapse_rho
+    rho0, rc = _collapse_rho(1e4, 64, 1, amp=0.0)
+    n = 1 << 20
+    centre = np.array([[n // 2, n // 2, n // 2]])
+    assert rc == pytest.approx(np.sqrt(3) / 2)
+    assert rho0(20, centre)[0] / rho0(20, np.array([[0, 0, 0]]))[0] == pytest.approx(1e4, rel=1e-4)
