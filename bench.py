@@ -275,6 +275,85 @@ def _batched_form(args):
     return out
 
 
+def _collapse_form(args):
+    """Collapse-like hierarchy: levels 6..13 Jeans-refined around a softened singular
+    isothermal sphere (contrast 1e6), radiation coupled to the gas energy, levels 6..9
+    sharing the coarse dt and 10..13 subcycling (34 solves per coarse step, 16 on level 13).
+    Mixed precision (FP32 inner PCG, FP64 refinement to 1e-10) with one persistent launch
+    per inner solve, against mixed and FP64 host-polled sweeps; every variant advances
+    one coarse step from the same state."""
+    import torch
+    from paper_1401_1112_amd import BC_DIRICHLET, FP64, MIXED
+    from paper_1401_1112_amd.solver import HierarchySolver, solver_from_problem
+    from synth.configs import config_collapse
+    t_gen = time.perf_counter()
+    p = config_collapse()
+    first = solver_from_problem(p, precision=MIXED, persistent=True, max_blocks=args.max_blocks)
+    t_gen = time.perf_counter() - t_gen
+    fields = {l: tuple(t.clone() for t in first._fields[l]) for l in first.levels}
+    slots = {l: first.info(l)[0] for l in first.levels}
+    out = {"workload": f"collapse levels 6..13: {sum(slots.values())} cells "
+                       f"({', '.join(f'L{l} {slots[l]}' for l in first.levels)}), Jeans J = 0.14, "
+                       "coupled E-T, nsub 1 on levels 7..9 and 2 on 10..13, Dirichlet interfaces, tol 1e-10",
+           "generation_s": round(t_gen, 1)}
+
+    def reset(s):
+        for l in s.levels:
+            rho, E, T = fields[l]
+            s.set_fields(l, rho, E, T, kmode=1)
+
+    if not args.no_tune:
+        from paper_1401_1112_amd.autotune import tune_level_shapes
+
+        def tune_step():
+            reset(first)
+            first.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+
+        print("bench: tuning the collapse launch shape", file=sys.stderr, flush=True)
+        best, times, cached = tune_level_shapes(first, tune_step, list(slots.values()), MIXED)
+        out["tuned_shape_mixed"] = {"best": best, "from_cache": cached, "candidate_ms_per_step": times}
+        first.set_launch(args.max_blocks, True, 0)
+
+    results = {}
+    for name, prec, pers in (("mixed_persistent", MIXED, True), ("mixed_polled", MIXED, False),
+                             ("fp64_polled", FP64, False)):
+        print(f"bench: collapse form {name}", file=sys.stderr, flush=True)
+        if first is not None:
+            s, first = first, None
+        else:
+            s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, persistent=pers,
+                                nsub=p.nsub, max_blocks=args.max_blocks)
+        reset(s)
+        s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)  # warm-up
+        reset(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = s.stats()
+        ci = sum(x["n_leaf"] * x["iters"] for x in st)
+        results[name] = {l: s.E(l, with_T=True) for l in s.levels}
+        out[name] = {"ms_per_step": round(el * 1e3, 1), "solves": len(st),
+                     "pcg_iterations": sum(x["iters"] for x in st),
+                     "outer_sweeps": sum(x["outer_iters"] for x in st),
+                     "cell_iterations_per_s": ci / el,
+                     "launch_modes": sorted({x["launch_mode"] for x in st}),
+                     "residual": _residual_gate(st, p.tol), "min_E": min(x["min_E"] for x in st)}
+        s.close()
+    ref = results["fp64_polled"]
+    for name in ("mixed_persistent", "mixed_polled"):
+        worst_e = max(float(torch.linalg.vector_norm(results[name][l][0] - ref[l][0])
+                            / torch.linalg.vector_norm(ref[l][0])) for l in ref)
+        worst_t = max(float(torch.linalg.vector_norm(results[name][l][1] - ref[l][1])
+                            / torch.linalg.vector_norm(ref[l][1])) for l in ref)
+        out[name]["rel_l2_vs_fp64_gpu"] = {"E": worst_e, "T": worst_t}
+    out["mixed_persistent_equals_polled_bitwise"] = all(
+        bool(torch.equal(results["mixed_persistent"][l][0], results["mixed_polled"][l][0])) for l in ref)
+    out["mixed_speedup_vs_fp64"] = out["fp64_polled"]["ms_per_step"] / out["mixed_persistent"]["ms_per_step"]
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +368,8 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-patches", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=16)
+    ap.add_argument("--no-collapse", action="store_true",
+                    help="skip the collapse-like form (levels 6..13, ~41 M cells; ~1 min of setup)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (level solves: --max-blocks or the default)")
     args = ap.parse_args(argv)
@@ -399,6 +480,10 @@ def main(argv=None):
         import torch as _t
         _t.cuda.empty_cache()
         out["forms"]["batched"] = _batched_form(args)
+    if not args.no_collapse:
+        import torch as _t
+        _t.cuda.empty_cache()
+        out["forms"]["collapse"] = _collapse_form(args)
     if not args.no_cpu_baseline:
         cb = _cpu_baseline(p, args.cpu_budget)
         cb.pop("seconds", None)

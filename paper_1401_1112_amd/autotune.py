@@ -22,6 +22,13 @@ import tempfile
 import torch
 
 LEVEL_BLOCKS = (256, 512, 1024, 2048, 4096)
+LEVEL_SHAPES = (
+    {"max_blocks": 512, "persistent": 0, "persistent_per_cu": 0},
+    {"max_blocks": 1024, "persistent": 0, "persistent_per_cu": 0},
+    {"max_blocks": 2048, "persistent": 0, "persistent_per_cu": 0},
+    {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 0},
+    {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 1},
+)
 BATCH_SHAPES = (
     {"persistent": 0, "persistent_per_cu": 0},
     {"persistent": 1, "persistent_per_cu": 0},
@@ -117,3 +124,11 @@ def tune_batch(solver, run, sizes, precision, repeats=2, use_cache=True):
     return tune(workload_key("batch", sizes, precision), list(BATCH_SHAPES),
                 lambda c: solver.set_launch(0, c["persistent"], c["persistent_per_cu"]), run, repeats,
                 solver.stream, use_cache)
+
+
+def tune_level_shapes(solver, run, sizes, precision, repeats=2, use_cache=True):
+    """Blocks per sweep and host-polled or persistent launches of a hierarchy's level
+    solves; `run` advances one step from the same state every time."""
+    return tune(workload_key("level-shapes", sizes, precision), list(LEVEL_SHAPES),
+                lambda c: solver.set_launch(c["max_blocks"], c["persistent"], c["persistent_per_cu"]), run,
+                repeats, solver.stream, use_cache)

@@ -19,10 +19,15 @@
 namespace amrfld {
 
 // At most kMaxTilesPerBlock tiles per block: the operator sweep stages the
-// block's whole range of the new p in LDS (16 tiles = 32 KB in FP64).
+// block's whole range of the new p in LDS (16 tiles = 32 KB in FP64).  A level
+// with more than max_blocks * 16 tiles gets a whole multiple of max_blocks, so
+// that the blocks of a persistent launch of max_blocks blocks each sweep the
+// same number of equal ranges.
 int sweep_blocks(int n_tiles, int max_blocks) {
-  const int g = std::max(1, std::min(n_tiles, max_blocks));
-  return std::max(g, (n_tiles + kMaxTilesPerBlock - 1) / kMaxTilesPerBlock);
+  const int B = std::max(1, max_blocks);
+  if (n_tiles <= B) return std::max(1, n_tiles);
+  const int64_t rounds = (int64_t(n_tiles) + int64_t(B) * kMaxTilesPerBlock - 1) / (int64_t(B) * kMaxTilesPerBlock);
+  return int(rounds * B);
 }
 
 namespace {

@@ -116,3 +116,58 @@ def test_collapse_persistent_equals_polled():
     assert ia == ib
     for l in p.hierarchy.levels:
         assert np.array_equal(a[l][0], b[l][0]) and np.array_equal(a[l][1], b[l][1])
+
+
+# ------------------------------------------------------------------ full size
+@pytest.fixture(scope="module")
+def collapse_full():
+    """The benchmark's collapse hierarchy (levels 6..13, ~41 M cells) with its fields on
+    the device, sampled once."""
+    from paper_1401_1112_amd import MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem
+    p = config_collapse()
+    s = solver_from_problem(p, precision=MIXED, persistent=True)
+    fields = {l: tuple(t.clone() for t in s._fields[l]) for l in s.levels}
+    yield p, s, fields
+    s.close()
+
+
+def _step_from(s, p, fields):
+    from paper_1401_1112_amd import BC_DIRICHLET
+    for l in s.levels:
+        rho, E, T = fields[l]
+        s.set_fields(l, rho, E, T, kmode=1)
+    s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+    return s.stats(), {l: s.E(l, with_T=True) for l in s.levels}
+
+
+def test_collapse_full_size_properties(collapse_full):
+    # the oracle cannot take a 41 M-cell hierarchy in test time; at full size every
+    # solve must meet its threshold on the FP64 true residual, the persistent launch
+    # must give the host-polled results bitwise, and mixed must agree with FP64
+    import torch
+    from paper_1401_1112_amd import FP64
+    from paper_1401_1112_amd.solver import HierarchySolver
+    p, s, fields = collapse_full
+    st_p, res_p = _step_from(s, p, fields)
+    assert len(st_p) == 34 and sum(1 for x in st_p if x["level"] == 13) == 16
+    for x in st_p:
+        thr = max(p.tol * x["rnorm0"], p.abs_floor * x["bnorm"])
+        assert x["converged"] == 1 and x["launch_mode"] == 1
+        assert x["true_rel_res"] * x["rnorm0"] <= thr * (1 + 1e-12), x
+    s.set_launch(0, False, 0)
+    st_q, res_q = _step_from(s, p, fields)
+    assert [x["iters"] for x in st_q] == [x["iters"] for x in st_p]
+    for l in s.levels:
+        assert torch.equal(res_p[l][0], res_q[l][0]) and torch.equal(res_p[l][1], res_q[l][1])
+    s.set_launch(0, True, 0)
+    f = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=FP64, nsub=p.nsub)
+    st_f, res_f = _step_from(f, p, fields)
+    f.close()
+    for x in st_f:
+        thr = max(p.tol * x["rnorm0"], p.abs_floor * x["bnorm"])
+        assert x["converged"] == 1 and x["true_rel_res"] * x["rnorm0"] <= 1.05 * thr, x
+    for l in s.levels:
+        for k in (0, 1):
+            a, b = res_p[l][k], res_f[l][k]
+            assert float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) <= 1e-8
