@@ -14,7 +14,7 @@ does the same work.
 
 Output: one JSON line (metric: PCG cell-iterations per second = sum over solves
 of leaf cells x iterations / wall time), with the roofline of the dominant
-kernel (the operator sweep, pass A) from HIP events around its launches and the
+kernel (the operator sweep, pass A) from HIP events its launches record and the
 CPU FP64 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -47,9 +47,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(kernel: str):
+def _measured_traffic(kernel: str, max_blocks: int):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel source or the launch shape differ from those the counters
+    were taken with."""
     prof = os.path.join(ROOT, "profiles", "fld_lognormal_L6-9_fp64_hbm_counters.txt")
     try:
         kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
@@ -58,6 +59,8 @@ def _measured_traffic(kernel: str):
         return None
     cur = kernel_source_sha()
     if kv.get("traffic_kernel") != kernel or kv.get("traffic_source_sha256_prefix") != cur:
+        return None
+    if kv.get("traffic_max_blocks") != str(max_blocks):
         return None
     return float(kv["traffic_kib_per_dispatch"]) * 1024.0
 
@@ -218,7 +221,7 @@ def _batched_form(args):
         bs.close()
         del h
         torch.cuda.empty_cache()
-        out["tuned_shape"] = {"best": best, "from_cache": cached, "candidate_ms_per_step": times}
+        out["tuned_shape"] = {"best": best, "source": cached, "candidate_ms_per_step": times}
         forms.append(("fp64_tuned", {"persistent": bool(best["persistent"]), "graph": True,
                                      "persistent_per_cu": best["persistent_per_cu"]}, 0))
     results = {}
@@ -311,7 +314,7 @@ def _collapse_form(args):
 
         print("bench: tuning the collapse launch shape", file=sys.stderr, flush=True)
         best, times, cached = tune_level_shapes(first, tune_step, list(slots.values()), MIXED)
-        out["tuned_shape_mixed"] = {"best": best, "from_cache": cached, "candidate_ms_per_step": times}
+        out["tuned_shape_mixed"] = {"best": best, "source": cached, "candidate_ms_per_step": times}
         first.set_launch(args.max_blocks, True, 0)
 
     results = {}
@@ -405,7 +408,7 @@ def main(argv=None):
         from paper_1401_1112_amd.autotune import tune_levels
         best, times, cached = tune_levels(s, one_step, [s.info(l)[0] for l in s.levels], 0)
         args.max_blocks = best["max_blocks"]
-        launch = {"max_blocks": args.max_blocks, "tuned": True, "from_cache": cached,
+        launch = {"max_blocks": args.max_blocks, "tuned": True, "source": cached,
                   "candidate_ms_per_step": times}
     for _ in range(args.warmup):
         one_step()
@@ -430,7 +433,7 @@ def main(argv=None):
     roofline = None
     if a_ms > 0:
         achieved = a_bytes / (a_ms * 1e-3) / 1e9
-        traffic = _measured_traffic("k_pass_a<double>")
+        traffic = _measured_traffic("k_pass_a<double>", args.max_blocks if args.max_blocks > 0 else 1024)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else round(traffic),
@@ -439,7 +442,8 @@ def main(argv=None):
                     "alg_bytes_per_launch": round(a_bytes / max(n_a, 1)),
                     "kernel": "k_pass_a (p update + 7-point operator + (p,q) partials)",
                     "bytes_per_slot": PASS_A_BYTES, "timed_launches": n_a,
-                    "timing": f"HIP events around the sweeps of every {args.time_period}th PCG iteration",
+                    "timing": f"HIP start/stop events recorded by the launches themselves "
+                              f"(hipExtLaunchKernelGGL) of the sweeps of every {args.time_period}th PCG iteration",
                     "avg_launch_us": round(a_ms * 1e3 / max(n_a, 1), 2),
                     "pass_b_GBs": round(b_bytes / (b_ms * 1e-3) / 1e9, 1) if b_ms > 0 else None,
                     "pass_b_bytes_per_slot": PASS_B_BYTES}

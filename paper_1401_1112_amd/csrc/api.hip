@@ -365,7 +365,7 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
   while (!all_done(sc_host, np) && launched < max_iter) {
     const int k = std::min(chunk, max_iter - launched);
     if (period > 0) {
-      while (int(c->sweep_ev.size()) < 3 * ((launched + k) / period + 1)) {
+      while (int(c->sweep_ev.size()) < 4 * ((launched + k) / period + 1)) {
         hipEvent_t e;
         check(hipEventCreate(&e), "event");
         c->sweep_ev.push_back(e);
@@ -375,12 +375,12 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
       const int it = launched + t + 1;
       T* pn = p[it & 1];
       const T* po = p[(it & 1) ^ 1];
-      hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[3 * (it / period - 1)] : nullptr;
-      if (e) check(hipEventRecord(e[0], s), "event");
-      launch_pass_a<T>(s, D, P, it, Cp, diag, r, po, pn, q, sc_dev, c->partials);
-      if (e) check(hipEventRecord(e[1], s), "event");
-      launch_pass_b<T>(s, D, P, it, diag, pn, q, x, r, sc_dev, c->partials);
-      if (e) check(hipEventRecord(e[2], s), "event");
+      // every period-th iteration: each sweep's launch records its own start and end
+      hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[4 * (it / period - 1)] : nullptr;
+      launch_pass_a<T>(s, D, P, it, Cp, diag, r, po, pn, q, sc_dev, c->partials, e ? e[0] : nullptr,
+                       e ? e[1] : nullptr);
+      launch_pass_b<T>(s, D, P, it, diag, pn, q, x, r, sc_dev, c->partials, e ? e[2] : nullptr,
+                       e ? e[3] : nullptr);
     }
     launched += k;
     launch_check(s, P, launched, sc_dev, c->partials);
@@ -409,11 +409,11 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
   }
   if (period > 0) {
     // timed iterations that did work for at least one problem
-    for (int it = period; it <= max_done && 3 * (it / period) <= int(c->sweep_ev.size()); it += period) {
+    for (int it = period; it <= max_done && 4 * (it / period) <= int(c->sweep_ev.size()); it += period) {
       const int kk = it / period - 1;
       float ta = 0.f, tb = 0.f;
-      check(hipEventElapsedTime(&ta, c->sweep_ev[3 * kk], c->sweep_ev[3 * kk + 1]), "event");
-      check(hipEventElapsedTime(&tb, c->sweep_ev[3 * kk + 1], c->sweep_ev[3 * kk + 2]), "event");
+      check(hipEventElapsedTime(&ta, c->sweep_ev[4 * kk], c->sweep_ev[4 * kk + 1]), "event");
+      check(hipEventElapsedTime(&tb, c->sweep_ev[4 * kk + 2], c->sweep_ev[4 * kk + 3]), "event");
       ls->a_ms += ta;
       ls->b_ms += tb;
       ls->n_timed += 1;

@@ -131,13 +131,16 @@ template <typename T>
 void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const T* Cp, const T* diag,
                      const T* b, const T* x, T* r, T* p_clear, double* part);
 void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, PcgScalars* sc);
+// t0 / t1 (optional): events that the launch itself records when the kernel
+// starts and ends, so that they time the kernel alone.
 template <typename T>
 void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* Cp,
                    const T* diag, const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc,
-                   double* part);
+                   double* part, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 template <typename T>
 void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* diag,
-                   const T* p, const T* q, T* x, T* r, PcgScalars* sc, double* part);
+                   const T* p, const T* q, T* x, T* r, PcgScalars* sc, double* part,
+                   hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part);
 // All iterations of all problems in one cooperative launch (grid barrier between
 // sweeps); bar is the control buffer (kBarWords), P.done_count = bar + kBarDone;

@@ -12,6 +12,8 @@
 //
 // Partial buffer: [0, G) operator-sweep partial (p, q); [G, 4G) update-sweep
 // partials (r, z), ||r||^2, max relative change (also used by the start sweeps).
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "common.h"
@@ -273,7 +275,10 @@ __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int
         jv[u][a] = j;
         const bool inr = j >= s0 && j < s1;
         const int jo = inr ? ii[u] : j;  // no gather needed inside the range
-        cj[u][a] = Cp[size_t(a) * n + j];
+        // the coefficient of a -face lives at the neighbour; cells on the + side of
+        // their oct use their own (already loaded) coefficient instead
+        const int jc = ((pos >> a) & 1) ? ii[u] : j;
+        cj[u][a] = Cp[size_t(a) * n + jc];
         rj[u][a] = r[jo];
         dj[u][a] = diag[jo];
         pj[u][a] = p_old[jo];
@@ -717,16 +722,25 @@ void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, P
 
 template <typename T>
 void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* Cp, const T* diag,
-                   const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part) {
+                   const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part, hipEvent_t t0,
+                   hipEvent_t t1) {
   const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
-  hipLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), lds, s, L, P, it, Cp, diag, r, p_old, p_new, q, sc,
-                     part);
+  if (t0)
+    hipExtLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), uint32_t(lds), s, t0, t1, 0u, L, P, it, Cp, diag,
+                          r, p_old, p_new, q, sc, part);
+  else
+    hipLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), lds, s, L, P, it, Cp, diag, r, p_old, p_new, q, sc,
+                       part);
 }
 
 template <typename T>
 void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* diag, const T* p,
-                   const T* q, T* x, T* r, PcgScalars* sc, double* part) {
-  hipLaunchKernelGGL(k_pass_b<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, it, diag, p, q, x, r, sc, part);
+                   const T* q, T* x, T* r, PcgScalars* sc, double* part, hipEvent_t t0, hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_pass_b<T>, dim3(P.G), dim3(kBlock), 0u, s, t0, t1, 0u, L, P, it, diag, p, q, x, r, sc,
+                          part);
+  else
+    hipLaunchKernelGGL(k_pass_b<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, it, diag, p, q, x, r, sc, part);
 }
 
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part) {
@@ -829,13 +843,15 @@ template void launch_pcg_init<double>(hipStream_t, const DevLevel&, const SweepP
                                       double*);
 template void launch_pass_a<double>(hipStream_t, const DevLevel&, const SweepPlan&, int, const double*,
                                     const double*, const double*, const double*, double*, double*,
-                                    PcgScalars*, double*);
+                                    PcgScalars*, double*, hipEvent_t, hipEvent_t);
 template void launch_pass_b<double>(hipStream_t, const DevLevel&, const SweepPlan&, int, const double*,
-                                    const double*, const double*, double*, double*, PcgScalars*, double*);
+                                    const double*, const double*, double*, double*, PcgScalars*, double*,
+                                    hipEvent_t, hipEvent_t);
 template void launch_pass_a<float>(hipStream_t, const DevLevel&, const SweepPlan&, int, const float*,
                                    const float*, const float*, const float*, float*, float*, PcgScalars*,
-                                   double*);
+                                   double*, hipEvent_t, hipEvent_t);
 template void launch_pass_b<float>(hipStream_t, const DevLevel&, const SweepPlan&, int, const float*,
-                                   const float*, const float*, float*, float*, PcgScalars*, double*);
+                                   const float*, const float*, float*, float*, PcgScalars*, double*,
+                                   hipEvent_t, hipEvent_t);
 
 }  // namespace amrfld

@@ -5,7 +5,8 @@ device-to-device copy of a known size, whose FETCH_SIZE / WRITE_SIZE readings
 calibrate the per-dispatch HBM byte counters of the solver kernels.
 
 ``python -m paper_1401_1112_amd.profiling batch --patches 512 --steps 2 --mode polled``
-runs the batched workload alone (for kernel traces of the batch form).
+runs the batched workload alone (for kernel traces of the batch form);
+``... collapse --mode polled --precision mixed`` likewise the collapse-like hierarchy.
 
 ``python -m paper_1401_1112_amd.profiling summarize DIR`` prints a per-kernel
 summary (count, average duration, and the averages of any counters) from the
@@ -57,6 +58,43 @@ def run_batch(patches: int, steps: int, mode: str, per_cu: int) -> None:
     print(f"batch {mode}: {patches} patches, {steps} steps in {el:.3f} s, {ci / el:.3e} cell-iterations/s, "
           f"{st[0]['sweep_blocks']} sweep blocks, {st[0]['launch_blocks']} launch blocks", flush=True)
     bs.close()
+
+
+def run_collapse(steps: int, mode: str, precision: str) -> None:
+    """The collapse-like hierarchy (levels 6..13, ~41 M cells, coupled E-T): one warm-up
+    and `steps` timed coarse steps from the same state, host-polled or one persistent
+    launch per solve."""
+    import time
+
+    import torch
+
+    from synth.configs import config_collapse
+
+    from . import _lib as L
+    from .solver import solver_from_problem
+    p = config_collapse()
+    prec = L.MIXED if precision == "mixed" else L.FP64
+    s = solver_from_problem(p, precision=prec, persistent=(mode == "persistent"))
+    fields = {lv: tuple(t.clone() for t in s._fields[lv]) for lv in s.levels}
+
+    def step():
+        for lv in s.levels:
+            rho, E, T = fields[lv]
+            s.set_fields(lv, rho, E, T, kmode=1)
+        s.advance(p.dt_coarse, L.BC_DIRICHLET, p.tol)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    st = s.stats()
+    print(f"collapse {precision} {mode}: {el * 1e3:.1f} ms per coarse step, {len(st)} solves, "
+          f"{sum(x['iters'] for x in st)} PCG iterations, {sum(x['outer_iters'] for x in st)} refinement sweeps",
+          flush=True)
+    s.close()
 
 
 def _short(name: str) -> str:
@@ -113,8 +151,14 @@ def main(argv=None):
     b.add_argument("--steps", type=int, default=2)
     b.add_argument("--mode", choices=("polled", "persistent", "graph"), default="polled")
     b.add_argument("--per-cu", type=int, default=0)
+    cl = sub.add_parser("collapse")
+    cl.add_argument("--steps", type=int, default=1)
+    cl.add_argument("--mode", choices=("polled", "persistent"), default="polled")
+    cl.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     a = ap.parse_args(argv)
-    if a.cmd == "copy":
+    if a.cmd == "collapse":
+        run_collapse(a.steps, a.mode, a.precision)
+    elif a.cmd == "copy":
         run_copy(a.mib, a.reps)
     elif a.cmd == "batch":
         run_batch(a.patches, a.steps, a.mode, a.per_cu)

@@ -19,19 +19,20 @@ def test_tune_picks_fastest_and_caches(tmp_path, monkeypatch):
     applied = []
     cands = [{"max_blocks": b} for b in (256, 1024, 4096)]
     costs = {256: 3.0, 1024: 1.5, 4096: 2.0}
-    best, ms, cached = A.tune("k", cands, applied.append, lambda: None, timer=_fake_timer(costs), device="dev0")
-    assert best == {"max_blocks": 1024} and not cached
+    best, ms, src = A.tune("k", cands, applied.append, lambda: None, timer=_fake_timer(costs), device="dev0",
+                           arch="none")
+    assert best == {"max_blocks": 1024} and src == "timed"
     assert applied[-1] == best
     assert json.load(open(tmp_path / "tune.json"))["dev0|k"]["best"] == best
     # a second call returns the cached choice without timing
     def no_timer(*a):
         raise AssertionError("timed again")
-    best2, _, cached2 = A.tune("k", cands, applied.append, lambda: None, timer=no_timer, device="dev0")
-    assert best2 == best and cached2 and applied[-1] == best
+    best2, _, src2 = A.tune("k", cands, applied.append, lambda: None, timer=no_timer, device="dev0", arch="none")
+    assert best2 == best and src2 == "cache" and applied[-1] == best
     # another device or workload is timed anew
-    best3, _, cached3 = A.tune("k", cands, applied.append, lambda: None,
-                               timer=_fake_timer({256: 1.0, 1024: 2.0, 4096: 3.0}), device="dev1")
-    assert best3 == {"max_blocks": 256} and not cached3
+    best3, _, src3 = A.tune("k", cands, applied.append, lambda: None,
+                            timer=_fake_timer({256: 1.0, 1024: 2.0, 4096: 3.0}), device="dev1", arch="none")
+    assert best3 == {"max_blocks": 256} and src3 == "timed"
 
 
 def test_workload_key_separates_sizes_and_precision():
@@ -40,3 +41,31 @@ def test_workload_key_separates_sizes_and_precision():
     assert a != A.workload_key("batch", [8, 16, 34], 0)
     assert a != A.workload_key("batch", [8, 16, 32], 1)
     assert a != A.workload_key("levels", [8, 16, 32], 0)
+
+
+def test_shipped_table_applies_on_its_architecture(tmp_path, monkeypatch):
+    monkeypatch.setenv("AMRFLD_TUNE_CACHE", str(tmp_path / "tune.json"))
+    table = tmp_path / "shipped.json"
+    table.write_text(json.dumps({"arch": "gfx950", "entries": {"w": {"best": {"max_blocks": 512}, "ms": {}}}}))
+    monkeypatch.setattr(A, "SHIPPED", str(table))
+    applied = []
+
+    def no_timer(*a):
+        raise AssertionError("timed")
+    best, _, src = A.tune("w", [{"max_blocks": 512}], applied.append, lambda: None, timer=no_timer,
+                          device="d", arch="gfx950:sramecc+:xnack-")
+    assert best == {"max_blocks": 512} and src == "shipped" and applied == [best]
+    # another architecture, or another workload, is timed
+    best, _, src = A.tune("w", [{"max_blocks": 1024}], applied.append, lambda: None,
+                          timer=_fake_timer({1024: 1.0}), device="d", arch="gfx942")
+    assert src == "timed"
+
+
+def test_shipped_table_keys_match_the_benchmark_workloads():
+    # the shipped entries are keyed by the benchmark workloads' sizes
+    from synth.configs import patch_sizes
+    d = json.load(open(A.SHIPPED))
+    assert d["arch"] == "gfx950"
+    keys = set(d["entries"])
+    assert A.workload_key("levels", [262144, 1250000, 1250000, 1250000], 0) in keys
+    assert A.workload_key("batch", [int(max(2, n)) for n in patch_sizes(4000, 512)], 0) in keys
