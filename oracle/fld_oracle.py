@@ -28,6 +28,10 @@ What it computes (Commercon, Debout & Teyssier 2014):
   is restricted into the refined cells of its parent level.
 * Two-temperature coupling term kappa_P rho c (a T^4 - E) (Sect. 2.1), reduced
   to one equation in E by linearising the emission term in T.
+* For comparison, the unique-time-step method (Sect. 1, end of Sect. 3.1): all
+  levels coupled in one system advanced with the finest time step, a coarse
+  cell coupled to each finer cell of a refined neighbour's face with
+  2^(3-ndim) A / 3, rows scaled by the cell volume.
 * Levermore-Pomraning limited diffusivity ``K = c lambda(R) / (rho kappa_R)``
   with ``R = |grad E| / (rho kappa_R E)`` (Sect. 2.1).
 
@@ -344,6 +348,138 @@ class Oracle:
     def total_energy(self):
         """Sum of V E over the leaves of every level."""
         return float(sum(L.vol * self.E[l][L.leaf_slots].sum() for l, L in self.lev.items()))
+
+    # ------------------------------------------- unique time step (all levels coupled)
+    def composite_numbering(self):
+        """Offset of each level's leaves in the composite vector (levels base..max, leaves
+        in slot order) and the total count."""
+        off, n = {}, 0
+        for l in range(self.base, self.max_level + 1):
+            off[l] = n
+            n += len(self.lev[l].leaf_slots)
+        return off, n
+
+    def _facing_children(self, level, nb, d):
+        """Slots at level + 1 of the four children of the refined cells ``nb`` (level) that
+        lie on the face reached by crossing direction d from a neighbouring cell: for a
+        plus-side face (the refined cell lies at +axis) the children on its minus side."""
+        F = self.lev[level + 1]
+        axis, side = d >> 1, d & 1
+        cell = self.lev[level].cells[nb]
+        trans = [a for a in range(3) if a != axis]
+        out = []
+        for u in (0, 1):
+            for v in (0, 1):
+                off = np.zeros(3, dtype=np.int64)
+                off[trans[0]], off[trans[1]] = u, v
+                off[axis] = 0 if side == 1 else 1
+                out.append(F.lookup(2 * cell + off))
+        ch = np.stack(out, axis=1)
+        if np.any(ch < 0) or np.any(F.refined[ch]):
+            raise ValueError("a refined neighbour's facing children must be leaves (2:1 balance)")
+        return ch
+
+    def assemble_composite(self, dt):
+        """One system over the leaves of every level, all advanced by the same dt (the
+        unique-time-step method the paper compares with, Sect. 1; coefficients as in the
+        remark closing Sect. 3.1).  Same-level faces: C = A = K_f dt / dx^2.  A cell's face
+        towards a coarser leaf: C = (2/3) A (centres 3 dx / 2 apart).  A cell's face towards
+        a refined neighbour: the 2^(ndim-1) = 4 finer cells on that face are not
+        interpolated to the cell's level; each is coupled with C = 2^(3-ndim) A / 3 = A / 3
+        (ndim = 3), K_f taken with that finer cell.  Every row is multiplied by its cell
+        volume, which makes the matrix symmetric (V_f (2/3) A_f = V_c A_c / 3 for
+        dx_c = 2 dx_f).  Returns (A, b, coupling per level, level offsets)."""
+        off, n = self.composite_numbering()
+        K = {l: self.cell_K(l) for l in self.lev}
+        rows, cols, vals = [], [], []
+        b = np.empty(n)
+        couplings = {}
+        for l, L in self.lev.items():
+            leaves = L.leaf_slots
+            nl = len(leaves)
+            gi = off[l] + np.arange(nl)
+            coef = dt / (L.dx * L.dx)
+            diag = np.ones(nl)
+            bl = self.E[l][leaves].copy()
+            for d in range(6):
+                t = L.ftype[leaves, d]
+                nb = L.fnb[leaves, d]
+                m = t == SAME
+                C = harmonic_mean(K[l][leaves[m]], K[l][nb[m]]) * coef
+                diag[m] += C
+                rows.append(gi[m])
+                cols.append(off[l] + L.leaf_of[nb[m]])
+                vals.append(-L.vol * C)
+                m = t == F2C
+                if m.any():
+                    C = (2.0 / 3.0) * harmonic_mean(K[l][leaves[m]], K[l - 1][nb[m]]) * coef
+                    diag[m] += C
+                    rows.append(gi[m])
+                    cols.append(off[l - 1] + self.lev[l - 1].leaf_of[nb[m]])
+                    vals.append(-L.vol * C)
+                m = t == C2F
+                if m.any():
+                    ch = self._facing_children(l, nb[m], d)
+                    for k in range(4):
+                        f = ch[:, k]
+                        C = harmonic_mean(K[l][leaves[m]], K[l + 1][f]) * coef / 3.0
+                        diag[m] += C
+                        rows.append(gi[m])
+                        cols.append(off[l + 1] + self.lev[l + 1].leaf_of[f])
+                        vals.append(-L.vol * C)
+            if self.T.get(l) is not None:
+                T = self.T[l][leaves]
+                rho = self.rho[l][leaves]
+                eta = self.kappa_P * rho * self.c * dt
+                beta_T = 4.0 * self.a * T ** 3
+                denom = rho * self.c_v + eta * beta_T
+                f = eta * beta_T / denom
+                diag += eta * (1.0 - f)
+                bl += eta * (1.0 - f) * self.a * T ** 4
+                couplings[l] = (eta, denom)
+            rows.append(gi)
+            cols.append(gi)
+            vals.append(L.vol * diag)
+            b[gi] = L.vol * bl
+        A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+        A.sum_duplicates()
+        A.sort_indices()
+        return A, b, couplings, off
+
+    def solve_composite(self, dt, tol=1e-10, max_iter=None, solver="pcg"):
+        """Advance every level by dt in one composite solve; updates E (and T) of the
+        leaves, then restricts each level into its parent's refined cells, finest first."""
+        A, b, couplings, off = self.assemble_composite(dt)
+        x0 = np.concatenate([self.E[l][self.lev[l].leaf_slots] for l in sorted(self.lev)])
+        if solver == "dense":
+            x = dense_solve(A, b)
+            st = {"iters": 0, "converged": True}
+        else:
+            x, st = pcg_jacobi(A, b, x0, tol, self.max_iter if max_iter is None else max_iter,
+                               self.abs_floor, self.linf_test)
+        st.update(level=-1, dt=dt, n_leaf=len(x), true_res=float(np.linalg.norm(b - A @ x)),
+                  bnorm=float(np.linalg.norm(b)), min_E=float(x.min()) if len(x) else 0.0)
+        for l, L in self.lev.items():
+            xl = x[off[l]:off[l] + len(L.leaf_slots)]
+            if l in couplings:
+                eta, denom = couplings[l]
+                T = self.T[l][L.leaf_slots]
+                self.T[l][L.leaf_slots] = T + eta * (xl - self.a * T ** 4) / denom
+            self.E[l][L.leaf_slots] = xl
+        for l in range(self.max_level, self.base, -1):
+            self.restrict(l)
+        self.history.append(st)
+        return st
+
+    def advance_unique(self, dt, tol=1e-10):
+        """One coarse step dt with the unique time step of the finest level: as many
+        composite solves as the adaptive schedule makes solves of the finest level."""
+        n = 1
+        for l in range(self.base + 1, self.max_level + 1):
+            n *= int(self.nsub.get(l, 2))
+        for _ in range(n):
+            self.solve_composite(dt / n, tol)
+        return n
 
 
 def pcg_jacobi(A, b, x0, tol, max_iter, abs_floor=1e-14, linf_test=True):
