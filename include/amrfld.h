@@ -188,6 +188,21 @@ typedef struct {
 amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* patches, int n_steps,
                                  double tol, int precision, double* E_out);
 
+/* Advance every level by dt_coarse with one time step shared by all levels, the
+ * finest level's: the unique-time-step method the paper compares its adaptive one
+ * with (Sect. 1; coefficients of the remark closing Sect. 3.1).  n = product over
+ * the finer levels of nsub composite solves of dt_coarse / n, each a Jacobi-PCG over
+ * the leaves of all levels coupled in one system: same-level faces A, a face
+ * towards a coarser leaf (2/3) A, a face shared with a refined neighbour coupled to
+ * each of its four finer cells with 2^(3-ndim) A / 3; every row is multiplied by
+ * its cell volume, which makes the matrix symmetric (and the total energy exactly
+ * conserved with zero-flux outer faces).  After each solve T is updated and the
+ * finer levels are restricted into their parents.  Runs in FP64 with host-polled
+ * sweeps whatever opts.precision and opts.persistent say; no flux registers are
+ * involved.  Stats: one entry per composite solve, with level = -1.  Errors: as
+ * amrfld_advance_subcycled; E_STATE when T is set on some levels only. */
+amrfld_status amrfld_advance_unique(amrfld_ctx* c, double dt_coarse, double tol);
+
 /* Copy a level's E (and T when T_out is not NULL) to DEVICE arrays of n_slots
  * float64 in slot order (stream-ordered). */
 amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double* T_out);

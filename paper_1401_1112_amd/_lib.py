@@ -77,6 +77,7 @@ SIGNATURES = [
     ("amrfld_set_coeffs", _I, [_P, _I, _P, _P, _P, _D, _D, _D, _I, _D]),
     ("amrfld_solve_level", _I, [_P, _I, _D, _I, _D]),
     ("amrfld_advance_subcycled", _I, [_P, _D, _I, _D]),
+    ("amrfld_advance_unique", _I, [_P, _D, _D]),
     ("amrfld_solve_batch", _I, [_P, _I, ctypes.POINTER(amrfld_patch), _I, _D, _I, _P]),
     ("amrfld_get_E", _I, [_P, _I, _P, _P]),
     ("amrfld_last_stats", _I, [_P, ctypes.POINTER(amrfld_stats), _I, ctypes.POINTER(_I)]),
@@ -170,6 +171,10 @@ def amrfld_solve_level(ctx, level, dt, bc_mode, tol):
 
 def amrfld_advance_subcycled(ctx, dt, bc_mode, tol):
     return load().amrfld_advance_subcycled(ctx, float(dt), int(bc_mode), float(tol))
+
+
+def amrfld_advance_unique(ctx, dt, tol):
+    return load().amrfld_advance_unique(ctx, float(dt), float(tol))
 
 
 def amrfld_solve_batch(ctx, patches, n_steps, tol, precision, E_out):

@@ -150,6 +150,7 @@ struct amrfld_ctx {
   PcgScalars* h_sc = nullptr;   // pinned mirror
   int sc_cap = 0;
   struct BatchState* batch = nullptr;
+  struct CompositeState* comp = nullptr;  // unique-time-step system of all levels (built on first use)
   unsigned* bar = nullptr;  // grid barrier counter, generation, done counter, abort flag
   hipStream_t cap_stream = nullptr;  // library stream for graph capture (default priority)
   hipEvent_t cap_ev[2] = {nullptr, nullptr};
@@ -333,7 +334,7 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
                     T* const* p, T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
-  if (c->o.persistent) {
+  if (c->o.persistent && !D.cif) {
     // all iterations in one cooperative launch, when the device can run it
     const int per_cu = c->o.persistent_per_cu;
     if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
@@ -602,12 +603,204 @@ amrfld_status step(amrfld_ctx* c, int level, double dt, int mode, double tol) {
 
 }  // namespace
 
+// Concatenated slot space of all levels for the unique-time-step composite system:
+// each level's slots at a tile-aligned offset (padding slots are identity rows),
+// neighbour, coarse-neighbour and child tables in that space, the level of each oct.
+struct CompositeState {
+  std::vector<int64_t> off;  // slot offset of each level (index level - base)
+  int64_t n_slots = 0, n_oct = 0;
+  int n_levels = 0;
+  int32_t *nbr = nullptr, *cnb = nullptr, *child = nullptr, *lvl = nullptr;
+  PatchParams* pp = nullptr;
+  std::vector<PatchParams> pp_host;
+  double *x = nullptr, *K = nullptr, *rho = nullptr, *T = nullptr;
+  double *Cp = nullptr, *cif = nullptr, *diag = nullptr, *b = nullptr;
+  uint8_t* c2f = nullptr;
+
+  DevLevel dev() const {
+    DevLevel d;
+    d.n_slots = int(n_slots);
+    d.n_oct = int(n_oct);
+    d.nbr = nbr;
+    d.cnb = cnb;
+    d.child = child;
+    d.oct_prob = lvl;
+    d.pp = pp;
+    d.cif = cif;
+    d.c2f = c2f;
+    return d;
+  }
+  void release() {
+    for (void* p : {(void*)nbr, (void*)cnb, (void*)child, (void*)lvl, (void*)pp, (void*)x, (void*)K, (void*)rho,
+                    (void*)T, (void*)Cp, (void*)cif, (void*)diag, (void*)b, (void*)c2f})
+      dfree(p);
+  }
+};
+
 namespace {
 
 template <class T>
 void upload(amrfld_ctx* c, T** dst, const std::vector<T>& v, const char* what) {
   *dst = dalloc<T>(int64_t(v.size()), what);
   check(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream()), what);
+}
+
+// The composite slot space of the context's levels (rebuilt after a level changes).
+void build_composite(amrfld_ctx* c) {
+  if (c->comp) return;
+  CompositeState* C = new CompositeState();
+  c->comp = C;
+  const int base = c->o.base_level;
+  C->n_levels = c->finest - base + 1;
+  C->off.assign(C->n_levels + 1, 0);
+  for (int k = 0; k < C->n_levels; ++k) {
+    const int64_t ns = c->L(base + k).t.n_slots();
+    C->off[k + 1] = C->off[k] + (ns + kBlock - 1) / kBlock * kBlock;
+  }
+  C->n_slots = C->off[C->n_levels];
+  C->n_oct = C->n_slots / 8;
+  if (C->n_slots > int64_t(0x7fffffff)) throw std::invalid_argument("hierarchy too large for 32-bit slot indices");
+  std::vector<int32_t> nbr(6 * C->n_oct, -1), cnb(6 * C->n_oct, -1), child(C->n_slots, -2), lvl(C->n_oct, 0);
+  for (int k = 0; k < C->n_levels; ++k) {
+    const LevelTables& t = c->L(base + k).t;
+    const int64_t oo = C->off[k] / 8;
+    for (int64_t o = oo; o < C->off[k + 1] / 8; ++o) lvl[o] = k;
+    for (int64_t o = 0; o < t.n_oct; ++o) {
+      for (int d = 0; d < 6; ++d) {
+        const int32_t nb = t.nbr[o * 6 + d], cb = t.cnb[o * 6 + d];
+        nbr[(oo + o) * 6 + d] = nb >= 0 ? int32_t(oo + nb) : -1;
+        cnb[(oo + o) * 6 + d] = (cb >= 0 && k > 0) ? int32_t(C->off[k - 1] + cb) : -1;
+      }
+    }
+    for (int64_t i = 0; i < t.n_slots(); ++i) {
+      const int32_t ch = t.child[i];
+      child[C->off[k] + i] = (ch >= 0 && k + 1 < C->n_levels) ? int32_t(C->off[k + 1] / 8 + ch) : -1;
+    }
+  }
+  upload(c, &C->nbr, nbr, "composite tables");
+  upload(c, &C->cnb, cnb, "composite tables");
+  upload(c, &C->child, child, "composite tables");
+  upload(c, &C->lvl, lvl, "composite tables");
+  C->pp = dalloc<PatchParams>(C->n_levels, "composite parameters");
+  C->pp_host.assign(C->n_levels, PatchParams{});
+  const int64_t n = C->n_slots;
+  C->x = dalloc<double>(n, "composite fields");
+  C->K = dalloc<double>(n, "composite fields");
+  C->rho = dalloc<double>(n, "composite fields");
+  C->T = dalloc<double>(n, "composite fields");
+  C->Cp = dalloc<double>(3 * n, "composite system");
+  C->cif = dalloc<double>(3 * n, "composite system");
+  C->diag = dalloc<double>(n, "composite system");
+  C->b = dalloc<double>(n, "composite system");
+  C->c2f = dalloc<uint8_t>(n, "composite system");
+  launch_fill(c->stream(), C->x, n, 0.0);  // padding slots keep x = 0 (identity rows)
+  launch_fill(c->stream(), C->rho, n, 1.0);
+  launch_fill(c->stream(), C->T, n, 1.0);
+  check(hipStreamSynchronize(c->stream()), "composite tables");
+}
+
+// One composite solve: every level advanced by dt together.
+amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
+  const hipStream_t s = c->stream();
+  CompositeState& C = *c->comp;
+  const int base = c->o.base_level;
+  for (int k = 0; k < C.n_levels; ++k) upload_tables(c, c->L(base + k));
+  ensure_workspace(c, C.n_slots);
+  ensure_scalars(c, 1 + C.n_levels);
+  const bool coupled = c->L(base).has_T;
+  check(hipEventRecord(c->ev[0], s), "event");
+  for (int k = 0; k < C.n_levels; ++k) {
+    LevelState& L = c->L(base + k);
+    const double* Ec = k > 0 ? c->L(base + k - 1).E : nullptr;
+    launch_cell_K(s, L.dev(), L.E, L.rho, Ec, kparams(L), C.K + C.off[k]);
+    const size_t bytes = size_t(L.t.n_slots()) * sizeof(double);
+    check(hipMemcpyAsync(C.x + C.off[k], L.E, bytes, hipMemcpyDeviceToDevice, s), "gather");
+    check(hipMemcpyAsync(C.rho + C.off[k], L.rho, bytes, hipMemcpyDeviceToDevice, s), "gather");
+    if (coupled) check(hipMemcpyAsync(C.T + C.off[k], L.T, bytes, hipMemcpyDeviceToDevice, s), "gather");
+    const double dx = 1.0 / double(int64_t(1) << (base + k));
+    PatchParams& P = C.pp_host[k];
+    P.dx = dx;
+    P.vol = dx * dx * dx;
+    P.coef = dt / (dx * dx);
+  }
+  check(hipMemcpyAsync(C.pp, C.pp_host.data(), C.n_levels * sizeof(PatchParams), hipMemcpyHostToDevice, s),
+        "parameters");
+  CouplingParams cp = cparams(c, c->L(base));
+  cp.T = coupled ? C.T : nullptr;
+  const DevLevel D = C.dev();
+  launch_assemble_composite(s, D, C.K, C.x, C.rho, cp, dt, C.Cp, C.cif, C.c2f, C.diag, C.b);
+  const int n_tiles = tiles_of(C.n_slots);
+  const int B = c->o.max_blocks > 0 ? c->o.max_blocks : 1024;
+  const SweepPlan P = single_plan(sweep_blocks(n_tiles, B), n_tiles);
+  LoopStats ls;
+  ls.iters.assign(1, 0);
+  pcg_fp64(c, D, P, SolveArrays{C.Cp, C.diag, C.b, C.x, C.n_slots}, tol, &ls);
+  check(hipEventRecord(c->ev[2], s), "event");
+  if (c->o.true_residual) launch_true_residual(s, D, P, C.Cp, C.diag, C.b, C.x, c->sc, c->partials);
+  int64_t n_leaf = 0;
+  for (int k = 0; k < C.n_levels; ++k) {
+    LevelState& L = c->L(base + k);
+    check(hipMemcpyAsync(L.E, C.x + C.off[k], size_t(L.t.n_slots()) * sizeof(double), hipMemcpyDeviceToDevice, s),
+          "scatter");
+    const int tl = tiles_of(L.t.n_slots());
+    launch_post_solve(s, L.dev(), single_plan(sweep_blocks(tl, B), tl), L.E, L.rho, cparams(c, L), dt, L.T,
+                      c->sc + 1 + k, c->partials);
+    n_leaf += L.t.n_leaf;
+  }
+  for (int level = c->finest; level > base; --level) {
+    LevelState& F = c->L(level);
+    launch_restrict(s, F.dev(), F.E, c->L(level - 1).E);
+  }
+  check(hipEventRecord(c->ev[3], s), "event");
+  read_scalars(c, c->h_sc, c->sc, 1 + C.n_levels);
+  check(hipGetLastError(), "kernels");
+  const PcgScalars& h = c->h_sc[0];
+  amrfld_stats st{};
+  st.level = -1;
+  st.iters = h.iter;
+  st.converged = h.converged;
+  st.n_leaf = n_leaf;
+  st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
+  st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+  st.linf_change = h.linf;
+  st.min_E = c->h_sc[1].min_E;
+  for (int k = 1; k < C.n_levels; ++k) st.min_E = std::min(st.min_E, c->h_sc[1 + k].min_E);
+  st.dt = dt;
+  st.rnorm0 = h.rnorm0;
+  st.bnorm = h.bnorm;
+  st.sweep_blocks = P.G;
+  st.launch_blocks = P.G;
+  float ms = 0.f, pms = 0.f;
+  check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
+  check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
+  st.ms = ms;
+  st.pcg_ms = pms;
+  st.n_timed = ls.n_timed;
+  st.pass_a_ms = ls.a_ms;
+  st.pass_b_ms = ls.b_ms;
+  st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
+  c->stats.push_back(st);
+  if (st.status == AMRFLD_E_NONFINITE) return fail(c, AMRFLD_E_NONFINITE, "non-finite value in the composite residual");
+  if (st.status == AMRFLD_E_NOCONV) return fail(c, AMRFLD_E_NOCONV, "composite PCG did not converge within max_iter");
+  return AMRFLD_OK;
+}
+
+amrfld_status advance_unique(amrfld_ctx* c, double dt_coarse, double tol) {
+  int64_t n = 1;
+  for (int l = c->o.base_level + 1; l <= c->finest; ++l) n *= c->nsub(l);
+  if (n > (int64_t(1) << 20)) return fail(c, AMRFLD_E_INVALID, "too many unique time steps per coarse step");
+  const int base = c->o.base_level;
+  for (int l = base; l <= c->finest; ++l)
+    if (c->L(l).has_T != c->L(base).has_T)
+      return fail(c, AMRFLD_E_STATE, "T must be set on every level or on none");
+  build_composite(c);
+  amrfld_status worst = AMRFLD_OK;
+  for (int64_t k = 0; k < n; ++k) {
+    const amrfld_status st = solve_composite(c, dt_coarse / double(n), tol);
+    if (st != AMRFLD_OK && worst == AMRFLD_OK) worst = st;
+    if (st == AMRFLD_E_NONFINITE || st == AMRFLD_E_DEVICE) return st;
+  }
+  return worst;
 }
 
 // Morton-ordered octs of each patch, tile-aligned slot ranges (padding slots are
@@ -1005,6 +1198,10 @@ void amrfld_destroy(amrfld_ctx* c) {
     c->batch->release();
     delete c->batch;
   }
+  if (c->comp) {
+    c->comp->release();
+    delete c->comp;
+  }
   dfree(c->bar);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& e : c->cap_ev)
@@ -1045,6 +1242,11 @@ amrfld_status amrfld_build_level(amrfld_ctx* c, int level, int64_t n_oct, const 
     L.release();
     L.t = std::move(t);
     L.child_dirty = true;
+    if (c->comp) {  // the composite slot space no longer matches the levels
+      c->comp->release();
+      delete c->comp;
+      c->comp = nullptr;
+    }
     const int64_t n = L.t.n_slots();
     L.rho = dalloc<double>(n, "fields");
     L.E = dalloc<double>(n, "fields");
@@ -1135,6 +1337,19 @@ amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_m
   }
   c->stats.clear();
   return guarded(c, [&]() { return step(c, c->o.base_level, dt_coarse, bc_mode, tol); });
+}
+
+amrfld_status amrfld_advance_unique(amrfld_ctx* c, double dt_coarse, double tol) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (!(dt_coarse > 0.0) || !std::isfinite(dt_coarse)) return fail(c, AMRFLD_E_INVALID, "dt must be positive");
+  if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
+  if (c->finest < 0) return fail(c, AMRFLD_E_STATE, "no level built");
+  for (int l = c->o.base_level; l <= c->finest; ++l) {
+    const amrfld_status r = check_level_ready(c, l);
+    if (r != AMRFLD_OK) return r;
+  }
+  c->stats.clear();
+  return guarded(c, [&]() { return advance_unique(c, dt_coarse, tol); });
 }
 
 amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* patches, int n_steps,

@@ -184,6 +184,41 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned n_blocks, u
   return ok != 0;
 }
 
+// Couplings of slot ii to other levels in the composite system of all levels: its
+// out-of-oct faces that look at a coarser leaf, and the four finer cells on each
+// face shared with a refined same-level neighbour (their coefficients are stored
+// at the finer cells, so both rows of a pair read the same value).  Returns the
+// sum of coefficient x get(neighbour), to be subtracted from the row.
+template <typename T, class Get>
+__device__ __forceinline__ T interface_terms(int ii, const DevLevel& L, int n, Get get) {
+  const int pos = ii & 7, o = ii >> 3;
+  T s = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T cf = T(L.cif[size_t(a) * n + ii]);
+    if (cf != T(0)) {
+      const int my = (pos >> a) & 1;
+      s += cf * get(L.cnb[o * 6 + 2 * a + my]);
+    }
+  }
+  const unsigned m = L.c2f[ii];
+  if (m) {
+    for (int d = 0; d < 6; ++d) {
+      if (!((m >> d) & 1)) continue;
+      const int a = d >> 1, side = d & 1;
+      const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+      const int co = L.child[same_level_nb(L.nbr, ii, d)];
+      const int fb = side ? 0 : 1;  // the finer cells on the side that faces ii
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int f = (co << 3) | (fb << a) | ((k & 1) << t0) | ((k >> 1) << t1);
+        s += T(L.cif[size_t(a) * n + f]) * get(f);
+      }
+    }
+  }
+  return s;
+}
+
 // The 7-point operator at slot ii applied to a vector whose value at ii is pi
 // and at other slots is get(j).  T is the storage and arithmetic type.
 template <typename T, class Get>

@@ -58,8 +58,16 @@ struct DevLevel {
   const int32_t* child = nullptr;     // [n_slots]
   const int32_t* parent = nullptr;    // [n_oct]
   double dx = 1.0, vol = 1.0;
-  const int32_t* oct_prob = nullptr;  // batch: patch of each oct (nullptr for a level)
-  const PatchParams* pp = nullptr;    // batch: per-patch parameters (nullptr for a level)
+  const int32_t* oct_prob = nullptr;  // batch: patch of each oct; composite: level of each oct
+  const PatchParams* pp = nullptr;    // batch: per-patch parameters; composite: per-level dx, vol, coef
+  // Composite system of all levels (unique time step), else nullptr: cif[a * n + i]
+  // is the volume-scaled coefficient of slot i's out-of-oct face on axis a when that
+  // face looks at a coarser leaf (0 otherwise); bit d of c2f[i] is set when the
+  // same-level neighbour in direction d is refined, whose four finer cells on that
+  // face are then coupled to i with their own cif.  nbr, cnb and child then hold
+  // indices into the concatenated slot space of all levels.
+  const double* cif = nullptr;
+  const uint8_t* c2f = nullptr;
 };
 
 // How the blocks of a sweep are spread over independent problems (a level is
@@ -111,6 +119,13 @@ void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const do
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
                      double dt, double w, double alpha, const CouplingParams& cp, double* Cp,
                      double* diag, double* b);
+// Composite system of all levels advanced with one dt (unique time step): per slot
+// the volume-scaled same-level coefficients Cp, interface coefficients cif, the
+// refined-neighbour mask c2f, diagonal and right-hand side; E is the concatenated
+// energy, K the concatenated diffusivity of every level.
+void launch_assemble_composite(hipStream_t s, const DevLevel& C, const double* K, const double* E,
+                               const double* rho, const CouplingParams& cp, double dt, double* Cp, double* cif,
+                               uint8_t* c2f, double* diag, double* b);
 void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, const double* K_c,
                           const double* E_f, const double* E_c, double dt, double* reg_c,
                           int n_slots_c);

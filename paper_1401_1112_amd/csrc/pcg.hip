@@ -15,6 +15,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -122,7 +123,8 @@ __device__ __forceinline__ void body_pcg_init(int vb, DevLevel L, SweepPlan P, c
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
     const T di = diag[ii];
-    const T ax = apply_stencil<T>(ii, L.nbr, Cp, n, di, x[ii], [&](int j) { return x[j]; });
+    T ax = apply_stencil<T>(ii, L.nbr, Cp, n, di, x[ii], [&](int j) { return x[j]; });
+    if (L.cif) ax -= dev::interface_terms<T>(ii, L, n, [&](int j) { return x[j]; });
     if (valid) {
       const T ri = b[i] - ax;
       r[i] = ri;
@@ -130,7 +132,9 @@ __device__ __forceinline__ void body_pcg_init(int vb, DevLevel L, SweepPlan P, c
       const double rd = double(ri);
       v[0] += rd * double(ri / di);
       v[1] += rd * rd;
-      v[2] += double(b[i]) * double(b[i]);
+      // ||b|| over the unknowns only: identity rows (refined and padding slots) hold
+      // b = E there, which is no part of the system
+      if (L.child[i] == -1) v[2] += double(b[i]) * double(b[i]);
     }
   }
   const bool mx[3] = {false, false, false};
@@ -175,7 +179,7 @@ __device__ __forceinline__ void body_init_finish(int prob, SweepPlan P, const do
 // cross-lane shuffle, out-of-oct neighbours inside the range from LDS, and the
 // rest recomputed from r, d and p_{it-1} in global memory (the two p buffers
 // alternate, so p_{it-1} is never overwritten during the sweep).
-template <typename T>
+template <typename T, bool COMP>
 __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int it,
                                                    const T* __restrict__ Cp, const T* __restrict__ diag,
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
@@ -310,6 +314,15 @@ __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int
           acc -= c_out * pn;
         }
       }
+      if constexpr (COMP) {  // couplings to the other levels of the composite system
+        if (valid[u]) {
+          acc -= dev::interface_terms<T>(ii[u], L, n, [&](int j) -> T {
+            if (j >= s0 && j < s1) return pl[j - s0];
+            const T z = r[j] / diag[j];
+            return first ? z : fma(tb, p_old[j], z);
+          });
+        }
+      }
       if (valid[u]) {
         q[ii[u]] = acc;
         v[0] += double(pi) * double(acc);
@@ -417,7 +430,8 @@ __device__ __forceinline__ void body_true_residual(int vb, DevLevel L, SweepPlan
     const int i = t * kBlock + int(threadIdx.x);
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
-    const double ax = apply_stencil<double>(ii, L.nbr, Cp, n, diag[ii], x[ii], [&](int j) { return x[j]; });
+    double ax = apply_stencil<double>(ii, L.nbr, Cp, n, diag[ii], x[ii], [&](int j) { return x[j]; });
+    if (L.cif) ax -= dev::interface_terms<double>(ii, L, n, [&](int j) { return x[j]; });
     if (valid) {
       const double ri = b[i] - ax;
       v[0] += ri * ri;
@@ -495,7 +509,7 @@ __device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, c
       x_new[i] = xi;
       r32[i] = float(ri);
       v[0] += ri * ri;
-      v[1] += b[i] * b[i];
+      if (L.child[i] == -1) v[1] += b[i] * b[i];  // ||b|| over the unknowns only
       if (d) v[2] = fmax(v[2], rel_change(x_old[i], double(d[i])));
     }
   }
@@ -594,7 +608,18 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int 
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
                                                    T* __restrict__ p_new, T* __restrict__ q,
                                                    PcgScalars* scs, double* part) {
-  body_pass_a<T>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
+  body_pass_a<T, false>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
+}
+
+// The operator sweep of the composite system of all levels (FP64).
+__global__ __launch_bounds__(kBlock) void k_pass_a_composite(DevLevel L, SweepPlan P, int it,
+                                                             const double* __restrict__ Cp,
+                                                             const double* __restrict__ diag,
+                                                             const double* __restrict__ r,
+                                                             const double* __restrict__ p_old,
+                                                             double* __restrict__ p_new, double* __restrict__ q,
+                                                             PcgScalars* scs, double* part) {
+  body_pass_a<double, true>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
 }
 
 template <typename T>
@@ -671,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan
     T* pn = (it & 1) ? p1 : p0;
     const T* po = (it & 1) ? p0 : p1;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
-      body_pass_a<T>(vb, L, P, it, Cp, diag, r, po, pn, q, scs, part);
+      body_pass_a<T, false>(vb, L, P, it, Cp, diag, r, po, pn, q, scs, part);
     if (!grid_barrier(bar, nb, epoch, spin_limit)) {
       if (threadIdx.x == 0) __hip_atomic_store(bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
@@ -725,6 +750,17 @@ void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it,
                    const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part, hipEvent_t t0,
                    hipEvent_t t1) {
   const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
+  if constexpr (std::is_same<T, double>::value) {
+    if (L.cif) {  // composite system of all levels
+      if (t0)
+        hipExtLaunchKernelGGL(k_pass_a_composite, dim3(P.G), dim3(kBlock), uint32_t(lds), s, t0, t1, 0u, L, P, it,
+                              Cp, diag, r, p_old, p_new, q, sc, part);
+      else
+        hipLaunchKernelGGL(k_pass_a_composite, dim3(P.G), dim3(kBlock), lds, s, L, P, it, Cp, diag, r, p_old,
+                           p_new, q, sc, part);
+      return;
+    }
+  }
   if (t0)
     hipExtLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), uint32_t(lds), s, t0, t1, 0u, L, P, it, Cp, diag,
                           r, p_old, p_new, q, sc, part);

@@ -129,6 +129,81 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
   b[i] = bb;
 }
 
+// Composite system (unique time step): rows of every level's leaves multiplied by
+// the cell volume.  Same-level faces C = A = K_f dt / dx^2; a face towards a coarser
+// leaf C = (2/3) A; a face shared with a refined same-level neighbour couples to its
+// four finer cells, each with 2^(3-ndim) A / 3 = A / 3 (K_f with that finer cell).
+// The coefficient of a fine-to-coarse pair is stored once, at the finer cell
+// (V_f (2/3) A_f, equal to V_c A_c / 3), and read by both rows.
+__global__ __launch_bounds__(kBlock) void k_assemble_composite(
+    DevLevel L, const double* __restrict__ K, const double* __restrict__ E, const double* __restrict__ rho,
+    CouplingParams cp, double dt, double* __restrict__ Cp, double* __restrict__ cif, uint8_t* __restrict__ c2f,
+    double* __restrict__ diag, double* __restrict__ b) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int n = L.n_slots;
+  if (i >= n) return;
+  if (L.child[i] != -1) {  // refined or padding slot: identity row, r stays 0
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cp[size_t(a) * n + i] = 0.0;
+      cif[size_t(a) * n + i] = 0.0;
+    }
+    c2f[i] = 0;
+    diag[i] = 1.0;
+    b[i] = E[i];
+    return;
+  }
+  const PatchParams& P = L.pp[L.oct_prob[i >> 3]];
+  const double coef = P.coef, V = P.vol, Ki = K[i];
+  double d = 1.0, bb = E[i];
+  double cplus[3] = {0.0, 0.0, 0.0}, cf[3] = {0.0, 0.0, 0.0};
+  unsigned mask = 0;
+  for (int dir = 0; dir < 6; ++dir) {
+    const int a = dir >> 1, side = dir & 1;
+    const int j = same_level_nb(L.nbr, i, dir);
+    if (j >= 0) {
+      const int co = L.child[j];
+      if (co >= 0) {  // refined neighbour: its four finer cells on the shared face
+        mask |= 1u << dir;
+        const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+        const int fb = side ? 0 : 1;
+        for (int k = 0; k < 4; ++k) {
+          const int f = (co << 3) | (fb << a) | ((k & 1) << t0) | ((k >> 1) << t1);
+          d += harmonic(Ki, K[f]) * coef / 3.0;
+        }
+      } else {
+        const double C = harmonic(Ki, K[j]) * coef;
+        d += C;
+        if (side) cplus[a] = V * C;
+      }
+    } else {
+      const int c = L.cnb[(i >> 3) * 6 + dir];
+      if (c >= 0) {  // coarser leaf, centre distance 3 dx / 2
+        const double C = (2.0 / 3.0) * harmonic(Ki, K[c]) * coef;
+        d += C;
+        cf[a] = V * C;
+      }
+    }
+  }
+  if (cp.T) {  // linearised coupling term kappa_P rho c (a T^4 - E)
+    const double T = cp.T[i], r = rho[i];
+    const double eta = cp.kappa_P * r * cp.c_light * dt;
+    const double bT = 4.0 * cp.a_rad * T * T * T;
+    const double den = r * cp.c_v + eta * bT;
+    const double f = eta * bT / den;
+    d += eta * (1.0 - f);
+    bb += eta * (1.0 - f) * cp.a_rad * (T * T * T * T);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Cp[size_t(a) * n + i] = cplus[a];
+    cif[size_t(a) * n + i] = cf[a];
+  }
+  c2f[i] = uint8_t(mask);
+  diag[i] = V * d;
+  b[i] = V * bb;
+}
+
 // One thread per (fine oct, direction): the four cells of that oct face that
 // see a coarser leaf add their energy gain V C (E_c - E_i) (eq. mean_flux with
 // dt inside C) to the register of that coarse cell, on its face looking back.
@@ -228,6 +303,13 @@ void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const do
   const double coef = dt / (L.dx * L.dx);
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, K, K_coarse, E,
                      E_coarse, rho, reg, coef, w, alpha, cp, dt, Cp, diag, b);
+}
+
+void launch_assemble_composite(hipStream_t s, const DevLevel& C, const double* K, const double* E,
+                               const double* rho, const CouplingParams& cp, double dt, double* Cp, double* cif,
+                               uint8_t* c2f, double* diag, double* b) {
+  hipLaunchKernelGGL(k_assemble_composite, dim3(grid_for(C.n_slots)), dim3(kBlock), 0, s, C, K, E, rho, cp, dt, Cp,
+                     cif, c2f, diag, b);
 }
 
 void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, const double* K_c,

@@ -98,6 +98,14 @@ class HierarchySolver:
             self._check(st)
         return st
 
+    def advance_unique(self, dt, tol=1e-10, raise_on_error=True):
+        """One coarse step with the unique time step of the finest level (all levels in
+        one composite system per fine step)."""
+        st = L.amrfld_advance_unique(self.ctx, dt, tol)
+        if raise_on_error and st != L.OK:
+            self._check(st)
+        return st
+
     def E(self, level, with_T=False):
         ns, _ = self.info(level)
         e = torch.empty(ns, dtype=torch.float64, device=self.device)

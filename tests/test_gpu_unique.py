@@ -1,0 +1,148 @@
+"""The unique-time-step composite solve on the GPU (amrfld_advance_unique) against the
+oracle's: all levels coupled in one volume-scaled system advanced with the finest step.
+
+Bar: per level E (and T) within 1e-12 relative L2 with equal iteration counts (a near-tie
+of a residual with its threshold falls back to fixed counts, tol = 0); on one level the
+composite solve equals the level solve bitwise (the volume scaling is an exact power of
+two); the total energy is conserved to the solver tolerance, also at the benchmark size.
+"""
+import numpy as np
+import pytest
+
+from _util import align, oracle_from_problem
+from synth.configs import config_collapse, config_fld_lognormal, config_heat_gaussian, config_tiny, config_uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _fields(s, p):
+    from paper_1401_1112_amd.solver import to_numpy
+    out = {}
+    for l in p.hierarchy.levels:
+        if p.T is not None:
+            e, t = s.E(l, with_T=True)
+            out[l] = (to_numpy(e), to_numpy(t), s.cells(l))
+        else:
+            out[l] = (to_numpy(s.E(l)), None, s.cells(l))
+    return out
+
+
+def _run_pair(p, steps, tol, max_iter):
+    from paper_1401_1112_amd.solver import solver_from_problem
+    s = solver_from_problem(p, max_iter=max_iter)
+    o = oracle_from_problem(p, max_iter=max_iter)
+    counts = []
+    for _ in range(steps):
+        start = len(o.history)
+        s.advance_unique(p.dt_coarse, tol, raise_on_error=False)
+        o.advance_unique(p.dt_coarse, tol)
+        counts.append(([x["iters"] for x in s.stats()], [h["iters"] for h in o.history[start:]]))
+    g = _fields(s, p)
+    s.close()
+    worst = 0.0
+    for l in p.hierarchy.levels:
+        e, t, c = g[l]
+        worst = max(worst, _rel(e, align(l, o.cells(l), o.E[l], c)))
+        if t is not None:
+            worst = max(worst, _rel(t, align(l, o.cells(l), o.T[l], c)))
+    return counts, worst
+
+
+def _parity(p, steps):
+    counts, worst = _run_pair(p, steps, p.tol, p.max_iter)
+    print(f"{p.name}: counts {counts}; worst relative L2 {worst:.3e}")
+    if all(g == o for g, o in counts):
+        assert worst <= 1e-12
+        return
+    n_fix = max(max(g + o) for g, o in counts)
+    counts2, worst2 = _run_pair(p, steps, 0.0, n_fix)
+    assert all(g == o for g, o in counts2)
+    assert worst2 <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+@pytest.mark.parametrize("kmode", ["lp", "const"])
+def test_unique_parity_tiny(seed, kmode):
+    _parity(config_tiny(seed, base_level=3, max_level=5, p_refine=0.5, kmode=kmode, tol=1e-12), 2)
+
+
+def test_unique_parity_heat_gaussian():
+    _parity(config_heat_gaussian(n_coarse_steps=2), 2)
+
+
+def test_unique_parity_coupled_collapse():
+    _parity(config_collapse(base_level=3, max_level=7, jeans=2.5, contrast=1e4, field_n=64, shared_dt_levels=2), 1)
+
+
+def test_unique_on_one_level_is_the_level_solve_bitwise():
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    p = config_uniform(5, kmode="lp", seed=4)
+    a = solver_from_problem(p)
+    b = solver_from_problem(p)
+    a.advance_unique(p.dt_coarse, 1e-12)
+    b.advance(p.dt_coarse, BC_DIRICHLET, 1e-12)
+    assert [x["iters"] for x in a.stats()] == [x["iters"] for x in b.stats()]
+    assert a.stats()[0]["level"] == -1
+    assert np.array_equal(to_numpy(a.E(5)), to_numpy(b.E(5)))
+    a.close()
+    b.close()
+
+
+def _total_energy(s, p):
+    from paper_1401_1112_amd.solver import to_numpy
+    tot = 0.0
+    for l in p.hierarchy.levels:
+        e = to_numpy(s.E(l))
+        c = s.cells(l)
+        leaf = np.ones(len(c), dtype=bool)
+        if l + 1 in p.hierarchy.octs:
+            par = np.asarray(p.hierarchy.octs[l + 1], dtype=np.int64)
+            n = np.int64(1) << l
+            kc = (c[:, 0].astype(np.int64) * n + c[:, 1]) * n + c[:, 2]
+            kp = (par[:, 0] * n + par[:, 1]) * n + par[:, 2]
+            leaf = ~np.isin(kc, kp)
+        tot += float(e[leaf].sum()) / float(1 << (3 * l))
+    return tot
+
+
+def test_unique_conserves_total_energy():
+    from paper_1401_1112_amd.solver import solver_from_problem
+    p = config_tiny(1, base_level=3, max_level=5, p_refine=0.5, kmode="lp")
+    s = solver_from_problem(p, abs_floor=0.0)
+    e0 = _total_energy(s, p)
+    s.advance_unique(p.dt_coarse, 1e-13)
+    assert abs(_total_energy(s, p) - e0) <= 1e-12 * abs(e0)
+    s.close()
+
+
+def test_unique_full_size_lognormal():
+    # the benchmark hierarchy (4.0 M cells), one coarse step = 8 composite solves: every
+    # solve meets its threshold on the true residual, the zero-flux outer boundary keeps
+    # the total energy, and the result stays close to the adaptive step's
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    p = config_fld_lognormal()
+    s = solver_from_problem(p)
+    e0 = _total_energy(s, p)
+    s.advance_unique(p.dt_coarse, p.tol)
+    st = s.stats()
+    assert len(st) == 8
+    for x in st:
+        thr = max(p.tol * x["rnorm0"], p.abs_floor * x["bnorm"])
+        assert x["converged"] == 1 and x["true_rel_res"] * x["rnorm0"] <= 1.05 * thr, x
+    e1 = _total_energy(s, p)
+    assert abs(e1 - e0) <= 1e-9 * abs(e0)
+    u = {l: to_numpy(s.E(l)) for l in p.hierarchy.levels}
+    s.close()
+    a = solver_from_problem(p)
+    a.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+    for l in p.hierarchy.levels:
+        d = _rel(u[l], to_numpy(a.E(l)))
+        print(f"level {l}: unique vs adaptive relative L2 {d:.2e}")
+        assert d < 0.1
+    a.close()
