@@ -179,6 +179,45 @@ def _mixed_form(p, s64, init, ms64, args):
     return out
 
 
+def _unique_form(p, s, init, ms_ats, args):
+    """The comparison the paper makes: the same coarse step with the unique time step of
+    the finest level, all levels coupled in one composite system per fine step (8 solves
+    over all 4.0 M cells), against the adaptive level-by-level step (15 level solves)."""
+    import torch
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import to_numpy
+
+    def reset():
+        for lvl in s.levels:
+            rho, E = init[lvl]
+            s.set_fields(lvl, rho, E, kmode=1)
+
+    reset()
+    s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+    ats = {l: to_numpy(s.E(l)) for l in s.levels}
+    reset()
+    s.advance_unique(p.dt_coarse, p.tol)  # warm-up (composite tables and workspace)
+    steps = max(1, min(args.steps, 3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = []
+    for _ in range(steps):
+        reset()
+        s.advance_unique(p.dt_coarse, p.tol)
+        sts.append(s.stats())
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    st = sts[-1]
+    dtu = {l: to_numpy(s.E(l)) for l in s.levels}
+    diff = max(_rel_err(dtu[l], ats[l])[1] for l in s.levels)
+    ci = sum(x["n_leaf"] * x["iters"] for x in st)
+    return {"ms_per_step": round(el * 1e3, 2), "composite_solves": len(st),
+            "pcg_iterations": sum(x["iters"] for x in st), "cells_per_solve": st[0]["n_leaf"],
+            "cell_iterations_per_s": ci / el, "residual": _residual_gate(st, p.tol),
+            "adaptive_ms_per_step": round(ms_ats, 2), "adaptive_speedup": el * 1e3 / ms_ats,
+            "rel_l2_unique_vs_adaptive": diff}
+
+
 def _batched_form(args):
     """The batching form: independent patches with log-uniform sizes 8^3..128^3, own
     log-normal density, mixed Dirichlet / Neumann / Robin faces, 16 backward-Euler steps,
@@ -344,6 +383,29 @@ def _collapse_form(args):
                      "launch_modes": sorted({x["launch_mode"] for x in st}),
                      "residual": _residual_gate(st, p.tol), "min_E": min(x["min_E"] for x in st)}
         s.close()
+    if not args.no_unique:
+        # the same coarse step with the unique time step of level 13 (16 composite solves)
+        print("bench: collapse form unique_fp64", file=sys.stderr, flush=True)
+        u = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=FP64, nsub=p.nsub,
+                            max_blocks=args.max_blocks)
+        reset(u)
+        u.advance_unique(p.dt_coarse, p.tol)
+        reset(u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u.advance_unique(p.dt_coarse, p.tol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = u.stats()
+        ref64 = results["fp64_polled"]
+        out["unique_fp64"] = {
+            "ms_per_step": round(el * 1e3, 1), "composite_solves": len(st),
+            "pcg_iterations": sum(x["iters"] for x in st), "residual": _residual_gate(st, p.tol),
+            "cell_iterations_per_s": sum(x["n_leaf"] * x["iters"] for x in st) / el,
+            "adaptive_fp64_speedup": el * 1e3 / out["fp64_polled"]["ms_per_step"],
+            "rel_l2_vs_adaptive_fp64": max(float(torch.linalg.vector_norm(u.E(l) - ref64[l][0])
+                                                 / torch.linalg.vector_norm(ref64[l][0])) for l in u.levels)}
+        u.close()
     ref = results["fp64_polled"]
     for name in ("mixed_persistent", "mixed_polled"):
         worst_e = max(float(torch.linalg.vector_norm(results[name][l][0] - ref[l][0])
@@ -368,6 +430,7 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--max-blocks", type=int, default=0, help="blocks per PCG sweep (0: library default)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
+    ap.add_argument("--no-unique", action="store_true", help="skip the unique-time-step comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-patches", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=16)
@@ -477,6 +540,8 @@ def main(argv=None):
         "cpu_baseline": None,
     }
     out["forms"] = {}
+    if not args.no_unique:
+        out["forms"]["unique_time_step"] = _unique_form(p, s, init, elapsed * 1e3 / args.steps, args)
     if not args.no_mixed:
         out["forms"]["mixed"] = _mixed_form(p, s, init, elapsed * 1e3 / args.steps, args)
     s.close()

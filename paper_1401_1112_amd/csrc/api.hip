@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -380,6 +381,9 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
       hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[4 * (it / period - 1)] : nullptr;
       launch_pass_a<T>(s, D, P, it, Cp, diag, r, po, pn, q, sc_dev, c->partials, e ? e[0] : nullptr,
                        e ? e[1] : nullptr);
+      if constexpr (std::is_same<T, double>::value) {
+        if (D.n_if_rows > 0) launch_interface(s, D, pn, q, sc_dev, D.if_part);
+      }
       launch_pass_b<T>(s, D, P, it, diag, pn, q, x, r, sc_dev, c->partials, e ? e[2] : nullptr,
                        e ? e[3] : nullptr);
     }
@@ -616,6 +620,10 @@ struct CompositeState {
   double *x = nullptr, *K = nullptr, *rho = nullptr, *T = nullptr;
   double *Cp = nullptr, *cif = nullptr, *diag = nullptr, *b = nullptr;
   uint8_t* c2f = nullptr;
+  // rows coupled to other levels: row, entry range, column, coefficient index into cif
+  int n_if_rows = 0, n_if_entries = 0;
+  int32_t *if_row = nullptr, *if_ptr = nullptr, *if_col = nullptr, *if_src = nullptr;
+  double *if_val = nullptr, *if_part = nullptr;
 
   DevLevel dev() const {
     DevLevel d;
@@ -628,11 +636,19 @@ struct CompositeState {
     d.pp = pp;
     d.cif = cif;
     d.c2f = c2f;
+    d.n_if_rows = n_if_rows;
+    d.if_row = if_row;
+    d.if_ptr = if_ptr;
+    d.if_col = if_col;
+    d.if_src = if_src;
+    d.if_val = if_val;
+    d.if_part = if_part;
     return d;
   }
   void release() {
     for (void* p : {(void*)nbr, (void*)cnb, (void*)child, (void*)lvl, (void*)pp, (void*)x, (void*)K, (void*)rho,
-                    (void*)T, (void*)Cp, (void*)cif, (void*)diag, (void*)b, (void*)c2f})
+                    (void*)T, (void*)Cp, (void*)cif, (void*)diag, (void*)b, (void*)c2f, (void*)if_row,
+                    (void*)if_ptr, (void*)if_col, (void*)if_src, (void*)if_val, (void*)if_part})
       dfree(p);
   }
 };
@@ -677,10 +693,63 @@ void build_composite(amrfld_ctx* c) {
       child[C->off[k] + i] = (ch >= 0 && k + 1 < C->n_levels) ? int32_t(C->off[k + 1] / 8 + ch) : -1;
     }
   }
+  // rows with couplings to other levels: faces towards a coarser leaf, and the four
+  // finer cells of each face shared with a refined same-level neighbour
+  std::vector<int32_t> if_row, if_ptr(1, 0), if_col, if_src;
+  const int64_t n3 = C->n_slots;
+  for (int k = 0; k < C->n_levels; ++k) {
+    const LevelTables& t = c->L(base + k).t;
+    for (int64_t i = 0; i < t.n_slots(); ++i) {
+      if (t.child[i] != -1) continue;
+      const int pos = int(i & 7);
+      const int64_t o = i >> 3, gi = C->off[k] + i;
+      const size_t before = if_col.size();
+      for (int a = 0; a < 3 && k > 0; ++a) {
+        const int d = 2 * a + ((pos >> a) & 1);
+        if (t.nbr[o * 6 + d] < 0 && t.cnb[o * 6 + d] >= 0) {
+          if_col.push_back(int32_t(C->off[k - 1] + t.cnb[o * 6 + d]));
+          if_src.push_back(int32_t(a * n3 + gi));
+        }
+      }
+      for (int d = 0; d < 6 && k + 1 < C->n_levels; ++d) {
+        const int a = d >> 1, side = d & 1, bit = 1 << a;
+        int64_t j = -1;
+        if (((pos >> a) & 1) != side) {
+          j = i ^ bit;
+        } else if (t.nbr[o * 6 + d] >= 0) {
+          j = (int64_t(t.nbr[o * 6 + d]) << 3) | (pos ^ bit);
+        }
+        if (j < 0 || t.child[j] < 0) continue;
+        const int64_t co = C->off[k + 1] / 8 + t.child[j];
+        const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2, fb = side ? 0 : 1;
+        for (int q = 0; q < 4; ++q) {
+          const int64_t f = (co << 3) | (fb << a) | ((q & 1) << t0) | ((q >> 1) << t1);
+          if_col.push_back(int32_t(f));
+          if_src.push_back(int32_t(a * n3 + f));
+        }
+      }
+      if (if_col.size() > before) {
+        if_row.push_back(int32_t(gi));
+        if_ptr.push_back(int32_t(if_col.size()));
+      }
+    }
+  }
+  if (3 * n3 > int64_t(0x7fffffff) || if_col.size() > size_t(0x7fffffff))
+    throw std::invalid_argument("hierarchy too large for 32-bit interface indices");
+  C->n_if_rows = int(if_row.size());
+  C->n_if_entries = int(if_col.size());
   upload(c, &C->nbr, nbr, "composite tables");
   upload(c, &C->cnb, cnb, "composite tables");
   upload(c, &C->child, child, "composite tables");
   upload(c, &C->lvl, lvl, "composite tables");
+  if (!if_row.empty()) {
+    upload(c, &C->if_row, if_row, "composite interfaces");
+    upload(c, &C->if_ptr, if_ptr, "composite interfaces");
+    upload(c, &C->if_col, if_col, "composite interfaces");
+    upload(c, &C->if_src, if_src, "composite interfaces");
+  }
+  C->if_part = dalloc<double>(std::max(1, (C->n_if_rows + kBlock - 1) / kBlock), "composite interfaces");
+  if (C->n_if_entries > 0) C->if_val = dalloc<double>(C->n_if_entries, "composite interfaces");
   C->pp = dalloc<PatchParams>(C->n_levels, "composite parameters");
   C->pp_host.assign(C->n_levels, PatchParams{});
   const int64_t n = C->n_slots;
@@ -729,9 +798,14 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   cp.T = coupled ? C.T : nullptr;
   const DevLevel D = C.dev();
   launch_assemble_composite(s, D, C.K, C.x, C.rho, cp, dt, C.Cp, C.cif, C.c2f, C.diag, C.b);
+  launch_interface_values(s, C.n_if_entries, C.if_src, C.cif, C.if_val);
   const int n_tiles = tiles_of(C.n_slots);
   const int B = c->o.max_blocks > 0 ? c->o.max_blocks : 1024;
-  const SweepPlan P = single_plan(sweep_blocks(n_tiles, B), n_tiles);
+  SweepPlan P = single_plan(sweep_blocks(n_tiles, B), n_tiles);
+  if (C.n_if_rows > 0) {
+    P.extra_part = C.if_part;
+    P.n_extra = interface_blocks(D);
+  }
   LoopStats ls;
   ls.iters.assign(1, 0);
   pcg_fp64(c, D, P, SolveArrays{C.Cp, C.diag, C.b, C.x, C.n_slots}, tol, &ls);

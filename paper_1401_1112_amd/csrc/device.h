@@ -68,6 +68,15 @@ struct DevLevel {
   // indices into the concatenated slot space of all levels.
   const double* cif = nullptr;
   const uint8_t* c2f = nullptr;
+  // Composite: the rows with couplings to other levels, row if_row[t] holding
+  // entries [if_ptr[t], if_ptr[t+1]) of column if_col and coefficient cif[if_src].
+  int n_if_rows = 0;
+  const int32_t* if_row = nullptr;
+  const int32_t* if_ptr = nullptr;
+  const int32_t* if_col = nullptr;
+  const int32_t* if_src = nullptr;
+  const double* if_val = nullptr;  // cif[if_src[e]], gathered once per solve
+  double* if_part = nullptr;       // partials of the interface kernel
 };
 
 // How the blocks of a sweep are spread over independent problems (a level is
@@ -83,6 +92,10 @@ struct SweepPlan {
   const int32_t* blk0 = nullptr;      // [n_prob + 1] or nullptr
   const int32_t* tile0 = nullptr;     // [n_prob + 1] or nullptr
   unsigned* done_count = nullptr;     // counts problems that stopped (read by the persistent sweep)
+  // one problem only: more (p, q) partials that the update sweep adds after the
+  // operator sweep's (the couplings of the composite system to other levels)
+  const double* extra_part = nullptr;
+  int n_extra = 0;
 };
 inline SweepPlan single_plan(int G, int n_tiles) {
   SweepPlan p;
@@ -157,6 +170,14 @@ void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it,
                    const T* p, const T* q, T* x, T* r, PcgScalars* sc, double* part,
                    hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part);
+// Composite system: after the operator sweep of iteration `it`, q -= (couplings to
+// other levels) p for the listed rows, and partials of p . (that part of q) in
+// part_if (ceil(n_if_rows / kBlock) of them); skipped once the problem stopped.
+int interface_blocks(const DevLevel& L);
+// val[e] = cif[src[e]] for the n_entries interface entries (once per solve).
+void launch_interface_values(hipStream_t s, int n_entries, const int32_t* src, const double* cif, double* val);
+void launch_interface(hipStream_t s, const DevLevel& L, const double* p, double* q, const PcgScalars* sc,
+                      double* part_if);
 // All iterations of all problems in one cooperative launch (grid barrier between
 // sweeps); bar is the control buffer (kBarWords), P.done_count = bar + kBarDone;
 // its first kBarAbort words are zeroed before the start sweeps.  Returns an

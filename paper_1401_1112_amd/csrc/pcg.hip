@@ -15,7 +15,6 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "common.h"
 
@@ -179,7 +178,7 @@ __device__ __forceinline__ void body_init_finish(int prob, SweepPlan P, const do
 // cross-lane shuffle, out-of-oct neighbours inside the range from LDS, and the
 // rest recomputed from r, d and p_{it-1} in global memory (the two p buffers
 // alternate, so p_{it-1} is never overwritten during the sweep).
-template <typename T, bool COMP>
+template <typename T>
 __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int it,
                                                    const T* __restrict__ Cp, const T* __restrict__ diag,
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
@@ -314,15 +313,6 @@ __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int
           acc -= c_out * pn;
         }
       }
-      if constexpr (COMP) {  // couplings to the other levels of the composite system
-        if (valid[u]) {
-          acc -= dev::interface_terms<T>(ii[u], L, n, [&](int j) -> T {
-            if (j >= s0 && j < s1) return pl[j - s0];
-            const T z = r[j] / diag[j];
-            return first ? z : fma(tb, p_old[j], z);
-          });
-        }
-      }
       if (valid[u]) {
         q[ii[u]] = acc;
         v[0] += double(pi) * double(acc);
@@ -367,6 +357,11 @@ __device__ __forceinline__ void body_pass_b(int vb, DevLevel L, SweepPlan P, int
   double pq[1];
   const bool mx1[1] = {false};
   reduce_partials_all<1>(part + bp.b0, bp.Gp, mx1, pq, lds);
+  if (P.extra_part) {  // couplings to other levels, summed after the operator sweep's partials
+    double pe[1];
+    reduce_partials_all<1>(P.extra_part, P.n_extra, mx1, pe, lds);
+    pq[0] += pe[0];
+  }
   const double alpha = sc->rho[it & 1] / pq[0];
   if (!isfinite(alpha)) {
     if (vb == bp.b0 && threadIdx.x == 0) {
@@ -608,18 +603,30 @@ __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int 
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
                                                    T* __restrict__ p_new, T* __restrict__ q,
                                                    PcgScalars* scs, double* part) {
-  body_pass_a<T, false>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
+  body_pass_a<T>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
 }
 
-// The operator sweep of the composite system of all levels (FP64).
-__global__ __launch_bounds__(kBlock) void k_pass_a_composite(DevLevel L, SweepPlan P, int it,
-                                                             const double* __restrict__ Cp,
-                                                             const double* __restrict__ diag,
-                                                             const double* __restrict__ r,
-                                                             const double* __restrict__ p_old,
-                                                             double* __restrict__ p_new, double* __restrict__ q,
-                                                             PcgScalars* scs, double* part) {
-  body_pass_a<double, true>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
+// Couplings of the composite system to other levels, one thread per listed row:
+// q[i] -= sum_e cif[src_e] p[col_e] with the new p of the operator sweep; the row's
+// share of (p, q) goes to this kernel's block partials (fixed order, no atomics).
+__global__ __launch_bounds__(kBlock) void k_interface(DevLevel L, const double* __restrict__ p,
+                                                      double* __restrict__ q, const PcgScalars* sc,
+                                                      double* __restrict__ part_if) {
+  __shared__ double lds[kLds];
+  if (sc->done) return;  // uniform: set by a previous kernel
+  const int t = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  double v[1] = {0.0};
+  if (t < L.n_if_rows) {
+    const int i = L.if_row[t];
+    const int e0 = L.if_ptr[t], e1 = L.if_ptr[t + 1];
+    double acc = 0.0;
+#pragma unroll 4
+    for (int e = e0; e < e1; ++e) acc += L.if_val[e] * p[L.if_col[e]];
+    q[i] -= acc;
+    v[0] = -p[i] * acc;
+  }
+  const bool mx[1] = {false};
+  write_partials<1>(v, mx, part_if, lds, int(blockIdx.x));
 }
 
 template <typename T>
@@ -696,7 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan
     T* pn = (it & 1) ? p1 : p0;
     const T* po = (it & 1) ? p0 : p1;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
-      body_pass_a<T, false>(vb, L, P, it, Cp, diag, r, po, pn, q, scs, part);
+      body_pass_a<T>(vb, L, P, it, Cp, diag, r, po, pn, q, scs, part);
     if (!grid_barrier(bar, nb, epoch, spin_limit)) {
       if (threadIdx.x == 0) __hip_atomic_store(bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
@@ -750,17 +757,6 @@ void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it,
                    const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part, hipEvent_t t0,
                    hipEvent_t t1) {
   const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
-  if constexpr (std::is_same<T, double>::value) {
-    if (L.cif) {  // composite system of all levels
-      if (t0)
-        hipExtLaunchKernelGGL(k_pass_a_composite, dim3(P.G), dim3(kBlock), uint32_t(lds), s, t0, t1, 0u, L, P, it,
-                              Cp, diag, r, p_old, p_new, q, sc, part);
-      else
-        hipLaunchKernelGGL(k_pass_a_composite, dim3(P.G), dim3(kBlock), lds, s, L, P, it, Cp, diag, r, p_old,
-                           p_new, q, sc, part);
-      return;
-    }
-  }
   if (t0)
     hipExtLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), uint32_t(lds), s, t0, t1, 0u, L, P, it, Cp, diag,
                           r, p_old, p_new, q, sc, part);
@@ -777,6 +773,26 @@ void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it,
                           part);
   else
     hipLaunchKernelGGL(k_pass_b<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, it, diag, p, q, x, r, sc, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_interface_values(int n, const int32_t* __restrict__ src,
+                                                             const double* __restrict__ cif,
+                                                             double* __restrict__ val) {
+  const int e = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  if (e < n) val[e] = cif[src[e]];
+}
+
+int interface_blocks(const DevLevel& L) { return std::max(1, (L.n_if_rows + kBlock - 1) / kBlock); }
+
+void launch_interface_values(hipStream_t s, int n_entries, const int32_t* src, const double* cif, double* val) {
+  if (n_entries <= 0) return;
+  hipLaunchKernelGGL(k_interface_values, dim3((n_entries + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n_entries,
+                     src, cif, val);
+}
+
+void launch_interface(hipStream_t s, const DevLevel& L, const double* p, double* q, const PcgScalars* sc,
+                      double* part_if) {
+  hipLaunchKernelGGL(k_interface, dim3(interface_blocks(L)), dim3(kBlock), 0, s, L, p, q, sc, part_if);
 }
 
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part) {
