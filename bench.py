@@ -218,6 +218,71 @@ def _unique_form(p, s, init, ms_ats, args):
             "rel_l2_unique_vs_adaptive": diff}
 
 
+def _dirac_form(args):
+    """The paper's linear diffusion test (Sect. 4.1) in 3D plane-parallel form: an energy
+    pulse (E0 = 1e5 per unit area on a background of 1) through refined slabs, levels 5..8
+    (2.79 M cells), up to t = 2e-3 (K = 1), with Dirichlet, Robin and Neumann interfaces:
+    total-energy gain and L2 error against the heat kernel, and the time per coarse step.
+    Two step sizes: the paper's coarse step (3.125e-5, 64 steps) and one 16x larger (4
+    steps), at which the finest level's diffusion number K dt / dx^2 is ~4 as the paper
+    also states."""
+    import numpy as np
+    import torch
+    from paper_1401_1112_amd import BC_DIRICHLET, BC_NEUMANN, BC_ROBIN
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    from synth.configs import config_dirac_slab
+    modes = {1.0: BC_DIRICHLET, 0.5: BC_ROBIN, 0.0: BC_NEUMANN}
+    E0, K = 1e5, 1.0
+    out = {}
+    for tag, dt, steps in (("paper_dt", 3.125e-5, 64), ("cfl4_dt", 5e-4, 4)):
+        out[tag] = {}
+        for alpha, mode in modes.items():
+            p = config_dirac_slab(dt_coarse=dt, n_coarse_steps=steps, robin_alpha=alpha)
+            s = solver_from_problem(p)
+            leaf = {}
+            for l in p.hierarchy.levels:
+                c = s.cells(l)
+                m = np.ones(len(c), dtype=bool)
+                if l + 1 in p.hierarchy.octs:
+                    par = np.asarray(p.hierarchy.octs[l + 1], dtype=np.int64)
+                    n = np.int64(1) << l
+                    m = ~np.isin((c[:, 0].astype(np.int64) * n + c[:, 1]) * n + c[:, 2],
+                                 (par[:, 0] * n + par[:, 1]) * n + par[:, 2])
+                leaf[l] = (m, c)
+
+            def total():
+                return sum(float(to_numpy(s.E(l))[leaf[l][0]].sum()) / float(1 << (3 * l)) for l in leaf)
+
+            e0 = total()
+            gains, its = [], 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            el = 0.0
+            for _ in range(steps):
+                t1 = time.perf_counter()
+                s.advance(p.dt_coarse, mode, p.tol)
+                torch.cuda.synchronize()
+                el += time.perf_counter() - t1
+                its += sum(x["iters"] for x in s.stats())
+                gains.append((total() - e0) / e0)
+            T = dt * steps
+            tt = T + (2.0 * p.info["pulse_half"]) ** 2 / (24.0 * K)
+            e2 = n2 = 0.0
+            for l, (m, c) in leaf.items():
+                x = (c[m, 0] + 0.5) / (1 << l)
+                a = 1.0 + E0 / np.sqrt(4.0 * np.pi * K * tt) * np.exp(-(x - 0.5) ** 2 / (4.0 * K * tt))
+                e = to_numpy(s.E(l))[m]
+                e2 += float(np.sum((e - a) ** 2)) / float(1 << (3 * l))
+                n2 += float(np.sum((a - 1.0) ** 2)) / float(1 << (3 * l))
+            s.close()
+            out[tag][f"alpha_{alpha}"] = {"energy_gain_end": gains[-1], "energy_gain_max": max(gains, key=abs),
+                                          "l2_error_vs_heat_kernel": float(np.sqrt(e2 / n2)),
+                                          "ms_per_coarse_step": round(el * 1e3 / steps, 2), "pcg_iterations": its}
+        out[tag]["workload"] = (f"levels 5..8 (2,785,280 cells), {steps} coarse steps of {dt}, "
+                                f"finest K dt/dx^2 = {K * dt / 8 * 256 ** 2:.2f}, tol 1e-8")
+    return out
+
+
 def _batched_form(args):
     """The batching form: independent patches with log-uniform sizes 8^3..128^3, own
     log-normal density, mixed Dirichlet / Neumann / Robin faces, 16 backward-Euler steps,
@@ -431,6 +496,7 @@ def main(argv=None):
     ap.add_argument("--max-blocks", type=int, default=0, help="blocks per PCG sweep (0: library default)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-unique", action="store_true", help="skip the unique-time-step comparison")
+    ap.add_argument("--no-dirac", action="store_true", help="skip the pulse-diffusion test of the paper")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-patches", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=16)
@@ -549,6 +615,8 @@ def main(argv=None):
         import torch as _t
         _t.cuda.empty_cache()
         out["forms"]["batched"] = _batched_form(args)
+    if not args.no_dirac:
+        out["forms"]["dirac_pulse"] = _dirac_form(args)
     if not args.no_collapse:
         import torch as _t
         _t.cuda.empty_cache()

@@ -168,6 +168,43 @@ def config_collapse(base_level: int = 6, max_level: int = 13, jeans: float = 0.1
                    info={"refined_per_level": counts, "jeans": jeans, "contrast": contrast})
 
 
+def config_dirac_slab(base_level: int = 5, max_level: int = 8, widths=(0.25, 0.125, 0.0625), E0: float = 1e5,
+                      dt_coarse: float = 3.125e-5, n_coarse_steps: int = 64, tol: float = 1e-8,
+                      bc_mode: str = "dirichlet", robin_alpha: float = 0.5) -> Problem:
+    """Plane-parallel energy pulse diffusing through nested refined slabs.
+
+    E = 1 plus a pulse of E0 per unit area spread uniformly over the two central cell
+    planes (x) of the finest level, each field value the cell average (so restriction
+    reproduces it).  Level l + 1 covers the level-l cells whose centre lies within
+    ``widths[l - base]`` of x = 0.5, over the whole y-z extent.  Constant K = 1,
+    zero-flux outer faces, ``n_coarse_steps`` steps of ``dt_coarse``."""
+    widths = list(widths)
+
+    def criterion(level, ijk):
+        k = level - base_level
+        if k >= len(widths):
+            return np.zeros(len(ijk))
+        x = (ijk[:, 0] + 0.5) / (1 << level)
+        return (np.abs(x - 0.5) < widths[k]).astype(np.float64)
+
+    h, counts = budgeted_hierarchy(base_level, max_level, criterion, 0.5, 1 << 62, seed=17)
+    top = max(h.levels)
+    half = 1.0 / (1 << top)  # the pulse spans [0.5 - dx_f, 0.5 + dx_f]
+
+    def E(level, ijk):
+        dx = 1.0 / (1 << level)
+        x0 = ijk[:, 0] * dx
+        overlap = np.clip(np.minimum(x0 + dx, 0.5 + half) - np.maximum(x0, 0.5 - half), 0.0, None)
+        return 1.0 + E0 * overlap / (2.0 * half) / dx
+
+    def rho(level, ijk):
+        return np.ones(len(ijk))
+
+    return Problem(f"dirac_slab_L{base_level}-{top}", h, rho, E, kmode="const", K_const=1.0,
+                   dt_coarse=dt_coarse, bc_mode=bc_mode, robin_alpha=robin_alpha, tol=tol,
+                   n_coarse_steps=n_coarse_steps, info={"refined_per_level": counts, "E0": E0, "pulse_half": half})
+
+
 def config_tiny(seed: int, base_level: int = 2, max_level: int = 4, kmode: str = "lp",
                 bc_mode: str = "dirichlet", dt_scale: float = 1.0, p_refine: float = 0.35,
                 tol: float = 1e-12, robin_alpha: float = 0.5) -> Problem:
