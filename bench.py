@@ -65,6 +65,27 @@ def _measured_traffic(kernel: str, max_blocks: int):
     return float(kv["traffic_kib_per_dispatch"]) * 1024.0
 
 
+def _copy_bandwidth(mib=1024, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of `mib` MiB (read + write
+    bytes over the event-timed duration, best of `reps`)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * mib * (1 << 20) / (best * 1e-3) / 1e9
+
+
 def _problem():
     from synth.configs import config_fld_lognormal
     return config_fld_lognormal()
@@ -575,7 +596,8 @@ def main(argv=None):
                               f"(hipExtLaunchKernelGGL) of the sweeps of every {args.time_period}th PCG iteration",
                     "avg_launch_us": round(a_ms * 1e3 / max(n_a, 1), 2),
                     "pass_b_GBs": round(b_bytes / (b_ms * 1e-3) / 1e9, 1) if b_ms > 0 else None,
-                    "pass_b_bytes_per_slot": PASS_B_BYTES}
+                    "pass_b_bytes_per_slot": PASS_B_BYTES,
+                    "copy_GBs_achievable": round(_copy_bandwidth(), 1)}
     out = {
         "metric": METRIC,
         "value": cell_it / elapsed,

@@ -33,7 +33,9 @@ What it computes (Commercon, Debout & Teyssier 2014):
   cell coupled to each finer cell of a refined neighbour's face with
   2^(3-ndim) A / 3, rows scaled by the cell volume.
 * Levermore-Pomraning limited diffusivity ``K = c lambda(R) / (rho kappa_R)``
-  with ``R = |grad E| / (rho kappa_R E)`` (Sect. 2.1).
+  with ``R = |grad E| / (rho kappa_R E)`` (Sect. 2.1); the Minerbo limiter of the
+  collapse runs (Sect. 5.1) as an option.
+* Optionally a theta-weighted step (Crank-Nicolson at theta = 1/2, Sect. 3.3.6).
 
 Readings where the paper is silent or ambiguous:
 
@@ -74,6 +76,15 @@ def lp_limiter(R):
     """Levermore-Pomraning flux limiter, rational form; lambda(0) = 1/3 (Sect. 2.1, 4.1)."""
     R = np.asarray(R, dtype=np.float64)
     return (2.0 + R) / (6.0 + 3.0 * R + R * R)
+
+
+def minerbo_limiter(R):
+    """Minerbo (1978) flux limiter, the limiter of the paper's collapse runs (Sect. 5.1):
+    2 / (3 + sqrt(9 + 12 R^2)) up to R = 3/2, 1 / (1 + R + sqrt(1 + 2R)) beyond."""
+    R = np.asarray(R, dtype=np.float64)
+    low = 2.0 / (3.0 + np.sqrt(9.0 + 12.0 * R * R))
+    high = 1.0 / (1.0 + R + np.sqrt(1.0 + 2.0 * R))
+    return np.where(R <= 1.5, low, high)
 
 
 def harmonic_mean(a, b):
@@ -124,8 +135,9 @@ class Oracle:
 
     def __init__(self, base_level, octs, *, kmode="lp", K_const=1.0, kappa_R=1.0, kappa_P=1.0,
                  c_light=1.0, a_rad=1.0, c_v=1.0, robin_alpha=0.5, abs_floor=1e-14,
-                 linf_test=True, max_iter=10000, nsub=None):
+                 linf_test=True, max_iter=10000, nsub=None, theta=1.0):
         self.base = int(base_level)
+        self.theta = float(theta)
         self.max_level = max(octs)
         self.kmode = kmode
         self.K_const = float(K_const)
@@ -224,7 +236,8 @@ class Oracle:
         g = self.grad_E(level)
         gn = np.sqrt(np.sum(g * g, axis=1))
         R = gn / (rho * self.kappa_R * E)
-        return self.c * lp_limiter(R) / (rho * self.kappa_R)
+        lam = minerbo_limiter(R) if self.kmode == "minerbo" else lp_limiter(R)
+        return self.c * lam / (rho * self.kappa_R)
 
     # ---------------------------------------------------------------- assembly
     def assemble(self, level, dt, mode):
@@ -283,6 +296,15 @@ class Oracle:
         return A, b, coupling
 
     # ------------------------------------------------------------------- solve
+    def theta_scheme(self, A1, b1, En):
+        """Theta-weighted form of a backward-Euler system (Crank-Nicolson for theta = 1/2,
+        the remedy Sect. 3.3.6 names for the first-order time error): the face fluxes are
+        taken theta at the new and 1 - theta at the old time, the ghost values being the
+        same at both, so A = I + theta (A1 - I) and b = b1 - (1 - theta) (A1 - I) E^n."""
+        I = sp.identity(A1.shape[0], format="csr")
+        D = A1 - I
+        return (I + self.theta * D).tocsr(), b1 - (1.0 - self.theta) * (D @ En)
+
     def solve_level(self, level, dt, mode=DIRICHLET, tol=1e-10, max_iter=None, solver="pcg"):
         """Advance one level by dt (Sect. 3.3.4).  Updates E (and T) in place, adds the
         fine-to-coarse fluxes to the parent register in Neumann / Robin mode, and
@@ -290,6 +312,8 @@ class Oracle:
         L = self.lev[level]
         A, b, coupling = self.assemble(level, dt, mode)
         x0 = self.E[level][L.leaf_slots].copy()
+        if self.theta != 1.0:
+            A, b = self.theta_scheme(A, b, x0)
         if solver == "dense":
             x = dense_solve(A, b)
             st = {"iters": 0, "converged": True}

@@ -43,6 +43,7 @@ class Problem:
     abs_floor: float = 1e-14
     linf_test: bool = True
     max_iter: int = 10000
+    theta: float = 1.0           # 1: backward Euler, 1/2: Crank-Nicolson
     info: dict = field(default_factory=dict)
 
     def nsub_of(self, level: int) -> int:
