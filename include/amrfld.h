@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum { AMRFLD_BC_DIRICHLET = 0, AMRFLD_BC_NEUMANN = 1, AMRFLD_BC_ROBIN = 2 } amrfld_bc;
 typedef enum { AMRFLD_FP64 = 0, AMRFLD_MIXED = 1 } amrfld_precision;
-typedef enum { AMRFLD_K_CONST = 0, AMRFLD_K_LP = 1 } amrfld_kmode;
+typedef enum { AMRFLD_K_CONST = 0, AMRFLD_K_LP = 1, AMRFLD_K_MINERBO = 2 } amrfld_kmode;
 
 typedef struct {
   int base_level;        /* coarsest level; it must cover the unit box */
@@ -83,6 +83,9 @@ typedef struct {
   int graph;             /* batch form with persistent: 1 = capture all steps in one hipGraph */
   void* stream;          /* hipStream_t */
   int persistent_per_cu; /* persistent launch: resident blocks per compute unit (0 = as many as fit) */
+  double theta;          /* time weighting of the level solves: 1 backward Euler (default), 1/2
+                            Crank-Nicolson (Sect. 3.3.6); values in [1/2, 1]; theta < 1 requires
+                            Dirichlet interfaces and no coupling term */
 } amrfld_opts;
 
 typedef struct {
@@ -134,9 +137,11 @@ amrfld_status amrfld_level_info(const amrfld_ctx* c, int level, int64_t* n_slots
  * temperature T (NULL: no coupling term on this level).  Refined slots carry the
  * value used for their restricted cell until the next restriction replaces E.
  * kappa_R, kappa_P: opacities per unit mass; c_light: speed of light; kmode:
- * AMRFLD_K_CONST (K = K_const everywhere, the heat equation of Sect. 1) or
- * AMRFLD_K_LP (K = c lambda(R) / (rho kappa_R), Sect. 2.1).  The values are
- * copied (stream-ordered) before return. */
+ * AMRFLD_K_CONST (K = K_const everywhere, the heat equation of Sect. 1),
+ * AMRFLD_K_LP (K = c lambda(R) / (rho kappa_R) with the Levermore-Pomraning
+ * limiter, Sect. 2.1) or AMRFLD_K_MINERBO (the same with the Minerbo limiter of
+ * the collapse runs, Sect. 5.1).  The values are copied (stream-ordered) before
+ * return. */
 amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, const double* E,
                                 const double* T, double kappa_R, double kappa_P, double c_light,
                                 int kmode, double K_const);

@@ -16,7 +16,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .fld_oracle import harmonic_mean, lp_limiter, pcg_jacobi
+from .fld_oracle import harmonic_mean, lp_limiter, minerbo_limiter, pcg_jacobi
 
 DIRICHLET, NEUMANN, ROBIN = 0, 1, 2
 
@@ -33,7 +33,8 @@ def patch_K(rho, E, dx, kmode="lp", K_const=1.0, kappa_R=1.0, c_light=1.0):
         g = (Ep - Em) / (dx + dx)
         g2 += g * g
     R = np.sqrt(g2) / (rho * kappa_R * E)
-    return c_light * lp_limiter(R) / (rho * kappa_R)
+    lam = minerbo_limiter(R) if kmode == "minerbo" else lp_limiter(R)
+    return c_light * lam / (rho * kappa_R)
 
 
 def patch_system(rho, E, dx, dt, modes, ghosts, fluxes, alpha=0.5, kmode="lp", K_const=1.0,

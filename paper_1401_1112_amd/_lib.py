@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_D
                 -5: "E_NOCONV", -6: "E_NONFINITE"}
 BC_DIRICHLET, BC_NEUMANN, BC_ROBIN = 0, 1, 2
 FP64, MIXED = 0, 1
-K_CONST, K_LP = 0, 1
+K_CONST, K_LP, K_MINERBO = 0, 1, 2
 
 
 class amrfld_opts(ctypes.Structure):
@@ -32,7 +32,7 @@ class amrfld_opts(ctypes.Structure):
         ("true_residual", ctypes.c_int), ("time_sweeps", ctypes.c_int),
         ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_blocks", ctypes.c_int),
         ("persistent", ctypes.c_int), ("graph", ctypes.c_int), ("stream", ctypes.c_void_p),
-        ("persistent_per_cu", ctypes.c_int),
+        ("persistent_per_cu", ctypes.c_int), ("theta", ctypes.c_double),
     ]
 
 

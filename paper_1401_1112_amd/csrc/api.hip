@@ -280,6 +280,17 @@ double* ensure_reg(amrfld_ctx* c, LevelState& L) {
   return L.reg;
 }
 
+// The theta-weighted step is defined for Dirichlet interfaces and no coupling term
+// (the stored flux and the temperature update assume backward Euler).
+amrfld_status check_theta(amrfld_ctx* c, int bc_mode) {
+  if (c->o.theta == 1.0) return AMRFLD_OK;
+  if (bc_mode != AMRFLD_BC_DIRICHLET)
+    return fail(c, AMRFLD_E_INVALID, "theta < 1 requires Dirichlet interfaces");
+  for (const LevelState& L : c->lev)
+    if (L.has_T) return fail(c, AMRFLD_E_INVALID, "theta < 1 is not defined with the coupling term");
+  return AMRFLD_OK;
+}
+
 amrfld_status check_level_ready(amrfld_ctx* c, int level) {
   if (level < c->o.base_level || level > c->finest)
     return fail(c, AMRFLD_E_INVALID, "level not built");
@@ -520,6 +531,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   const CouplingParams cp = cparams(c, L);
   launch_assemble(s, D, L.K, Lc ? Lc->K : nullptr, L.E, Lc ? Lc->E : nullptr, L.rho, L.reg, dt, w,
                   c->o.robin_alpha, cp, L.Cp, L.diag, L.b);
+  if (c->o.theta != 1.0) launch_theta_step(s, D, c->o.theta, L.E, L.Cp, L.diag, L.b);
 
   const int n_tiles = tiles_of(D.n_slots);
   const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
@@ -1221,6 +1233,7 @@ void amrfld_default_opts(amrfld_opts* o) {
   o->max_outer = 30;
   o->max_blocks = 0;
   o->stream = nullptr;
+  o->theta = 1.0;
 }
 
 const char* amrfld_create_error(void) { return g_create_error.c_str(); }
@@ -1246,6 +1259,10 @@ amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
   }
   if (o->max_blocks < 0 || o->persistent_per_cu < 0) {
     g_create_error = "max_blocks and persistent_per_cu must be >= 0";
+    return AMRFLD_E_INVALID;
+  }
+  if (!(o->theta >= 0.5 && o->theta <= 1.0)) {
+    g_create_error = "theta must be in [0.5, 1]";
     return AMRFLD_E_INVALID;
   }
   amrfld_ctx* c = nullptr;
@@ -1362,8 +1379,9 @@ amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, con
   if (!c) return AMRFLD_E_INVALID;
   if (level < c->o.base_level || level > c->finest) return fail(c, AMRFLD_E_INVALID, "level not built");
   if (!rho || !E) return fail(c, AMRFLD_E_INVALID, "rho and E are required");
-  if (kmode != AMRFLD_K_CONST && kmode != AMRFLD_K_LP) return fail(c, AMRFLD_E_INVALID, "unknown kmode");
-  if (kmode == AMRFLD_K_LP && !(kappa_R > 0.0 && c_light > 0.0))
+  if (kmode != AMRFLD_K_CONST && kmode != AMRFLD_K_LP && kmode != AMRFLD_K_MINERBO)
+    return fail(c, AMRFLD_E_INVALID, "unknown kmode");
+  if (kmode != AMRFLD_K_CONST && !(kappa_R > 0.0 && c_light > 0.0))
     return fail(c, AMRFLD_E_INVALID, "kappa_R and c_light must be positive");
   if (kmode == AMRFLD_K_CONST && !(K_const >= 0.0)) return fail(c, AMRFLD_E_INVALID, "K_const must be >= 0");
   if (T && !(kappa_P >= 0.0 && c_light > 0.0)) return fail(c, AMRFLD_E_INVALID, "kappa_P >= 0 and c_light > 0 needed with T");
@@ -1395,6 +1413,8 @@ amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mod
   if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
   const amrfld_status r = check_level_ready(c, level);
   if (r != AMRFLD_OK) return r;
+  const amrfld_status rt = check_theta(c, bc_mode);
+  if (rt != AMRFLD_OK) return rt;
   c->stats.clear();
   return guarded(c, [&]() { return solve_one(c, level, dt, bc_mode, tol); });
 }
@@ -1409,6 +1429,8 @@ amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_m
     const amrfld_status r = check_level_ready(c, l);
     if (r != AMRFLD_OK) return r;
   }
+  const amrfld_status rt = check_theta(c, bc_mode);
+  if (rt != AMRFLD_OK) return rt;
   c->stats.clear();
   return guarded(c, [&]() { return step(c, c->o.base_level, dt_coarse, bc_mode, tol); });
 }
@@ -1422,6 +1444,7 @@ amrfld_status amrfld_advance_unique(amrfld_ctx* c, double dt_coarse, double tol)
     const amrfld_status r = check_level_ready(c, l);
     if (r != AMRFLD_OK) return r;
   }
+  if (c->o.theta != 1.0) return fail(c, AMRFLD_E_INVALID, "the unique-time-step solve is backward Euler (theta = 1)");
   c->stats.clear();
   return guarded(c, [&]() { return advance_unique(c, dt_coarse, tol); });
 }
@@ -1433,6 +1456,7 @@ amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* 
   if (n_steps < 1) return fail(c, AMRFLD_E_INVALID, "n_steps must be >= 1");
   if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
   if (precision != AMRFLD_FP64 && precision != AMRFLD_MIXED) return fail(c, AMRFLD_E_INVALID, "unknown precision");
+  if (c->o.theta != 1.0) return fail(c, AMRFLD_E_INVALID, "the batch form is backward Euler (theta = 1)");
   std::vector<amrfld_patch> pt(patches, patches + n_prob);
   for (int q = 0; q < n_prob; ++q) {
     const amrfld_patch& p = pt[q];
@@ -1440,8 +1464,9 @@ amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* 
     if (p.n < 2 || p.n > 1024 || (p.n & 1)) return fail(c, AMRFLD_E_INVALID, at + "n must be even, 2..1024");
     if (!(p.dx > 0.0) || !(p.dt > 0.0)) return fail(c, AMRFLD_E_INVALID, at + "dx and dt must be positive");
     if (!p.rho || !p.E) return fail(c, AMRFLD_E_INVALID, at + "rho and E are required");
-    if (p.kmode != AMRFLD_K_CONST && p.kmode != AMRFLD_K_LP) return fail(c, AMRFLD_E_INVALID, at + "unknown kmode");
-    if (p.kmode == AMRFLD_K_LP && !(p.kappa_R > 0.0 && p.c_light > 0.0))
+    if (p.kmode != AMRFLD_K_CONST && p.kmode != AMRFLD_K_LP && p.kmode != AMRFLD_K_MINERBO)
+      return fail(c, AMRFLD_E_INVALID, at + "unknown kmode");
+    if (p.kmode != AMRFLD_K_CONST && !(p.kappa_R > 0.0 && p.c_light > 0.0))
       return fail(c, AMRFLD_E_INVALID, at + "kappa_R and c_light must be positive");
     for (int d = 0; d < 6; ++d)
       if (p.face_mode[d] < 0 || p.face_mode[d] > 2) return fail(c, AMRFLD_E_INVALID, at + "unknown face mode");

@@ -132,6 +132,10 @@ void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const do
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
                      double dt, double w, double alpha, const CouplingParams& cp, double* Cp,
                      double* diag, double* b);
+// Theta-weighted step (Crank-Nicolson at 1/2) from an assembled backward-Euler
+// level system: b -= (1 - theta) (A E - E) on the leaves, then A = I + theta (A - I).
+void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E, double* Cp, double* diag,
+                       double* b);
 // Composite system of all levels advanced with one dt (unique time step): per slot
 // the volume-scaled same-level coefficients Cp, interface coefficients cif, the
 // refined-neighbour mask c2f, diagonal and right-hand side; E is the concatenated

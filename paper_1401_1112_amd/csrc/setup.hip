@@ -60,8 +60,36 @@ __global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __r
   }
   const double rk = rho[i] * kappa_R;
   const double R = sqrt(g2) / (rk * Ei);
-  const double lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+  double lam;
+  if (kmode == 2) {  // Minerbo limiter
+    lam = R <= 1.5 ? 2.0 / (3.0 + sqrt(9.0 + 12.0 * R * R)) : 1.0 / (1.0 + R + sqrt(1.0 + 2.0 * R));
+  } else {  // Levermore-Pomraning limiter
+    lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+  }
   K[i] = c_light * lam / rk;
+}
+
+// Theta-weighted step from the backward-Euler system (A1, b1): the right-hand side
+// loses (1 - theta) (A1 - I) E^n (same-level fluxes at the old time; the ghost
+// values are the same at both times), then ...
+__global__ __launch_bounds__(kBlock) void k_theta_rhs(DevLevel L, const double* __restrict__ Cp,
+                                                      const double* __restrict__ diag,
+                                                      const double* __restrict__ E, double theta,
+                                                      double* __restrict__ b) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= L.n_slots || L.child[i] != -1) return;
+  const double ax = dev::apply_stencil<double>(i, L.nbr, Cp, L.n_slots, diag[i], E[i], [&](int j) { return E[j]; });
+  b[i] -= (1.0 - theta) * (ax - E[i]);
+}
+
+// ... the matrix becomes I + theta (A1 - I) (identity rows stay identity rows).
+__global__ __launch_bounds__(kBlock) void k_theta_scale(int n, double theta, double* __restrict__ Cp,
+                                                        double* __restrict__ diag) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Cp[size_t(a) * n + i] *= theta;
+  diag[i] = 1.0 + theta * (diag[i] - 1.0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_assemble(
@@ -310,6 +338,12 @@ void launch_assemble_composite(hipStream_t s, const DevLevel& C, const double* K
                                uint8_t* c2f, double* diag, double* b) {
   hipLaunchKernelGGL(k_assemble_composite, dim3(grid_for(C.n_slots)), dim3(kBlock), 0, s, C, K, E, rho, cp, dt, Cp,
                      cif, c2f, diag, b);
+}
+
+void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E, double* Cp, double* diag,
+                       double* b) {
+  hipLaunchKernelGGL(k_theta_rhs, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, Cp, diag, E, theta, b);
+  hipLaunchKernelGGL(k_theta_scale, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L.n_slots, theta, Cp, diag);
 }
 
 void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, const double* K_c,
