@@ -304,6 +304,86 @@ def _dirac_form(args):
     return out
 
 
+def _equilibrium_form(args):
+    """The paper's equilibrium test with a nonlinear diffusivity (Sect. 4.2): K = E^1.5,
+    E held at 4 (x = 0) and 0.5 (x = 1), relaxed from a step to the stationary profile
+    (E^2.5 linear in x), plane-parallel in 3D.  As in the paper's convergence study:
+    uniform grids of 8..128 cells per side, and 8 coarse cells with 1..4 more levels
+    refined where the profile changes by more than 10% per cell (28 cells along x at 4
+    levels), adaptive (Dirichlet interfaces) and unique time step.  Per run: coarse steps
+    to the steady state, L2 error against the profile (volume-weighted; and the form the
+    paper prints, with dx inside the square, over the effective cell count), the boundary
+    flux imbalance, and the time per coarse step."""
+    import numpy as np
+    import torch
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    from synth.configs import config_equilibrium, equilibrium_profile
+    a, lo, hi = 1.5, 4.0, 0.5
+    exact_flux = (lo ** (a + 1) - hi ** (a + 1)) / (a + 1)
+
+    def run(base, top, unique):
+        p = config_equilibrium(base_level=base, max_level=top, a=a, E_left=lo, E_right=hi, tol=1e-8)
+        s = solver_from_problem(p)
+        leaf = {}
+        for l in p.hierarchy.levels:
+            c = s.cells(l).astype(np.int64)
+            m = np.ones(len(c), dtype=bool)
+            if l + 1 in p.hierarchy.octs:
+                par = np.asarray(p.hierarchy.octs[l + 1], dtype=np.int64)
+                n = np.int64(1) << l
+                m = ~np.isin((c[:, 0] * n + c[:, 1]) * n + c[:, 2], (par[:, 0] * n + par[:, 1]) * n + par[:, 2])
+            leaf[l] = (m, c[m])
+
+        def leaves():
+            return {l: to_numpy(s.E(l))[m] for l, (m, _) in leaf.items()}
+
+        prev, steps, el, its = leaves(), 0, 0.0, 0
+        while steps < 1000:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if unique:
+                s.advance_unique(p.dt_coarse, p.tol)
+            else:
+                s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            its += sum(x["iters"] for x in s.stats())
+            steps += 1
+            cur = leaves()
+            done = max(float(np.abs(cur[l] - prev[l]).max()) for l in cur) < 1e-10
+            prev = cur
+            if done:
+                break
+        s.close()
+        e2 = lit = 0.0
+        flux = [0.0, 0.0]
+        n_eff = 1 << top
+        for l, e in prev.items():
+            c = leaf[l][1]
+            dx = 1.0 / (1 << l)
+            err = e - equilibrium_profile((c[:, 0] + 0.5) * dx, a, lo, hi)
+            e2 += float(np.sum(err ** 2)) * dx ** 3
+            lit += float(np.sum((err * dx) ** 2)) * dx ** 2  # one term per cell along x
+            for k, (face, v) in enumerate(((0, lo), ((1 << l) - 1, hi))):
+                on = c[:, 0] == face
+                Ki, Kb = e[on] ** a, v ** a
+                flux[k] += float(np.sum(4.0 * Ki * Kb / (Ki + Kb) * (v - e[on]) / dx)) * dx * dx
+        return {"cells_along_x": int(sum(len(np.unique(leaf[l][1][:, 0])) for l in leaf)),
+                "slots": int(sum(len(m) for m, _ in leaf.values())), "steps_to_steady": steps,
+                "pcg_iterations": its, "ms_per_coarse_step": round(el * 1e3 / steps, 3),
+                "l2_error": float(np.sqrt(e2)), "l2_error_paper_form": float(np.sqrt(lit / n_eff)),
+                "flux_in_rel_exact": flux[0] / exact_flux - 1.0,
+                "flux_imbalance_rel": (flux[0] + flux[1]) / flux[0]}
+
+    out = {"workload": "K = E^1.5, E(0) = 4, E(1) = 0.5, rho = 1, dt 0.05, tol 1e-8, steady when no leaf "
+                       "moves by 1e-10 in a coarse step"}
+    out["uniform"] = {str(1 << lv): run(lv, lv, False) for lv in (3, 4, 5, 6, 7)}
+    out["adaptive"] = {str(8 << k): run(3, 3 + k, False) for k in (1, 2, 3, 4)}
+    out["unique"] = {str(8 << k): run(3, 3 + k, True) for k in (1, 2, 3, 4)}
+    return out
+
+
 def _batched_form(args):
     """The batching form: independent patches with log-uniform sizes 8^3..128^3, own
     log-normal density, mixed Dirichlet / Neumann / Robin faces, 16 backward-Euler steps,
@@ -518,6 +598,8 @@ def main(argv=None):
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
     ap.add_argument("--no-unique", action="store_true", help="skip the unique-time-step comparison")
     ap.add_argument("--no-dirac", action="store_true", help="skip the pulse-diffusion test of the paper")
+    ap.add_argument("--no-equilibrium", action="store_true",
+                    help="skip the nonlinear equilibrium test of the paper")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
     ap.add_argument("--batch-patches", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=16)
@@ -639,6 +721,8 @@ def main(argv=None):
         out["forms"]["batched"] = _batched_form(args)
     if not args.no_dirac:
         out["forms"]["dirac_pulse"] = _dirac_form(args)
+    if not args.no_equilibrium:
+        out["forms"]["equilibrium"] = _equilibrium_form(args)
     if not args.no_collapse:
         import torch as _t
         _t.cuda.empty_cache()

@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum { AMRFLD_BC_DIRICHLET = 0, AMRFLD_BC_NEUMANN = 1, AMRFLD_BC_ROBIN = 2 } amrfld_bc;
 typedef enum { AMRFLD_FP64 = 0, AMRFLD_MIXED = 1 } amrfld_precision;
-typedef enum { AMRFLD_K_CONST = 0, AMRFLD_K_LP = 1, AMRFLD_K_MINERBO = 2 } amrfld_kmode;
+typedef enum { AMRFLD_K_CONST = 0, AMRFLD_K_LP = 1, AMRFLD_K_MINERBO = 2, AMRFLD_K_POWER = 3 } amrfld_kmode;
 
 typedef struct {
   int base_level;        /* coarsest level; it must cover the unit box */
@@ -86,6 +86,14 @@ typedef struct {
   double theta;          /* time weighting of the level solves: 1 backward Euler (default), 1/2
                             Crank-Nicolson (Sect. 3.3.6); values in [1/2, 1]; theta < 1 requires
                             Dirichlet interfaces and no coupling term */
+  double K_exp;          /* AMRFLD_K_POWER: K = K_const E^K_exp (the nonlinear equilibrium test,
+                            Sect. 4.2); default 0 */
+  int outer_mode[6];     /* faces of the unit box, in the order -x, +x, -y, +y, -z, +z: 0 no flux
+                            (default), 1 Dirichlet; level solves and the unique time step only */
+  double outer_value[6]; /* energy held at each Dirichlet face: the row of a cell on that face gets
+                            C = 2 K_f dt / dx^2 (the value dx / 2 from the centre), K_f the harmonic
+                            mean of the cell's K and the law's K at the held value (no gradient
+                            there); the flux-limited gradient also takes the held value dx / 2 away */
 } amrfld_opts;
 
 typedef struct {
@@ -139,9 +147,10 @@ amrfld_status amrfld_level_info(const amrfld_ctx* c, int level, int64_t* n_slots
  * kappa_R, kappa_P: opacities per unit mass; c_light: speed of light; kmode:
  * AMRFLD_K_CONST (K = K_const everywhere, the heat equation of Sect. 1),
  * AMRFLD_K_LP (K = c lambda(R) / (rho kappa_R) with the Levermore-Pomraning
- * limiter, Sect. 2.1) or AMRFLD_K_MINERBO (the same with the Minerbo limiter of
- * the collapse runs, Sect. 5.1).  The values are copied (stream-ordered) before
- * return. */
+ * limiter, Sect. 2.1), AMRFLD_K_MINERBO (the same with the Minerbo limiter of
+ * the collapse runs, Sect. 5.1) or AMRFLD_K_POWER (K = K_const E^K_exp, K_exp from
+ * the options, lagged at the start of each solve; E > 0 unless K_exp is an
+ * integer).  The values are copied (stream-ordered) before return. */
 amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, const double* E,
                                 const double* T, double kappa_R, double kappa_P, double c_light,
                                 int kmode, double K_const);

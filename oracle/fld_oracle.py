@@ -36,6 +36,9 @@ What it computes (Commercon, Debout & Teyssier 2014):
   with ``R = |grad E| / (rho kappa_R E)`` (Sect. 2.1); the Minerbo limiter of the
   collapse runs (Sect. 5.1) as an option.
 * Optionally a theta-weighted step (Crank-Nicolson at theta = 1/2, Sect. 3.3.6).
+* Optionally a power-law diffusivity K = K_const E^K_exp (the nonlinear
+  equilibrium test, Sect. 4.2) and Dirichlet values held at outer faces
+  (C = 2 K_f dt / dx^2 with the face dx / 2 away).
 
 Readings where the paper is silent or ambiguous:
 
@@ -135,9 +138,12 @@ class Oracle:
 
     def __init__(self, base_level, octs, *, kmode="lp", K_const=1.0, kappa_R=1.0, kappa_P=1.0,
                  c_light=1.0, a_rad=1.0, c_v=1.0, robin_alpha=0.5, abs_floor=1e-14,
-                 linf_test=True, max_iter=10000, nsub=None, theta=1.0):
+                 linf_test=True, max_iter=10000, nsub=None, theta=1.0, K_exp=0.0, outer=None):
         self.base = int(base_level)
         self.theta = float(theta)
+        self.K_exp = float(K_exp)
+        # outer faces: direction -> Dirichlet value held at the face (others: zero flux)
+        self.outer = {int(d): float(v) for d, v in (outer or {}).items()}
         self.max_level = max(octs)
         self.kmode = kmode
         self.K_const = float(K_const)
@@ -204,6 +210,15 @@ class Oracle:
         self.T[level] = None if T is None else np.array(T, dtype=np.float64).reshape(n)
 
     # ------------------------------------------------------------- diffusivity
+    def K_of_value(self, E, rho):
+        """Diffusivity of a boundary value: K_const, K_const E^K_exp, or c lambda(0) /
+        (rho kappa_R) = c / (3 rho kappa_R) (no gradient at a held value)."""
+        if self.kmode == "const":
+            return np.full(np.shape(rho), self.K_const)
+        if self.kmode == "power":
+            return np.full(np.shape(rho), self.K_const * E ** self.K_exp)
+        return self.c / (3.0 * rho * self.kappa_R)
+
     def grad_E(self, level):
         """Per-slot gradient of E with the neighbour distances of the stencil reading."""
         L = self.lev[level]
@@ -222,6 +237,10 @@ class Oracle:
                 if m.any():
                     v[m] = self.E[level - 1][nb[m]]
                     h[m] = 1.5 * L.dx
+                if d in self.outer:  # Dirichlet value held at the outer face, dx / 2 away
+                    m = t == OUTER
+                    v[m] = self.outer[d]
+                    h[m] = 0.5 * L.dx
                 vals.append(v)
                 dist.append(h)
             g[:, axis] = (vals[1] - vals[0]) / (dist[0] + dist[1])
@@ -232,6 +251,8 @@ class Oracle:
         L = self.lev[level]
         if self.kmode == "const":
             return np.full(L.n_slots, self.K_const)
+        if self.kmode == "power":
+            return self.K_const * self.E[level] ** self.K_exp
         rho, E = self.rho[level], self.E[level]
         g = self.grad_E(level)
         gn = np.sqrt(np.sum(g * g, axis=1))
@@ -275,6 +296,11 @@ class Oracle:
                 C = (2.0 / 3.0) * harmonic_mean(K[leaves[m]], Kc[nb[m]]) * coef
                 diag[m] += C
                 b[m] += C * self.E[level - 1][nb[m]]
+            m = t == OUTER
+            if d in self.outer and m.any():
+                C = self._outer_C(K[leaves[m]], self.rho[level][leaves[m]], d, coef)
+                diag[m] += C
+                b[m] += C * self.outer[d]
         coupling = None
         if self.T.get(level) is not None:
             T = self.T[level][leaves]
@@ -296,6 +322,12 @@ class Oracle:
         return A, b, coupling
 
     # ------------------------------------------------------------------- solve
+    def _outer_C(self, Ki, rho, d, coef):
+        """Face held at a Dirichlet value dx / 2 from the cell centre: C = 2 K_f dt / dx^2,
+        K_f the harmonic mean of the cell's and the boundary value's diffusivity."""
+        Kb = self.K_of_value(self.outer[d], rho)
+        return 2.0 * harmonic_mean(Ki, Kb) * coef
+
     def theta_scheme(self, A1, b1, En):
         """Theta-weighted form of a backward-Euler system (Crank-Nicolson for theta = 1/2,
         the remedy Sect. 3.3.6 names for the first-order time error): the face fluxes are
@@ -441,6 +473,11 @@ class Oracle:
                     rows.append(gi[m])
                     cols.append(off[l - 1] + self.lev[l - 1].leaf_of[nb[m]])
                     vals.append(-L.vol * C)
+                m = t == OUTER
+                if d in self.outer and m.any():
+                    C = self._outer_C(K[l][leaves[m]], self.rho[l][leaves[m]], d, coef)
+                    diag[m] += C
+                    bl[m] += C * self.outer[d]
                 m = t == C2F
                 if m.any():
                     ch = self._facing_children(l, nb[m], d)

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_D
                 -5: "E_NOCONV", -6: "E_NONFINITE"}
 BC_DIRICHLET, BC_NEUMANN, BC_ROBIN = 0, 1, 2
 FP64, MIXED = 0, 1
-K_CONST, K_LP, K_MINERBO = 0, 1, 2
+K_CONST, K_LP, K_MINERBO, K_POWER = 0, 1, 2, 3
 
 
 class amrfld_opts(ctypes.Structure):
@@ -33,6 +33,7 @@ class amrfld_opts(ctypes.Structure):
         ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("max_blocks", ctypes.c_int),
         ("persistent", ctypes.c_int), ("graph", ctypes.c_int), ("stream", ctypes.c_void_p),
         ("persistent_per_cu", ctypes.c_int), ("theta", ctypes.c_double),
+        ("K_exp", ctypes.c_double), ("outer_mode", ctypes.c_int * 6), ("outer_value", ctypes.c_double * 6),
     ]
 
 

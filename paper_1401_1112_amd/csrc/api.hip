@@ -52,7 +52,7 @@ struct LevelState {
   double *Cp = nullptr, *diag = nullptr, *b = nullptr, *reg = nullptr;
   bool has_fields = false, has_T = false;
   int kmode = 1;
-  double K_const = 1.0, kappa_R = 1.0, kappa_P = 1.0, c_light = 1.0;
+  double K_const = 1.0, kappa_R = 1.0, kappa_P = 1.0, c_light = 1.0, K_exp = 0.0;
 
   DevLevel dev() const {
     DevLevel d;
@@ -258,7 +258,18 @@ CellKParams kparams(const LevelState& L) {
   k.K_const = L.K_const;
   k.kappa_R = L.kappa_R;
   k.c_light = L.c_light;
+  k.K_exp = L.K_exp;
   return k;
+}
+
+OuterBC outer_bc(const amrfld_ctx* c) {
+  OuterBC b;
+  for (int d = 0; d < 6; ++d)
+    if (c->o.outer_mode[d] == 1) {
+      b.mask |= 1u << d;
+      b.val[d] = c->o.outer_value[d];
+    }
+  return b;
 }
 
 CouplingParams cparams(const amrfld_ctx* c, const LevelState& L) {
@@ -524,13 +535,13 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   // diffusivities of this level and of the coarser one (fine-to-coarse faces)
   if (Lc) {
     const double* Ecc = level - 1 > c->o.base_level ? c->L(level - 2).E : nullptr;
-    launch_cell_K(s, Lc->dev(), Lc->E, Lc->rho, Ecc, kparams(*Lc), Lc->K);
+    launch_cell_K(s, Lc->dev(), Lc->E, Lc->rho, Ecc, kparams(*Lc), outer_bc(c), Lc->K);
   }
-  launch_cell_K(s, D, L.E, L.rho, Lc ? Lc->E : nullptr, kparams(L), L.K);
+  launch_cell_K(s, D, L.E, L.rho, Lc ? Lc->E : nullptr, kparams(L), outer_bc(c), L.K);
   const double w = mode == AMRFLD_BC_DIRICHLET ? 1.0 : mode == AMRFLD_BC_NEUMANN ? 0.0 : c->o.robin_alpha;
   const CouplingParams cp = cparams(c, L);
   launch_assemble(s, D, L.K, Lc ? Lc->K : nullptr, L.E, Lc ? Lc->E : nullptr, L.rho, L.reg, dt, w,
-                  c->o.robin_alpha, cp, L.Cp, L.diag, L.b);
+                  c->o.robin_alpha, cp, kparams(L), outer_bc(c), L.Cp, L.diag, L.b);
   if (c->o.theta != 1.0) launch_theta_step(s, D, c->o.theta, L.E, L.Cp, L.diag, L.b);
 
   const int n_tiles = tiles_of(D.n_slots);
@@ -793,7 +804,7 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   for (int k = 0; k < C.n_levels; ++k) {
     LevelState& L = c->L(base + k);
     const double* Ec = k > 0 ? c->L(base + k - 1).E : nullptr;
-    launch_cell_K(s, L.dev(), L.E, L.rho, Ec, kparams(L), C.K + C.off[k]);
+    launch_cell_K(s, L.dev(), L.E, L.rho, Ec, kparams(L), outer_bc(c), C.K + C.off[k]);
     const size_t bytes = size_t(L.t.n_slots()) * sizeof(double);
     check(hipMemcpyAsync(C.x + C.off[k], L.E, bytes, hipMemcpyDeviceToDevice, s), "gather");
     check(hipMemcpyAsync(C.rho + C.off[k], L.rho, bytes, hipMemcpyDeviceToDevice, s), "gather");
@@ -803,13 +814,18 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
     P.dx = dx;
     P.vol = dx * dx * dx;
     P.coef = dt / (dx * dx);
+    P.kmode = L.kmode;  // the level's law, for the diffusivity of values held at box faces
+    P.K_const = L.K_const;
+    P.K_exp = L.K_exp;
+    P.kappa_R = L.kappa_R;
+    P.c_light = L.c_light;
   }
   check(hipMemcpyAsync(C.pp, C.pp_host.data(), C.n_levels * sizeof(PatchParams), hipMemcpyHostToDevice, s),
         "parameters");
   CouplingParams cp = cparams(c, c->L(base));
   cp.T = coupled ? C.T : nullptr;
   const DevLevel D = C.dev();
-  launch_assemble_composite(s, D, C.K, C.x, C.rho, cp, dt, C.Cp, C.cif, C.c2f, C.diag, C.b);
+  launch_assemble_composite(s, D, C.K, C.x, C.rho, cp, outer_bc(c), dt, C.Cp, C.cif, C.c2f, C.diag, C.b);
   launch_interface_values(s, C.n_if_entries, C.if_src, C.cif, C.if_val);
   const int n_tiles = tiles_of(C.n_slots);
   const int B = c->o.max_blocks > 0 ? c->o.max_blocks : 1024;
@@ -1006,9 +1022,9 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
     launch_zero_u32(st, c->bar, kBarWords);
     for (int step = 0; step < n_steps; ++step) {
       PcgScalars* sc = c->sc + int64_t(step) * np;
-      launch_cell_K(st, D, B.E, B.rho, nullptr, kp, B.K);
-      launch_assemble(st, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, B.Cp,
-                      B.diag, B.b);
+      launch_cell_K(st, D, B.E, B.rho, nullptr, kp, OuterBC{}, B.K);
+      launch_assemble(st, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, kp,
+                      OuterBC{}, B.Cp, B.diag, B.b);
       launch_init_scalars(st, sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
       launch_zero_u32(st, c->bar, kBarAbort);
       launch_pcg_init<double>(st, D, P, B.Cp, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
@@ -1148,11 +1164,11 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
   for (int step = 0; step < n_steps; ++step) {
     check(hipEventRecord(c->ev[0], s), "event");
     const CellKParams kp{1, 1.0, 1.0, 1.0};
-    launch_cell_K(s, D, B.E, B.rho, nullptr, kp, B.K);
+    launch_cell_K(s, D, B.E, B.rho, nullptr, kp, OuterBC{}, B.K);
     CouplingParams cp{};
     cp.T = nullptr;
-    launch_assemble(s, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, B.Cp,
-                    B.diag, B.b);
+    launch_assemble(s, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, kp,
+                    OuterBC{}, B.Cp, B.diag, B.b);
     LoopStats ls;
     ls.iters.assign(np, 0);
     std::vector<int> outer_iters(np, 0);
@@ -1265,6 +1281,15 @@ amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
     g_create_error = "theta must be in [0.5, 1]";
     return AMRFLD_E_INVALID;
   }
+  if (!std::isfinite(o->K_exp)) {
+    g_create_error = "K_exp must be finite";
+    return AMRFLD_E_INVALID;
+  }
+  for (int d = 0; d < 6; ++d)
+    if ((o->outer_mode[d] != 0 && o->outer_mode[d] != 1) || (o->outer_mode[d] == 1 && !std::isfinite(o->outer_value[d]))) {
+      g_create_error = "outer_mode must be 0 or 1, with a finite outer_value where it is 1";
+      return AMRFLD_E_INVALID;
+    }
   amrfld_ctx* c = nullptr;
   try {
     c = new amrfld_ctx();
@@ -1379,11 +1404,12 @@ amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, con
   if (!c) return AMRFLD_E_INVALID;
   if (level < c->o.base_level || level > c->finest) return fail(c, AMRFLD_E_INVALID, "level not built");
   if (!rho || !E) return fail(c, AMRFLD_E_INVALID, "rho and E are required");
-  if (kmode != AMRFLD_K_CONST && kmode != AMRFLD_K_LP && kmode != AMRFLD_K_MINERBO)
+  if (kmode != AMRFLD_K_CONST && kmode != AMRFLD_K_LP && kmode != AMRFLD_K_MINERBO && kmode != AMRFLD_K_POWER)
     return fail(c, AMRFLD_E_INVALID, "unknown kmode");
-  if (kmode != AMRFLD_K_CONST && !(kappa_R > 0.0 && c_light > 0.0))
+  if ((kmode == AMRFLD_K_LP || kmode == AMRFLD_K_MINERBO) && !(kappa_R > 0.0 && c_light > 0.0))
     return fail(c, AMRFLD_E_INVALID, "kappa_R and c_light must be positive");
-  if (kmode == AMRFLD_K_CONST && !(K_const >= 0.0)) return fail(c, AMRFLD_E_INVALID, "K_const must be >= 0");
+  if ((kmode == AMRFLD_K_CONST || kmode == AMRFLD_K_POWER) && !(K_const >= 0.0 && std::isfinite(K_const)))
+    return fail(c, AMRFLD_E_INVALID, "K_const must be finite and >= 0");
   if (T && !(kappa_P >= 0.0 && c_light > 0.0)) return fail(c, AMRFLD_E_INVALID, "kappa_P >= 0 and c_light > 0 needed with T");
   return guarded(c, [&]() -> amrfld_status {
     LevelState& L = c->L(level);
@@ -1401,6 +1427,7 @@ amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, con
     L.kappa_R = kappa_R;
     L.kappa_P = kappa_P;
     L.c_light = c_light;
+    L.K_exp = c->o.K_exp;
     L.has_fields = true;
     return AMRFLD_OK;
   });

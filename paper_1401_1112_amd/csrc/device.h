@@ -46,6 +46,7 @@ struct PatchParams {
   double ghost[6], flux[6];
   int mode[6];
   int kmode;
+  double K_exp;  // composite system: the level's power-law exponent (boundary diffusivity)
 };
 
 // One level's (or one batch's) device tables, slot order.  child: >= 0 child
@@ -111,8 +112,17 @@ inline SweepPlan single_plan(int G, int n_tiles) {
 }
 
 struct CellKParams {
-  int kmode;  // 0 const, 1 Levermore-Pomraning
+  int kmode;  // 0 const, 1 Levermore-Pomraning, 2 Minerbo, 3 power law K_const E^K_exp
   double K_const, kappa_R, c_light;
+  double K_exp = 0.0;
+};
+
+// Faces of the unit box (directions -x, +x, -y, +y, -z, +z): bit d of mask set
+// means a Dirichlet energy val[d] held at that face, dx / 2 from the cell centres;
+// the other faces carry no flux.
+struct OuterBC {
+  unsigned mask = 0;
+  double val[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 };
 
 struct CouplingParams {
@@ -125,13 +135,14 @@ int grid_for(int64_t n);
 
 // ------------------------------------------------------------ setup kernels
 void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const double* rho,
-                   const double* E_coarse, const CellKParams& kp, double* K);
+                   const double* E_coarse, const CellKParams& kp, const OuterBC& ob, double* K);
 // w: weight of the coarse-to-fine Dirichlet part (1 D, 0 N, alpha R); alpha: Robin
-// weight of batch patch faces whose mode is Robin.
+// weight of batch patch faces whose mode is Robin; kp and ob: the diffusivity law and
+// the box faces' Dirichlet values (no patch table).
 void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const double* K_coarse,
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
-                     double dt, double w, double alpha, const CouplingParams& cp, double* Cp,
-                     double* diag, double* b);
+                     double dt, double w, double alpha, const CouplingParams& cp, const CellKParams& kp,
+                     const OuterBC& ob, double* Cp, double* diag, double* b);
 // Theta-weighted step (Crank-Nicolson at 1/2) from an assembled backward-Euler
 // level system: b -= (1 - theta) (A E - E) on the leaves, then A = I + theta (A - I).
 void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E, double* Cp, double* diag,
@@ -141,8 +152,8 @@ void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const dou
 // refined-neighbour mask c2f, diagonal and right-hand side; E is the concatenated
 // energy, K the concatenated diffusivity of every level.
 void launch_assemble_composite(hipStream_t s, const DevLevel& C, const double* K, const double* E,
-                               const double* rho, const CouplingParams& cp, double dt, double* Cp, double* cif,
-                               uint8_t* c2f, double* diag, double* b);
+                               const double* rho, const CouplingParams& cp, const OuterBC& ob, double dt,
+                               double* Cp, double* cif, uint8_t* c2f, double* diag, double* b);
 void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, const double* K_c,
                           const double* E_f, const double* E_c, double dt, double* reg_c,
                           int n_slots_c);

@@ -12,11 +12,20 @@ namespace {
 using dev::harmonic;
 using dev::same_level_nb;
 
+// Diffusivity of an energy held at a box face: the cell law at that value with no
+// gradient there (flux limiter at R = 0, 1/3 for both limiters).
+__device__ inline double held_K(int kmode, double K_const, double K_exp, double kappa_R, double c_light,
+                                double rho, double v) {
+  if (kmode == 0) return K_const;
+  if (kmode == 3) return K_const * pow(v, K_exp);
+  return c_light / (3.0 * rho * kappa_R);
+}
+
 // ----------------------------------------------------------- setup kernels
 __global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __restrict__ E,
                                                    const double* __restrict__ rho,
                                                    const double* __restrict__ Ec, CellKParams kp,
-                                                   double* __restrict__ K) {
+                                                   OuterBC ob, double* __restrict__ K) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= L.n_slots) return;
   if (L.child[i] == -2) {  // padding slot of a batch
@@ -27,6 +36,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __r
   const int kmode = pp ? pp->kmode : kp.kmode;
   if (kmode == 0) {
     K[i] = pp ? pp->K_const : kp.K_const;
+    return;
+  }
+  if (kmode == 3) {  // power law (nonlinear equilibrium test, Sect. 4.2); levels only
+    K[i] = kp.K_const * pow(E[i], kp.K_exp);
     return;
   }
   const double dx = pp ? pp->dx : L.dx;
@@ -49,6 +62,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __r
         if (c >= 0) {
           v[side] = Ec[c];
           h[side] = 1.5 * dx;
+        } else if (!pp && ((ob.mask >> dir) & 1u)) {  // value held at the box face
+          v[side] = ob.val[dir];
+          h[side] = 0.5 * dx;
         } else {
           v[side] = Ei;
           h[side] = dx;
@@ -95,8 +111,8 @@ __global__ __launch_bounds__(kBlock) void k_theta_scale(int n, double theta, dou
 __global__ __launch_bounds__(kBlock) void k_assemble(
     DevLevel L, const double* __restrict__ K, const double* __restrict__ Kc,
     const double* __restrict__ E, const double* __restrict__ Ec, const double* __restrict__ rho,
-    const double* __restrict__ reg, double coef, double w, double alpha, CouplingParams cp, double dt,
-    double* __restrict__ Cp, double* __restrict__ diag, double* __restrict__ b) {
+    const double* __restrict__ reg, double coef, double w, double alpha, CouplingParams cp, CellKParams kp,
+    OuterBC ob, double dt, double* __restrict__ Cp, double* __restrict__ diag, double* __restrict__ b) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int n = L.n_slots;
   if (i >= n) return;
@@ -138,6 +154,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
         const double C = Ki * coef;  // ghost cell with the cell's own diffusivity
         d += wf * C;
         bb += wf * C * pp->ghost[dir] + (1.0 - wf) * pp->flux[dir];
+      } else if ((ob.mask >> dir) & 1u) {  // Dirichlet value held at the box face, dx / 2 away
+        const double v = ob.val[dir];
+        const double C = 2.0 * harmonic(Ki, held_K(kp.kmode, kp.K_const, kp.K_exp, kp.kappa_R, kp.c_light,
+                                                   rho[i], v)) * coef;
+        d += C;
+        bb += C * v;
       }
     }
   }
@@ -165,8 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
 // (V_f (2/3) A_f, equal to V_c A_c / 3), and read by both rows.
 __global__ __launch_bounds__(kBlock) void k_assemble_composite(
     DevLevel L, const double* __restrict__ K, const double* __restrict__ E, const double* __restrict__ rho,
-    CouplingParams cp, double dt, double* __restrict__ Cp, double* __restrict__ cif, uint8_t* __restrict__ c2f,
-    double* __restrict__ diag, double* __restrict__ b) {
+    CouplingParams cp, OuterBC ob, double dt, double* __restrict__ Cp, double* __restrict__ cif,
+    uint8_t* __restrict__ c2f, double* __restrict__ diag, double* __restrict__ b) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int n = L.n_slots;
   if (i >= n) return;
@@ -210,6 +232,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble_composite(
         const double C = (2.0 / 3.0) * harmonic(Ki, K[c]) * coef;
         d += C;
         cf[a] = V * C;
+      } else if ((ob.mask >> dir) & 1u) {  // Dirichlet value held at the box face, dx / 2 away
+        const double v = ob.val[dir];
+        const double C = 2.0 * harmonic(Ki, held_K(P.kmode, P.K_const, P.K_exp, P.kappa_R, P.c_light, rho[i], v)) *
+                         coef;
+        d += C;
+        bb += C * v;
       }
     }
   }
@@ -319,25 +347,25 @@ void launch_batch_scatter(hipStream_t s, const DevLevel& L, const int32_t* idx, 
 }
 
 void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const double* rho,
-                   const double* E_coarse, const CellKParams& kp, double* K) {
+                   const double* E_coarse, const CellKParams& kp, const OuterBC& ob, double* K) {
   hipLaunchKernelGGL(k_cell_K, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, E, rho, E_coarse,
-                     kp, K);
+                     kp, ob, K);
 }
 
 void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const double* K_coarse,
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
-                     double dt, double w, double alpha, const CouplingParams& cp, double* Cp, double* diag,
-                     double* b) {
+                     double dt, double w, double alpha, const CouplingParams& cp, const CellKParams& kp,
+                     const OuterBC& ob, double* Cp, double* diag, double* b) {
   const double coef = dt / (L.dx * L.dx);
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, K, K_coarse, E,
-                     E_coarse, rho, reg, coef, w, alpha, cp, dt, Cp, diag, b);
+                     E_coarse, rho, reg, coef, w, alpha, cp, kp, ob, dt, Cp, diag, b);
 }
 
 void launch_assemble_composite(hipStream_t s, const DevLevel& C, const double* K, const double* E,
-                               const double* rho, const CouplingParams& cp, double dt, double* Cp, double* cif,
-                               uint8_t* c2f, double* diag, double* b) {
-  hipLaunchKernelGGL(k_assemble_composite, dim3(grid_for(C.n_slots)), dim3(kBlock), 0, s, C, K, E, rho, cp, dt, Cp,
-                     cif, c2f, diag, b);
+                               const double* rho, const CouplingParams& cp, const OuterBC& ob, double dt,
+                               double* Cp, double* cif, uint8_t* c2f, double* diag, double* b) {
+  hipLaunchKernelGGL(k_assemble_composite, dim3(grid_for(C.n_slots)), dim3(kBlock), 0, s, C, K, E, rho, cp, ob, dt,
+                     Cp, cif, c2f, diag, b);
 }
 
 void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E, double* Cp, double* diag,

@@ -6,7 +6,8 @@ calibrate the per-dispatch HBM byte counters of the solver kernels.
 
 ``python -m paper_1401_1112_amd.profiling batch --patches 512 --steps 2 --mode polled``
 runs the batched workload alone (for kernel traces of the batch form);
-``... collapse --mode polled --precision mixed`` likewise the collapse-like hierarchy.
+``... collapse --mode polled --precision mixed`` likewise the collapse-like hierarchy, and
+``... unique --steps 1`` the unique-time-step composite solves of the lognormal hierarchy.
 
 ``python -m paper_1401_1112_amd.profiling summarize DIR`` prints a per-kernel
 summary (count, average duration, and the averages of any counters) from the
@@ -97,6 +98,40 @@ def run_collapse(steps: int, mode: str, precision: str) -> None:
     s.close()
 
 
+def run_unique(steps: int) -> None:
+    """The unique-time-step comparison on the lognormal hierarchy (levels 6..9, 4.0 M
+    cells): one warm-up and `steps` timed coarse steps, each 8 composite solves over all
+    levels, from the same state."""
+    import time
+
+    import torch
+
+    from synth.configs import config_fld_lognormal
+
+    from .solver import solver_from_problem
+    p = config_fld_lognormal()
+    s = solver_from_problem(p)
+    fields = {lv: tuple(t.clone() for t in s._fields[lv][:2]) for lv in s.levels}
+
+    def step():
+        for lv in s.levels:
+            rho, E = fields[lv]
+            s.set_fields(lv, rho, E, kmode=1)
+        s.advance_unique(p.dt_coarse, p.tol)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    st = s.stats()
+    print(f"unique: {el * 1e3:.1f} ms per coarse step, {len(st)} composite solves, "
+          f"{sum(x['iters'] for x in st)} PCG iterations over {st[0]['n_leaf']} cells", flush=True)
+    s.close()
+
+
 def _short(name: str) -> str:
     for pre in ("amrfld::(anonymous namespace)::", "void "):
         name = name.replace(pre, "")
@@ -155,8 +190,12 @@ def main(argv=None):
     cl.add_argument("--steps", type=int, default=1)
     cl.add_argument("--mode", choices=("polled", "persistent"), default="polled")
     cl.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
+    u = sub.add_parser("unique")
+    u.add_argument("--steps", type=int, default=1)
     a = ap.parse_args(argv)
-    if a.cmd == "collapse":
+    if a.cmd == "unique":
+        run_unique(a.steps)
+    elif a.cmd == "collapse":
         run_collapse(a.steps, a.mode, a.precision)
     elif a.cmd == "copy":
         run_copy(a.mib, a.reps)

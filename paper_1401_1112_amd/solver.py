@@ -12,7 +12,8 @@ class HierarchySolver:
     def __init__(self, base_level, octs, *, robin_alpha=0.5, max_iter=10000, precision=L.FP64,
                  linf_test=True, abs_floor=1e-14, a_rad=1.0, c_v=1.0, nsub=None, check_every=0,
                  true_residual=True, time_sweeps=0, inner_tol=1e-4, max_outer=30, max_blocks=0,
-                 persistent=False, persistent_per_cu=0, theta=1.0, device="cuda:0", stream=None):
+                 persistent=False, persistent_per_cu=0, theta=1.0, K_exp=0.0, outer=None, device="cuda:0",
+                 stream=None):
         L.load()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -37,6 +38,10 @@ class HierarchySolver:
         o.persistent = int(bool(persistent))
         o.persistent_per_cu = int(persistent_per_cu)
         o.theta = float(theta)
+        o.K_exp = float(K_exp)
+        for d, v in (outer or {}).items():  # box face direction -> Dirichlet energy held there
+            o.outer_mode[int(d)] = 1
+            o.outer_value[int(d)] = float(v)
         o.stream = self.stream.cuda_stream
         self.ctx = L.amrfld_create(o)
         self.levels = list(range(int(base_level), int(max(octs)) + 1))
@@ -126,7 +131,7 @@ class HierarchySolver:
 
 def sample_problem_fields(solver: HierarchySolver, problem):
     """Sample a problem's fields in the library's cell order and upload them."""
-    kmode = {"const": L.K_CONST, "lp": L.K_LP, "minerbo": L.K_MINERBO}[problem.kmode]
+    kmode = {"const": L.K_CONST, "lp": L.K_LP, "minerbo": L.K_MINERBO, "power": L.K_POWER}[problem.kmode]
     for lvl in solver.levels:
         c = solver.cells(lvl)
         T = None if problem.T is None else problem.T(lvl, c)
@@ -138,7 +143,8 @@ def sample_problem_fields(solver: HierarchySolver, problem):
 def solver_from_problem(problem, **over):
     kw = dict(robin_alpha=problem.robin_alpha, max_iter=problem.max_iter, linf_test=problem.linf_test,
               abs_floor=problem.abs_floor, a_rad=problem.a_rad, c_v=problem.c_v, nsub=problem.nsub,
-              theta=getattr(problem, "theta", 1.0))
+              theta=getattr(problem, "theta", 1.0), K_exp=getattr(problem, "K_exp", 0.0),
+              outer=getattr(problem, "outer", None))
     kw.update(over)
     s = HierarchySolver(problem.hierarchy.base_level, problem.hierarchy.octs, **kw)
     sample_problem_fields(s, problem)

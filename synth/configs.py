@@ -44,6 +44,8 @@ class Problem:
     linf_test: bool = True
     max_iter: int = 10000
     theta: float = 1.0           # 1: backward Euler, 1/2: Crank-Nicolson
+    K_exp: float = 0.0           # kmode "power": K = K_const E^K_exp
+    outer: Optional[dict] = None  # outer face direction -> Dirichlet value (others zero flux)
     info: dict = field(default_factory=dict)
 
     def nsub_of(self, level: int) -> int:
@@ -204,6 +206,57 @@ def config_dirac_slab(base_level: int = 5, max_level: int = 8, widths=(0.25, 0.1
     return Problem(f"dirac_slab_L{base_level}-{top}", h, rho, E, kmode="const", K_const=1.0,
                    dt_coarse=dt_coarse, bc_mode=bc_mode, robin_alpha=robin_alpha, tol=tol,
                    n_coarse_steps=n_coarse_steps, info={"refined_per_level": counts, "E0": E0, "pulse_half": half})
+
+
+def equilibrium_profile(x, a: float = 1.5, E_left: float = 4.0, E_right: float = 0.5):
+    """Stationary solution of d/dx (E^a dE/dx) = 0 on [0, 1] with E(0) = E_left and
+    E(1) = E_right: E^(a+1) is linear in x (Sect. 4.2)."""
+    lo, hi = E_left ** (a + 1.0), E_right ** (a + 1.0)
+    return ((hi - lo) * np.asarray(x, dtype=np.float64) + lo) ** (1.0 / (a + 1.0))
+
+
+def config_equilibrium(base_level: int = 3, max_level: int = 7, a: float = 1.5, E_left: float = 4.0,
+                       E_right: float = 0.5, threshold: float = 0.1, dt_coarse: float = 0.05,
+                       n_coarse_steps: int = 200, tol: float = 1e-8, bc_mode: str = "dirichlet") -> Problem:
+    """Equilibrium test with a nonlinear diffusivity (Sect. 4.2), plane-parallel in 3D.
+
+    rho = 1, K = E^a (the diffusivity the stationary profile of the paper belongs to),
+    Dirichlet values E_left at x = 0 and E_right at x = 1 held at the faces, zero flux
+    through the y and z faces, and a step E = E_left for x < 1/2, E_right above as the
+    initial state.  The mesh is the one the run settles on: a level-l cell is refined where
+    the relative change of the stationary profile over one cell, dx |E'| / E, exceeds
+    ``threshold`` at the cell or at one of its x neighbours (one buffer cell), over the
+    whole y-z extent.  base_level == max_level gives a uniform grid."""
+
+    def rel_change(level, x):
+        dx = 1.0 / (1 << level)
+        lo, hi = E_left ** (a + 1.0), E_right ** (a + 1.0)
+        u = (hi - lo) * x + lo
+        return dx * np.abs((hi - lo) / (a + 1.0) / u)
+
+    def criterion(level, ijk):
+        dx = 1.0 / (1 << level)
+        x = (ijk[:, 0] + 0.5) * dx
+        c = rel_change(level, x)
+        for s in (-1.0, 1.0):
+            xn = x + s * dx
+            ok = (xn > 0.0) & (xn < 1.0)
+            c = np.where(ok, np.maximum(c, rel_change(level, np.clip(xn, 0.0, 1.0))), c)
+        return c
+
+    h, counts = budgeted_hierarchy(base_level, max_level, criterion, threshold, 1 << 62, seed=23)
+    top = max(h.levels)
+
+    def E(level, ijk):
+        return np.where((ijk[:, 0] + 0.5) / (1 << level) < 0.5, E_left, E_right)
+
+    def rho(level, ijk):
+        return np.ones(len(ijk))
+
+    return Problem(f"equilibrium_L{base_level}-{top}", h, rho, E, kmode="power", K_const=1.0, K_exp=a,
+                   outer={0: E_left, 1: E_right}, dt_coarse=dt_coarse, bc_mode=bc_mode, tol=tol,
+                   n_coarse_steps=n_coarse_steps,
+                   info={"refined_per_level": counts, "a": a, "E_left": E_left, "E_right": E_right})
 
 
 def config_tiny(seed: int, base_level: int = 2, max_level: int = 4, kmode: str = "lp",

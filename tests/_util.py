@@ -11,7 +11,7 @@ def oracle_from_problem(p, **over):
     kw = dict(kmode=p.kmode, K_const=p.K_const, kappa_R=p.kappa_R, kappa_P=p.kappa_P,
               c_light=p.c_light, a_rad=p.a_rad, c_v=p.c_v, robin_alpha=p.robin_alpha,
               abs_floor=p.abs_floor, linf_test=p.linf_test, max_iter=p.max_iter, nsub=p.nsub,
-              theta=getattr(p, "theta", 1.0))
+              theta=getattr(p, "theta", 1.0), K_exp=getattr(p, "K_exp", 0.0), outer=getattr(p, "outer", None))
     kw.update(over)
     o = Oracle(p.hierarchy.base_level, p.hierarchy.octs, **kw)
     for l in p.hierarchy.levels:

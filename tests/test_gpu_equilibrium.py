@@ -1,0 +1,187 @@
+"""The nonlinear equilibrium test (Sect. 4.2) on the GPU: power-law diffusivity
+K = E^1.5, Dirichlet energies held at x = 0 and x = 1, plane-parallel relaxation to the
+stationary profile (E^2.5 linear in x).
+
+Reduced size (levels 3..5): parity with the oracle at every coarse step, for the adaptive
+step with each interface condition and for the unique time step (equal counts and 1e-12,
+else fixed counts); a flux-limited variant exercises the held values in the gradient.
+The paper's mesh (levels 3..7, 28 cells along x): parity over the first coarse steps; the
+steady state within the discretisation error of the profile, adaptive and unique alike;
+the unique step balances the boundary fluxes; a linear profile stays fixed.  Uniform
+grids of 8..128 cells per side approach the profile at close to second order."""
+import numpy as np
+import pytest
+
+import oracle as ora
+from synth.configs import config_equilibrium, equilibrium_profile
+from test_gpu_parity import MODES, _parity_protocol
+from test_gpu_unique import _parity as _unique_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _leaf_masks(s, p):
+    out = {}
+    for l in p.hierarchy.levels:
+        c = s.cells(l).astype(np.int64)
+        m = np.ones(len(c), dtype=bool)
+        if l + 1 in p.hierarchy.octs:
+            par = np.asarray(p.hierarchy.octs[l + 1], dtype=np.int64)
+            n = np.int64(1) << l
+            m = ~np.isin((c[:, 0] * n + c[:, 1]) * n + c[:, 2], (par[:, 0] * n + par[:, 1]) * n + par[:, 2])
+        out[l] = (m, c)
+    return out
+
+
+def _leaves(s, masks):
+    from paper_1401_1112_amd.solver import to_numpy
+    return {l: to_numpy(s.E(l))[m] for l, (m, _) in masks.items()}
+
+
+def _steady(s, p, masks, unique=False, max_steps=600, eps=1e-12):
+    from paper_1401_1112_amd import BC_DIRICHLET
+    prev = _leaves(s, masks)
+    for k in range(max_steps):
+        if unique:
+            s.advance_unique(p.dt_coarse, p.tol)
+        else:
+            s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+        cur = _leaves(s, masks)
+        if max(float(np.abs(cur[l] - prev[l]).max()) for l in cur) < eps:
+            return k + 1, cur
+        prev = cur
+    raise AssertionError("no steady state")
+
+
+def _l2(leaves, masks, a=1.5):
+    e2 = 0.0
+    for l, e in leaves.items():
+        c = masks[l][1][masks[l][0]]
+        x = (c[:, 0] + 0.5) / (1 << l)
+        e2 += float(np.sum((e - equilibrium_profile(x, a)) ** 2)) / float(1 << (3 * l))
+    return np.sqrt(e2)
+
+
+def _boundary_fluxes(leaves, masks, p):
+    out = []
+    for d, face in ((0, 0), (1, None)):
+        v, F = p.outer[d], 0.0
+        for l, e in leaves.items():
+            c = masks[l][1][masks[l][0]]
+            on = c[:, 0] == (0 if face == 0 else (1 << l) - 1)
+            dx = 1.0 / (1 << l)
+            Ki, Kb = e[on] ** p.K_exp, v ** p.K_exp
+            F += float(np.sum(2.0 * (2.0 * Ki * Kb / (Ki + Kb)) * (v - e[on]) / dx)) * dx * dx
+        out.append(F)
+    return out
+
+
+@pytest.mark.parametrize("mode", ["dirichlet", "neumann", "robin"])
+def test_equilibrium_parity_adaptive_reduced(mode):
+    p = config_equilibrium(max_level=5, tol=1e-12)
+    print(f"{mode}: {_parity_protocol(p, MODES[mode], steps=4)}")
+
+
+def test_equilibrium_parity_unique_reduced():
+    _unique_parity(config_equilibrium(max_level=5, tol=1e-12), 4)
+
+
+def test_equilibrium_flux_limited_parity():
+    # LP-limited diffusivity: the gradient takes the held values dx / 2 away
+    p = config_equilibrium(max_level=5, tol=1e-12)
+    p.kmode, p.kappa_R = "lp", 0.5
+    print(f"lp adaptive: {_parity_protocol(p, ora.DIRICHLET, steps=3)}")
+    _unique_parity(p, 3)
+
+
+def test_equilibrium_paper_mesh_parity():
+    p = config_equilibrium(tol=1e-12)
+    print(f"levels 3..7: {_parity_protocol(p, ora.DIRICHLET, steps=2)}")
+
+
+@pytest.fixture(scope="module")
+def steady_states():
+    from paper_1401_1112_amd.solver import solver_from_problem
+    out = {}
+    for unique in (False, True):
+        p = config_equilibrium(tol=1e-10)
+        s = solver_from_problem(p)
+        masks = _leaf_masks(s, p)
+        steps, leaves = _steady(s, p, masks, unique=unique)
+        s.close()
+        out[unique] = (steps, leaves, masks, p)
+    return out
+
+
+def test_equilibrium_steady_state_paper_mesh(steady_states):
+    (sa, la, ma, p), (su, lu, mu, _) = steady_states[False], steady_states[True]
+    ea, eu = _l2(la, ma), _l2(lu, mu)
+    print(f"levels 3..7: adaptive {sa} steps, L2 {ea:.4e}; unique {su} steps, L2 {eu:.4e}")
+    assert ea < 0.01 and eu < 0.01
+    # close on the paper's log scale: at 4 levels the non-conservative interfaces of the
+    # adaptive step cost a third more L2 error than the composite system (1.95e-3 against
+    # 1.45e-3), at 2 levels (oracle) the adaptive error is the smaller one
+    assert max(ea, eu) <= 1.5 * min(ea, eu)
+    rel = [float(np.max(np.abs(la[l] / equilibrium_profile((ma[l][1][ma[l][0]][:, 0] + 0.5) / (1 << l)) - 1)))
+           for l in la]
+    assert max(rel) < 0.05, rel  # relative errors of a few percent at most (Fig. 5)
+
+
+def test_equilibrium_unique_balances_boundary_fluxes(steady_states):
+    exact = (4.0 ** 2.5 - 0.5 ** 2.5) / 2.5
+    _, lu, mu, p = steady_states[True]
+    f_in, f_out = _boundary_fluxes(lu, mu, p)
+    assert abs(f_in + f_out) <= 1e-7 * abs(f_in), (f_in, f_out)
+    assert abs(f_in - exact) <= 0.01 * exact
+    _, la, ma, p = steady_states[False]
+    g_in, g_out = _boundary_fluxes(la, ma, p)
+    print(f"flux in/out: unique {f_in:.6f} {f_out:.6f}; adaptive {g_in:.6f} {g_out:.6f}; exact {exact:.6f}")
+    assert abs(g_in - exact) <= 0.01 * exact
+
+
+@pytest.mark.parametrize("method", ["dirichlet", "neumann", "robin", "unique"])
+def test_equilibrium_linear_profile_fixed(method):
+    from paper_1401_1112_amd import BC_DIRICHLET, BC_NEUMANN, BC_ROBIN
+    from paper_1401_1112_amd.solver import solver_from_problem
+    p = config_equilibrium(tol=1e-13)
+    p.K_exp = 0.0
+    p.E = lambda level, ijk: 4.0 - 3.5 * (ijk[:, 0] + 0.5) / (1 << level)
+    s = solver_from_problem(p, abs_floor=1e-16)
+    masks = _leaf_masks(s, p)
+    e0 = _leaves(s, masks)
+    if method == "unique":
+        s.advance_unique(p.dt_coarse, p.tol)
+    else:
+        s.advance(p.dt_coarse, {"dirichlet": BC_DIRICHLET, "neumann": BC_NEUMANN, "robin": BC_ROBIN}[method], p.tol)
+    e1 = _leaves(s, masks)
+    s.close()
+    assert max(float(np.abs(e1[l] - e0[l]).max()) for l in e0) <= 1e-11
+
+
+def test_equilibrium_uniform_grids_near_second_order():
+    from paper_1401_1112_amd.solver import solver_from_problem
+    errs = []
+    for lv in (3, 4, 5, 6, 7):
+        p = config_equilibrium(base_level=lv, max_level=lv, tol=1e-10)
+        s = solver_from_problem(p)
+        masks = _leaf_masks(s, p)
+        _, leaves = _steady(s, p, masks)
+        s.close()
+        errs.append(_l2(leaves, masks))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    print(f"uniform 8..128: L2 {errs}, ratios {ratios}")
+    assert all(r > 2.8 for r in ratios), ratios
+    assert errs[-1] < 0.0025
+
+
+def test_power_law_rejected_for_patches():
+    # the batch form keeps its patch laws (constant, LP, Minerbo)
+    from paper_1401_1112_amd import E_INVALID, K_POWER
+    from paper_1401_1112_amd.solver import BatchSolver
+    from synth.configs import patch_batch
+    patches, alpha = patch_batch(7, 2)
+    bs = BatchSolver(robin_alpha=alpha)
+    h = bs.upload(patches, kmode=K_POWER)
+    st = bs.run(h, 1, 1e-10, raise_on_error=False)
+    bs.close()
+    assert st == E_INVALID

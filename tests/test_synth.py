@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from synth.configs import config_heat_gaussian, config_tiny, patch_sizes
-from synth.hierarchy import is_balanced, random_balanced_hierarchy
+from synth.hierarchy import cell_coords_of_octs, is_balanced, random_balanced_hierarchy
 
 
 def test_heat_config_shape():
@@ -71,3 +71,26 @@ def test_collapse_config_shape():
     centre = np.array([[n // 2, n // 2, n // 2]])
     assert rc == pytest.approx(np.sqrt(3) / 2)
     assert rho0(20, centre)[0] / rho0(20, np.array([[0, 0, 0]]))[0] == pytest.approx(1e4, rel=1e-4)
+
+
+def test_equilibrium_mesh_has_the_papers_cell_count():
+    # 8 coarse cells, four more levels, refined where the profile changes by more than
+    # 10 % over a cell or a neighbour: 3 + 5 + 5 + 5 + 10 = 28 cells along x, the count
+    # the paper gives for its most resolved adaptive runs (Sect. 4.2); plane-parallel, so
+    # every level covers whole y-z planes
+    from synth.configs import config_equilibrium
+    from synth.hierarchy import is_balanced
+    p = config_equilibrium()
+    h = p.hierarchy
+    assert is_balanced(h) and h.levels == [3, 4, 5, 6, 7]
+    leaves_along_x = 0
+    for l in h.levels:
+        c = cell_coords_of_octs(h.octs[l]).astype(np.int64)
+        per_x = np.bincount(c[:, 0], minlength=1 << l)
+        xs = np.nonzero(per_x)[0]
+        assert np.all(per_x[xs] == (1 << l) ** 2)  # whole planes
+        refined = set()
+        if l + 1 in h.octs:
+            refined = set(np.asarray(h.octs[l + 1])[:, 0].tolist())
+        leaves_along_x += len([x for x in xs if x not in refined])
+    assert leaves_along_x == 28
