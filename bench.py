@@ -33,7 +33,12 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per slot (FP64): pass A reads r, p_old, diag, 3 face
 # coefficients and the per-oct neighbour table (24 B per oct = 3 B per slot),
 # writes p_new and q; pass B reads x, r, p, q, diag and writes x, r.
+# pass A's algorithmic bytes per slot as the method states them: read r, p, d and the
+# three face coefficients, the neighbour table (24 B per oct), write p and q
 PASS_A_BYTES = 3 * 8 + 3 * 8 + 3 + 2 * 8
+# what it moves with the coefficients formed from K: K (8 B) and the face mask (1 B)
+# instead of the three coefficients
+PASS_A_BYTES_FORMED = 3 * 8 + 8 + 1 + 3 + 2 * 8
 PASS_B_BYTES = 5 * 8 + 2 * 8
 METRIC = "PCG cell-iterations/s + HBM GB/s vs peak; FP64 vs mixed+batched at 1e-10"
 
@@ -428,7 +433,8 @@ def _batched_form(args):
         torch.cuda.empty_cache()
         out["tuned_shape"] = {"best": best, "source": cached, "candidate_ms_per_step": times}
         forms.append(("fp64_tuned", {"persistent": bool(best["persistent"]), "graph": True,
-                                     "persistent_per_cu": best["persistent_per_cu"]}, 0))
+                                     "persistent_per_cu": best["persistent_per_cu"],
+                                     "form_coefs": bool(best.get("form_coefs", 0))}, 0))
     results = {}
     for name, kw, prec in forms:
         print(f"bench: batched form {name}", file=sys.stderr, flush=True)
@@ -510,6 +516,7 @@ def _collapse_form(args):
             rho, E, T = fields[l]
             s.set_fields(l, rho, E, T, kmode=1)
 
+    tuned = None
     if not args.no_tune:
         from paper_1401_1112_amd.autotune import tune_level_shapes
 
@@ -520,14 +527,21 @@ def _collapse_form(args):
         print("bench: tuning the collapse launch shape", file=sys.stderr, flush=True)
         best, times, cached = tune_level_shapes(first, tune_step, list(slots.values()), MIXED)
         out["tuned_shape_mixed"] = {"best": best, "source": cached, "candidate_ms_per_step": times}
+        tuned = best
         first.set_launch(args.max_blocks, True, 0)
 
     results = {}
-    for name, prec, pers in (("mixed_persistent", MIXED, True), ("mixed_polled", MIXED, False),
-                             ("fp64_polled", FP64, False)):
+    shapes = [("mixed_persistent", MIXED, True), ("mixed_polled", MIXED, False), ("fp64_polled", FP64, False)]
+    if tuned is not None:
+        shapes.append(("mixed_tuned", MIXED, tuned))
+    for name, prec, pers in shapes:
         print(f"bench: collapse form {name}", file=sys.stderr, flush=True)
         if first is not None:
             s, first = first, None
+        elif isinstance(pers, dict):  # the tuned shape
+            s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, nsub=p.nsub)
+            s.set_launch(pers["max_blocks"], bool(pers["persistent"]), pers["persistent_per_cu"],
+                         bool(pers.get("form_coefs", 0)))
         else:
             s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, persistent=pers,
                                 nsub=p.nsub, max_blocks=args.max_blocks)
@@ -573,7 +587,7 @@ def _collapse_form(args):
                                                  / torch.linalg.vector_norm(ref64[l][0])) for l in u.levels)}
         u.close()
     ref = results["fp64_polled"]
-    for name in ("mixed_persistent", "mixed_polled"):
+    for name in [n for n in ("mixed_persistent", "mixed_polled", "mixed_tuned") if n in results]:
         worst_e = max(float(torch.linalg.vector_norm(results[name][l][0] - ref[l][0])
                             / torch.linalg.vector_norm(ref[l][0])) for l in ref)
         worst_t = max(float(torch.linalg.vector_norm(results[name][l][1] - ref[l][1])
@@ -605,6 +619,8 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=16)
     ap.add_argument("--no-collapse", action="store_true",
                     help="skip the collapse-like form (levels 6..13, ~41 M cells; ~1 min of setup)")
+    ap.add_argument("--form-coefs", action="store_true",
+                    help="level solves form the face coefficients from K in every sweep instead of reading them")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (level solves: --max-blocks or the default)")
     args = ap.parse_args(argv)
@@ -621,7 +637,8 @@ def main(argv=None):
     t_gen = time.perf_counter()
     p = _problem()
     t_gen = time.perf_counter() - t_gen
-    s = solver_from_problem(p, time_sweeps=args.time_period, max_blocks=args.max_blocks)
+    s = solver_from_problem(p, time_sweeps=args.time_period, max_blocks=args.max_blocks,
+                            form_coefs=args.form_coefs)
     init = {lvl: (s._fields[lvl][0].clone(), s._fields[lvl][1].clone()) for lvl in s.levels}
     kmode = 1
 
@@ -640,8 +657,9 @@ def main(argv=None):
         from paper_1401_1112_amd.autotune import tune_levels
         best, times, cached = tune_levels(s, one_step, [s.info(l)[0] for l in s.levels], 0)
         args.max_blocks = best["max_blocks"]
-        launch = {"max_blocks": args.max_blocks, "tuned": True, "source": cached,
-                  "candidate_ms_per_step": times}
+        args.form_coefs = bool(best.get("form_coefs", 0))
+        launch = {"max_blocks": args.max_blocks, "form_coefs": int(args.form_coefs), "tuned": True,
+                  "source": cached, "candidate_ms_per_step": times}
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
@@ -665,7 +683,8 @@ def main(argv=None):
     roofline = None
     if a_ms > 0:
         achieved = a_bytes / (a_ms * 1e-3) / 1e9
-        traffic = _measured_traffic("k_pass_a<double>", args.max_blocks if args.max_blocks > 0 else 1024)
+        traffic = None if args.form_coefs else _measured_traffic("k_pass_a<double>",
+                                                                   args.max_blocks if args.max_blocks > 0 else 1024)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else round(traffic),
@@ -674,6 +693,9 @@ def main(argv=None):
                     "alg_bytes_per_launch": round(a_bytes / max(n_a, 1)),
                     "kernel": "k_pass_a (p update + 7-point operator + (p,q) partials)",
                     "bytes_per_slot": PASS_A_BYTES, "timed_launches": n_a,
+                    "coefficients": "formed from K in the sweep (bitwise the stored ones)" if args.form_coefs
+                                    else "stored (3 per slot)",
+                    "bytes_per_slot_moved": PASS_A_BYTES_FORMED if args.form_coefs else PASS_A_BYTES,
                     "timing": f"HIP start/stop events recorded by the launches themselves "
                               f"(hipExtLaunchKernelGGL) of the sweeps of every {args.time_period}th PCG iteration",
                     "avg_launch_us": round(a_ms * 1e3 / max(n_a, 1), 2),

@@ -94,6 +94,11 @@ typedef struct {
                             C = 2 K_f dt / dx^2 (the value dx / 2 from the centre), K_f the harmonic
                             mean of the cell's K and the law's K at the held value (no gradient
                             there); the flux-limited gradient also takes the held value dx / 2 away */
+  int form_coefs;        /* 1: the PCG sweeps form each face coefficient from the two cells'
+                            diffusivities with the assembly's expression (the same bits) instead of
+                            reading the three stored per cell (default 0): 15 fewer bytes per cell
+                            and sweep for six divisions more (level solves and the batch form; the
+                            unique time step always reads stored coefficients) */
 } amrfld_opts;
 
 typedef struct {
@@ -229,11 +234,13 @@ amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_
  * step of the method (the same sweeps, dealt differently to the GPU), used to
  * time candidate shapes on the device.  max_blocks: blocks per sweep (0 = 1024;
  * each block sweeps a contiguous range of at most 16 tiles of 256 slots);
- * persistent, persistent_per_cu: as in amrfld_opts.  Negative values are
- * rejected with AMRFLD_E_INVALID and change nothing.  Results of one shape are
- * bitwise reproducible; between shapes the block partials are summed in other
- * groupings, so they may differ in the last bits. */
-amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, int persistent_per_cu);
+ * persistent, persistent_per_cu, form_coefs: as in amrfld_opts.  Negative values
+ * are rejected with AMRFLD_E_INVALID and change nothing.  Results of one shape are
+ * bitwise reproducible, and form_coefs changes no FP64 bit; between block counts
+ * the block partials are summed in other groupings, so they may differ in the
+ * last bits. */
+amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, int persistent_per_cu,
+                                int form_coefs);
 
 /* Message of the last failure on this context ("" if none). */
 const char* amrfld_last_error(const amrfld_ctx* c);

@@ -34,6 +34,7 @@ class amrfld_opts(ctypes.Structure):
         ("persistent", ctypes.c_int), ("graph", ctypes.c_int), ("stream", ctypes.c_void_p),
         ("persistent_per_cu", ctypes.c_int), ("theta", ctypes.c_double),
         ("K_exp", ctypes.c_double), ("outer_mode", ctypes.c_int * 6), ("outer_value", ctypes.c_double * 6),
+        ("form_coefs", ctypes.c_int),
     ]
 
 
@@ -82,7 +83,7 @@ SIGNATURES = [
     ("amrfld_solve_batch", _I, [_P, _I, ctypes.POINTER(amrfld_patch), _I, _D, _I, _P]),
     ("amrfld_get_E", _I, [_P, _I, _P, _P]),
     ("amrfld_last_stats", _I, [_P, ctypes.POINTER(amrfld_stats), _I, ctypes.POINTER(_I)]),
-    ("amrfld_set_launch", _I, [_P, _I, _I, _I]),
+    ("amrfld_set_launch", _I, [_P, _I, _I, _I, _I]),
     ("amrfld_last_error", ctypes.c_char_p, [_P]),
     ("amrfld_create_error", ctypes.c_char_p, []),
 ]
@@ -198,8 +199,8 @@ def amrfld_last_stats(ctx, max_n=None):
     return [arr[k].as_dict() for k in range(count)]
 
 
-def amrfld_set_launch(ctx, max_blocks, persistent, persistent_per_cu):
-    return load().amrfld_set_launch(ctx, int(max_blocks), int(persistent), int(persistent_per_cu))
+def amrfld_set_launch(ctx, max_blocks, persistent, persistent_per_cu, form_coefs):
+    return load().amrfld_set_launch(ctx, int(max_blocks), int(persistent), int(persistent_per_cu), int(form_coefs))
 
 
 def amrfld_last_error(ctx):

@@ -5,15 +5,17 @@ few runs after a warm-up run) and the fastest is kept in a JSON cache keyed by t
 device and a signature of the workload; a later call with the same key applies the
 cached choice without timing.  A shape only changes how the sweeps are dealt to the
 GPU (blocks per sweep, i.e. 256-slot tiles per block; host-polled sweeps or one
-persistent launch and its resident blocks per compute unit): results of one shape are
-bitwise reproducible, and between shapes they differ at most in the last bits, since
-the block partials are summed in other groupings.
+persistent launch and its resident blocks per compute unit) and whether the sweeps
+read stored face coefficients or form them from K (fewer bytes, more arithmetic:
+faster where the levels stream from HBM, slower where they sit in the Infinity
+Cache): results of one shape are bitwise reproducible, and between shapes they differ
+at most in the last bits, since the block partials are summed in other groupings.
 
 The cache lives at ``$AMRFLD_TUNE_CACHE`` or ``~/.cache/amrfld/tune.json``.  Below it
 sits a table shipped with the package (``tuned_gfx950.json``): shapes measured on MI355X
 for the benchmark workloads, keyed by workload and applied on devices of that
 architecture, so that those workloads run a fixed, profiled shape; a workload in
-neither is timed.
+neither is timed (``AMRFLD_TUNE_SHIPPED=0`` skips the table).
 """
 from __future__ import annotations
 
@@ -26,18 +28,23 @@ import tempfile
 import torch
 
 LEVEL_BLOCKS = (256, 512, 1024, 2048, 4096)
+LEVEL_CANDIDATES = tuple({"max_blocks": b, "form_coefs": f} for b in LEVEL_BLOCKS for f in (0, 1))
 LEVEL_SHAPES = (
-    {"max_blocks": 512, "persistent": 0, "persistent_per_cu": 0},
-    {"max_blocks": 1024, "persistent": 0, "persistent_per_cu": 0},
-    {"max_blocks": 2048, "persistent": 0, "persistent_per_cu": 0},
-    {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 0},
-    {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 1},
+    {"max_blocks": 512, "persistent": 0, "persistent_per_cu": 0, "form_coefs": 0},
+    {"max_blocks": 1024, "persistent": 0, "persistent_per_cu": 0, "form_coefs": 0},
+    {"max_blocks": 2048, "persistent": 0, "persistent_per_cu": 0, "form_coefs": 0},
+    {"max_blocks": 512, "persistent": 0, "persistent_per_cu": 0, "form_coefs": 1},
+    {"max_blocks": 1024, "persistent": 0, "persistent_per_cu": 0, "form_coefs": 1},
+    {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 0, "form_coefs": 0},
+    {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 1, "form_coefs": 0},
 )
 BATCH_SHAPES = (
-    {"persistent": 0, "persistent_per_cu": 0},
-    {"persistent": 1, "persistent_per_cu": 0},
-    {"persistent": 1, "persistent_per_cu": 2},
-    {"persistent": 1, "persistent_per_cu": 1},
+    {"persistent": 0, "persistent_per_cu": 0, "form_coefs": 0},
+    {"persistent": 0, "persistent_per_cu": 0, "form_coefs": 1},
+    {"persistent": 1, "persistent_per_cu": 0, "form_coefs": 0},
+    {"persistent": 1, "persistent_per_cu": 0, "form_coefs": 1},
+    {"persistent": 1, "persistent_per_cu": 2, "form_coefs": 0},
+    {"persistent": 1, "persistent_per_cu": 1, "form_coefs": 0},
 )
 
 
@@ -60,7 +67,10 @@ SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950
 
 
 def _shipped(key: str, arch: str = None):
-    """Entry of the shipped table for a workload key, if it applies to this device."""
+    """Entry of the shipped table for a workload key, if it applies to this device
+    (``AMRFLD_TUNE_SHIPPED=0`` ignores the table, so that its workloads are timed)."""
+    if os.environ.get("AMRFLD_TUNE_SHIPPED") == "0":
+        return None
     try:
         with open(SHIPPED) as f:
             d = json.load(f)
@@ -139,18 +149,20 @@ def tune(key, candidates, apply, run, repeats=3, stream=None, use_cache=True, ti
 
 
 def tune_levels(solver, run, sizes, precision, repeats=3, use_cache=True):
-    """Blocks per sweep of a hierarchy's level solves; `run` advances one step from the
-    same state every time (the caller resets the fields inside it)."""
-    return tune(workload_key("levels", sizes, precision), [{"max_blocks": b} for b in LEVEL_BLOCKS],
-                lambda c: solver.set_launch(max_blocks=c["max_blocks"]), run, repeats, solver.stream,
-                use_cache)
+    """Blocks per sweep and coefficient form of a hierarchy's level solves; `run`
+    advances one step from the same state every time (the caller resets the fields
+    inside it)."""
+    return tune(workload_key("levels", sizes, precision), list(LEVEL_CANDIDATES),
+                lambda c: solver.set_launch(max_blocks=c["max_blocks"], form_coefs=c.get("form_coefs", 0)), run,
+                repeats, solver.stream, use_cache)
 
 
 def tune_batch(solver, run, sizes, precision, repeats=2, use_cache=True):
     """Host-polled sweeps or a persistent launch (and its resident blocks per compute unit)
     for a batch of patches of the given sizes."""
     return tune(workload_key("batch", sizes, precision), list(BATCH_SHAPES),
-                lambda c: solver.set_launch(0, c["persistent"], c["persistent_per_cu"]), run, repeats,
+                lambda c: solver.set_launch(0, c["persistent"], c["persistent_per_cu"], c.get("form_coefs", 0)),
+                run, repeats,
                 solver.stream, use_cache)
 
 
@@ -158,5 +170,6 @@ def tune_level_shapes(solver, run, sizes, precision, repeats=2, use_cache=True):
     """Blocks per sweep and host-polled or persistent launches of a hierarchy's level
     solves; `run` advances one step from the same state every time."""
     return tune(workload_key("level-shapes", sizes, precision), list(LEVEL_SHAPES),
-                lambda c: solver.set_launch(c["max_blocks"], c["persistent"], c["persistent_per_cu"]), run,
+                lambda c: solver.set_launch(c["max_blocks"], c["persistent"], c["persistent_per_cu"],
+                                            c.get("form_coefs", 0)), run,
                 repeats, solver.stream, use_cache)

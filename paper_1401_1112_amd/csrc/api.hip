@@ -50,6 +50,7 @@ struct LevelState {
   bool child_dirty = true;
   double *rho = nullptr, *E = nullptr, *T = nullptr, *K = nullptr;
   double *Cp = nullptr, *diag = nullptr, *b = nullptr, *reg = nullptr;
+  uint8_t* mask = nullptr;  // per slot: faces that couple two leaves of the level
   bool has_fields = false, has_T = false;
   int kmode = 1;
   double K_const = 1.0, kappa_R = 1.0, kappa_P = 1.0, c_light = 1.0, K_exp = 0.0;
@@ -70,10 +71,11 @@ struct LevelState {
   }
   void release() {
     for (void* p : {(void*)nbr, (void*)cnb, (void*)parent, (void*)child, (void*)rho, (void*)E,
-                    (void*)T, (void*)K, (void*)Cp, (void*)diag, (void*)b, (void*)reg})
+                    (void*)T, (void*)K, (void*)Cp, (void*)diag, (void*)b, (void*)reg, (void*)mask})
       dfree(p);
     nbr = cnb = parent = child = nullptr;
     rho = E = T = K = Cp = diag = b = reg = nullptr;
+    mask = nullptr;
   }
 };
 
@@ -92,17 +94,19 @@ struct BatchState {
   int32_t *blk_prob = nullptr, *blk0 = nullptr, *tile0 = nullptr;
   int64_t* d_out_off = nullptr;
   double *E = nullptr, *rho = nullptr, *K = nullptr, *Cp = nullptr, *diag = nullptr, *b = nullptr;
+  uint8_t* mask = nullptr;
   PatchParams* pp = nullptr;
   const double** src = nullptr;  // device array of n_prob pointers
 
   void release() {
     for (void* p : {(void*)nbr, (void*)cnb, (void*)child, (void*)oct_prob, (void*)idx, (void*)blk_prob,
                     (void*)blk0, (void*)tile0, (void*)d_out_off, (void*)E, (void*)rho, (void*)K, (void*)Cp,
-                    (void*)diag, (void*)b, (void*)pp, (void*)src})
+                    (void*)diag, (void*)b, (void*)pp, (void*)src, (void*)mask})
       if (p) (void)hipFree(p);
     nbr = cnb = child = oct_prob = idx = blk_prob = blk0 = tile0 = nullptr;
     d_out_off = nullptr;
     E = rho = K = Cp = diag = b = nullptr;
+    mask = nullptr;
     pp = nullptr;
     src = nullptr;
   }
@@ -144,8 +148,8 @@ struct amrfld_ctx {
   int64_t partial_n = 0;
   // mixed-precision workspace
   int64_t ws32_n = 0;
-  float *Cp32 = nullptr, *diag32 = nullptr, *r32 = nullptr, *d32 = nullptr, *p32[2] = {nullptr, nullptr},
-        *q32 = nullptr;
+  float *Cp32 = nullptr, *K32 = nullptr, *diag32 = nullptr, *r32 = nullptr, *d32 = nullptr,
+        *p32[2] = {nullptr, nullptr}, *q32 = nullptr;
   double* x_alt = nullptr;
   PcgScalars* sc = nullptr;     // [2 sc_cap]: outer (or plain) solves, then inner solves
   PcgScalars* h_sc = nullptr;   // pinned mirror
@@ -215,13 +219,14 @@ void ensure_workspace(amrfld_ctx* c, int64_t n) {
 
 void ensure_workspace32(amrfld_ctx* c, int64_t n) {
   if (n <= c->ws32_n) return;
-  for (void* p : {(void*)c->Cp32, (void*)c->diag32, (void*)c->r32, (void*)c->d32, (void*)c->p32[0],
-                  (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
+  for (void* p : {(void*)c->Cp32, (void*)c->K32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
+                  (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
     dfree(p);
-  c->Cp32 = c->diag32 = c->r32 = c->d32 = c->p32[0] = c->p32[1] = c->q32 = nullptr;
+  c->Cp32 = c->K32 = c->diag32 = c->r32 = c->d32 = c->p32[0] = c->p32[1] = c->q32 = nullptr;
   c->x_alt = nullptr;
   c->ws32_n = 0;
   c->Cp32 = dalloc<float>(3 * n, "workspace fp32");
+  c->K32 = dalloc<float>(n, "workspace fp32");
   c->diag32 = dalloc<float>(n, "workspace fp32");
   c->r32 = dalloc<float>(n, "workspace fp32");
   c->d32 = dalloc<float>(n, "workspace fp32");
@@ -260,6 +265,29 @@ CellKParams kparams(const LevelState& L) {
   k.c_light = L.c_light;
   k.K_exp = L.K_exp;
   return k;
+}
+
+// The operator's face coefficients as the sweeps read them: stored, or formed
+// from K and the face mask (scale = dt / dx^2, or per problem from the batch table).
+FaceCoefs<double> face_coefs(const amrfld_ctx* c, const double* Cp, const double* K, const uint8_t* mask,
+                             double scale, double theta, bool per_problem) {
+  FaceCoefs<double> A;
+  if (!c->o.form_coefs) {
+    A.Cp = Cp;
+    return A;
+  }
+  A.K = K;
+  A.mask = mask;
+  A.scale = scale;
+  A.theta = theta;
+  A.per_problem = per_problem;
+  return A;
+}
+
+FaceCoefs<double> stored_face_coefs(const double* Cp) {
+  FaceCoefs<double> A;
+  A.Cp = Cp;
+  return A;
 }
 
 OuterBC outer_bc(const amrfld_ctx* c) {
@@ -353,7 +381,7 @@ bool all_done(const PcgScalars* h, int n) {
 // after each batch, the next batch size predicted from the slowest problem's
 // observed convergence rate.  Launches after a problem converged return at once.
 template <typename T>
-void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const T* Cp, const T* diag, T* x, T* r,
+void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag, T* x, T* r,
                     T* const* p, T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
@@ -366,7 +394,7 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
     const int blocks = persistent_blocks<T>(Pp, per_cu);
     if (blocks > 0) {
       launch_zero_u32(s, c->bar, kBarWords);
-      const hipError_t e = launch_pcg_persistent<T>(s, D, Pp, max_iter, Cp, diag, x, r, p, q, sc_dev, c->partials,
+      const hipError_t e = launch_pcg_persistent<T>(s, D, Pp, max_iter, A, diag, x, r, p, q, sc_dev, c->partials,
                                                     c->bar, per_cu);
       if (e == hipSuccess) {
         read_scalars(c, sc_host, sc_dev, np);
@@ -401,7 +429,7 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
       const T* po = p[(it & 1) ^ 1];
       // every period-th iteration: each sweep's launch records its own start and end
       hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[4 * (it / period - 1)] : nullptr;
-      launch_pass_a<T>(s, D, P, it, Cp, diag, r, po, pn, q, sc_dev, c->partials, e ? e[0] : nullptr,
+      launch_pass_a<T>(s, D, P, it, A, diag, r, po, pn, q, sc_dev, c->partials, e ? e[0] : nullptr,
                        e ? e[1] : nullptr);
       if constexpr (std::is_same<T, double>::value) {
         if (D.n_if_rows > 0) launch_interface(s, D, pn, q, sc_dev, D.if_part);
@@ -459,7 +487,7 @@ PcgScalars make_scalars(double tol, double abs_floor, int max_iter, int linf_tes
 
 // Operator arrays of one solve (a level or a whole batch), slot order.
 struct SolveArrays {
-  const double* Cp;
+  FaceCoefs<double> A;
   const double* diag;
   const double* b;
   double* x;  // x_0 on entry (the energy, updated in place)
@@ -472,10 +500,10 @@ void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveA
   const int np = P.n_prob;
   for (int q = 0; q < np; ++q) c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
   write_scalars(c, c->sc, c->h_sc, np);
-  launch_pcg_init<double>(s, D, P, A.Cp, A.diag, A.b, A.x, c->r, c->p[0], c->partials);
+  launch_pcg_init<double>(s, D, P, A.A, A.diag, A.b, A.x, c->r, c->p[0], c->partials);
   launch_init_finish(s, P, c->partials, c->sc);
   check(hipEventRecord(c->ev[1], s), "event");
-  pcg_iterations<double>(c, D, P, A.Cp, A.diag, A.x, c->r, c->p, c->q, c->sc, c->h_sc, c->o.max_iter, ls);
+  pcg_iterations<double>(c, D, P, A.A, A.diag, A.x, c->r, c->p, c->q, c->sc, c->h_sc, c->o.max_iter, ls);
 }
 
 // FP32 inner PCG on A d = r inside an FP64 iterative-refinement loop: the FP64
@@ -487,7 +515,17 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
   ensure_workspace32(c, A.n);
-  launch_to_f32(s, A.n, A.Cp, A.diag, c->Cp32, c->diag32);
+  launch_to_f32(s, A.n, A.A.Cp, A.A.K, A.diag, c->Cp32, c->K32, c->diag32);
+  FaceCoefs<float> A32;
+  if (A.A.Cp) {
+    A32.Cp = c->Cp32;
+  } else {
+    A32.K = c->K32;
+    A32.mask = A.A.mask;
+    A32.scale = A.A.scale;
+    A32.theta = A.A.theta;
+    A32.per_problem = A.A.per_problem;
+  }
   for (int q = 0; q < np; ++q) {
     c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
     c->h_sc[np + q] = make_scalars(c->o.inner_tol, 0.0, c->o.max_iter, 0);
@@ -501,7 +539,7 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
   const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
   int budget = c->o.max_iter;
   for (int outer = 0; outer <= max_outer; ++outer) {
-    launch_ir_sweep(s, D, P, A.Cp, A.diag, A.b, x_cur, outer == 0 ? nullptr : c->d32, x_nxt, c->r32, out,
+    launch_ir_sweep(s, D, P, A.A, A.diag, A.b, x_cur, outer == 0 ? nullptr : c->d32, x_nxt, c->r32, out,
                     c->partials);
     std::swap(x_cur, x_nxt);
     launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, std::max(1, budget), out, in, c->partials);
@@ -511,7 +549,7 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
     launch_init_finish(s, P, c->partials, in);
     int before = 0;
     for (int v : ls->iters) before = std::max(before, v);
-    pcg_iterations<float>(c, D, P, c->Cp32, c->diag32, c->d32, c->r32, c->p32, c->q32, in, c->h_sc + np,
+    pcg_iterations<float>(c, D, P, A32, c->diag32, c->d32, c->r32, c->p32, c->q32, in, c->h_sc + np,
                           std::max(1, budget), ls);
     int after = 0;
     for (int v : ls->iters) after = std::max(after, v);
@@ -541,8 +579,12 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   const double w = mode == AMRFLD_BC_DIRICHLET ? 1.0 : mode == AMRFLD_BC_NEUMANN ? 0.0 : c->o.robin_alpha;
   const CouplingParams cp = cparams(c, L);
   launch_assemble(s, D, L.K, Lc ? Lc->K : nullptr, L.E, Lc ? Lc->E : nullptr, L.rho, L.reg, dt, w,
-                  c->o.robin_alpha, cp, kparams(L), outer_bc(c), L.Cp, L.diag, L.b);
-  if (c->o.theta != 1.0) launch_theta_step(s, D, c->o.theta, L.E, L.Cp, L.diag, L.b);
+                  c->o.robin_alpha, cp, kparams(L), outer_bc(c), L.Cp, L.mask, L.diag, L.b);
+  const double scale = dt / (D.dx * D.dx);
+  if (c->o.theta != 1.0)
+    launch_theta_step(s, D, c->o.theta, L.E, face_coefs(c, L.Cp, L.K, L.mask, scale, 1.0, false), L.Cp, L.diag,
+                      L.b);
+  const FaceCoefs<double> Aop = face_coefs(c, L.Cp, L.K, L.mask, scale, c->o.theta, false);
 
   const int n_tiles = tiles_of(D.n_slots);
   const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
@@ -550,7 +592,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   LoopStats ls;
   ls.iters.assign(1, 0);
   std::vector<int> outer_iters(1, 0);
-  const SolveArrays A{L.Cp, L.diag, L.b, L.E, D.n_slots};
+  const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots};
   if (c->o.precision == AMRFLD_MIXED) {
     pcg_mixed(c, D, P, A, tol, &ls, &outer_iters);
   } else {
@@ -558,7 +600,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   }
   check(hipEventRecord(c->ev[2], s), "event");
   if (c->o.true_residual && c->o.precision != AMRFLD_MIXED)
-    launch_true_residual(s, D, P, L.Cp, L.diag, L.b, L.E, c->sc, c->partials);
+    launch_true_residual(s, D, P, Aop, L.diag, L.b, L.E, c->sc, c->partials);
   launch_post_solve(s, D, P, L.E, L.rho, cp, dt, L.T, c->sc, c->partials);
   if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN)) {
     double* reg = ensure_reg(c, *Lc);
@@ -836,9 +878,9 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   }
   LoopStats ls;
   ls.iters.assign(1, 0);
-  pcg_fp64(c, D, P, SolveArrays{C.Cp, C.diag, C.b, C.x, C.n_slots}, tol, &ls);
+  pcg_fp64(c, D, P, SolveArrays{stored_face_coefs(C.Cp), C.diag, C.b, C.x, C.n_slots}, tol, &ls);
   check(hipEventRecord(c->ev[2], s), "event");
-  if (c->o.true_residual) launch_true_residual(s, D, P, C.Cp, C.diag, C.b, C.x, c->sc, c->partials);
+  if (c->o.true_residual) launch_true_residual(s, D, P, stored_face_coefs(C.Cp), C.diag, C.b, C.x, c->sc, c->partials);
   int64_t n_leaf = 0;
   for (int k = 0; k < C.n_levels; ++k) {
     LevelState& L = c->L(base + k);
@@ -994,6 +1036,7 @@ void build_batch(amrfld_ctx* c, const std::vector<int>& sizes) {
   B->rho = dalloc<double>(B->n_slots, "batch fields");
   B->K = dalloc<double>(B->n_slots, "batch fields");
   B->Cp = dalloc<double>(3 * B->n_slots, "batch fields");
+  B->mask = dalloc<uint8_t>(B->n_slots, "batch fields");
   B->diag = dalloc<double>(B->n_slots, "batch fields");
   B->b = dalloc<double>(B->n_slots, "batch fields");
   B->pp = dalloc<PatchParams>(B->n_prob, "batch params");
@@ -1018,21 +1061,22 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
   CouplingParams cp{};
   cp.T = nullptr;
   const CellKParams kp{1, 1.0, 1.0, 1.0};
+  const FaceCoefs<double> Aop = face_coefs(c, B.Cp, B.K, B.mask, 1.0, 1.0, true);
   auto record = [&](hipStream_t st) -> hipError_t {
     launch_zero_u32(st, c->bar, kBarWords);
     for (int step = 0; step < n_steps; ++step) {
       PcgScalars* sc = c->sc + int64_t(step) * np;
       launch_cell_K(st, D, B.E, B.rho, nullptr, kp, OuterBC{}, B.K);
       launch_assemble(st, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, kp,
-                      OuterBC{}, B.Cp, B.diag, B.b);
+                      OuterBC{}, B.Cp, B.mask, B.diag, B.b);
       launch_init_scalars(st, sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
       launch_zero_u32(st, c->bar, kBarAbort);
-      launch_pcg_init<double>(st, D, P, B.Cp, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
+      launch_pcg_init<double>(st, D, P, Aop, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
       launch_init_finish(st, P, c->partials, sc);
-      const hipError_t e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, B.Cp, B.diag, B.E, c->r, c->p,
+      const hipError_t e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, Aop, B.diag, B.E, c->r, c->p,
                                                          c->q, sc, c->partials, c->bar, per_cu);
       if (e != hipSuccess) return e;
-      if (c->o.true_residual) launch_true_residual(st, D, P, B.Cp, B.diag, B.b, B.E, sc, c->partials);
+      if (c->o.true_residual) launch_true_residual(st, D, P, Aop, B.diag, B.b, B.E, sc, c->partials);
       launch_post_solve(st, D, P, B.E, B.rho, cp, 0.0, nullptr, sc, c->partials);
     }
     return hipGetLastError();
@@ -1168,11 +1212,12 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     CouplingParams cp{};
     cp.T = nullptr;
     launch_assemble(s, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, kp,
-                    OuterBC{}, B.Cp, B.diag, B.b);
+                    OuterBC{}, B.Cp, B.mask, B.diag, B.b);
     LoopStats ls;
     ls.iters.assign(np, 0);
     std::vector<int> outer_iters(np, 0);
-    const SolveArrays A{B.Cp, B.diag, B.b, B.E, B.n_slots};
+    const FaceCoefs<double> Aop = face_coefs(c, B.Cp, B.K, B.mask, 1.0, 1.0, true);
+    const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots};
     if (precision == AMRFLD_MIXED) {
       pcg_mixed(c, D, P, A, tol, &ls, &outer_iters);
     } else {
@@ -1180,7 +1225,7 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     }
     check(hipEventRecord(c->ev[2], s), "event");
     if (c->o.true_residual && precision != AMRFLD_MIXED)
-      launch_true_residual(s, D, P, B.Cp, B.diag, B.b, B.E, c->sc, c->partials);
+      launch_true_residual(s, D, P, Aop, B.diag, B.b, B.E, c->sc, c->partials);
     launch_post_solve(s, D, P, B.E, B.rho, cp, 0.0, nullptr, c->sc, c->partials);
     check(hipEventRecord(c->ev[3], s), "event");
     read_scalars(c, c->h_sc, c->sc, np);
@@ -1323,7 +1368,7 @@ void amrfld_destroy(amrfld_ctx* c) {
   for (auto& e : c->cap_ev)
     if (e) (void)hipEventDestroy(e);
   for (void* p : {(void*)c->r, (void*)c->p[0], (void*)c->p[1], (void*)c->q, (void*)c->partials,
-                  (void*)c->sc, (void*)c->Cp32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
+                  (void*)c->sc, (void*)c->Cp32, (void*)c->K32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
                   (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
     dfree(p);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -1368,6 +1413,7 @@ amrfld_status amrfld_build_level(amrfld_ctx* c, int level, int64_t n_oct, const 
     L.E = dalloc<double>(n, "fields");
     L.K = dalloc<double>(n, "fields");
     L.Cp = dalloc<double>(3 * n, "fields");
+    L.mask = dalloc<uint8_t>(n, "fields");
     L.diag = dalloc<double>(n, "fields");
     L.b = dalloc<double>(n, "fields");
     L.has_fields = false;
@@ -1534,15 +1580,17 @@ amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_
   return AMRFLD_OK;
 }
 
-amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, int persistent_per_cu) {
+amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, int persistent_per_cu,
+                                int form_coefs) {
   if (!c) return AMRFLD_E_INVALID;
-  if (max_blocks < 0 || persistent < 0 || persistent_per_cu < 0) {
+  if (max_blocks < 0 || persistent < 0 || persistent_per_cu < 0 || form_coefs < 0) {
     c->err = "set_launch: negative launch parameter";
     return AMRFLD_E_INVALID;
   }
   c->o.max_blocks = max_blocks;
   c->o.persistent = persistent ? 1 : 0;
   c->o.persistent_per_cu = persistent_per_cu;
+  c->o.form_coefs = form_coefs ? 1 : 0;
   c->err.clear();
   return AMRFLD_OK;
 }

@@ -30,9 +30,25 @@ __device__ __forceinline__ int same_level_nb(const int32_t* __restrict__ nbr, in
   return n < 0 ? -1 : ((n << 3) | (pos ^ bit));
 }
 
-__device__ __forceinline__ double harmonic(double a, double b) {
-  const double s = a + b;
-  return s != 0.0 ? (2.0 * a * b) / s : 0.0;
+template <typename T>
+__device__ __forceinline__ T harmonic(T a, T b) {
+  const T s = a + b;
+  return s != T(0) ? (T(2) * a * b) / s : T(0);
+}
+
+// Coefficient of a face formed from the diffusivities of its two cells (the
+// assembly's expression; harmonic is symmetric bit for bit).
+template <typename T>
+__device__ __forceinline__ T face_coef(T Ki, T Kj, T scale, T theta) {
+  T c = harmonic(Ki, Kj) * scale;
+  if (theta != T(1)) c *= theta;
+  return c;
+}
+
+// dt / dx^2 of problem `prob` of a solve.
+template <typename T>
+__device__ __forceinline__ T coef_scale(const FaceCoefs<T>& A, const DevLevel& L, int prob) {
+  return T(A.per_problem ? L.pp[prob].coef : A.scale);
 }
 
 // Block-wide reduction; the result is valid in thread 0.
@@ -239,6 +255,35 @@ __device__ __forceinline__ T apply_stencil(int ii, const int32_t* __restrict__ n
     if (nb >= 0) {
       const int j = (nb << 3) | (pos ^ bit);
       const T c_out = my ? c_own : Ca[j];
+      if (c_out != T(0)) acc -= c_out * get(j);
+    }
+  }
+  return acc;
+}
+
+// The same operator with stored or formed face coefficients; `scale` is the
+// problem's coef_scale.
+template <typename T, class Get>
+__device__ __forceinline__ T apply_stencil(int ii, const int32_t* __restrict__ nbr, const FaceCoefs<T>& A,
+                                           T scale, int n, T di, T pi, Get get) {
+  if (A.Cp) return apply_stencil<T>(ii, nbr, A.Cp, n, di, pi, get);
+  const int pos = ii & 7, o = ii >> 3;
+  const T Ki = A.K[ii];
+  const unsigned m = A.mask[ii];
+  const T th = T(A.theta);
+  T acc = di * pi;
+#pragma unroll
+  for (int axis = 0; axis < 3; ++axis) {
+    const int bit = 1 << axis;
+    const T K_sib = __shfl_xor(Ki, bit, 64);
+    const T p_sib = __shfl_xor(pi, bit, 64);
+    const int my = (pos >> axis) & 1;
+    const T c_in = ((m >> (2 * axis + 1 - my)) & 1u) ? face_coef(Ki, K_sib, scale, th) : T(0);
+    acc -= c_in * p_sib;
+    const int nb = nbr[o * 6 + 2 * axis + my];
+    if (nb >= 0 && ((m >> (2 * axis + my)) & 1u)) {
+      const int j = (nb << 3) | (pos ^ bit);
+      const T c_out = face_coef(Ki, A.K[j], scale, th);
       if (c_out != T(0)) acc -= c_out * get(j);
     }
   }

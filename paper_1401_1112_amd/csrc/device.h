@@ -125,6 +125,24 @@ struct OuterBC {
   double val[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 };
 
+// Face coefficients of the operator of a solve, stored or formed in every sweep.
+// Stored (Cp set): Cp[a][i] is the coefficient of the +a face of slot i, zero
+// unless both sides are leaves of the level.  Formed (K set): the face of slot i
+// in direction d couples it to its neighbour j when bit d of mask[i] is set, with
+// coefficient harmonic(K_i, K_j) * scale, times theta when theta != 1: the very
+// expression of the assembly, so both forms give the same bits while the sweeps
+// read one diffusivity per slot instead of three coefficients.  scale = dt / dx^2
+// of the level, or per problem from the batch table (per_problem).
+template <typename T>
+struct FaceCoefs {
+  const T* Cp = nullptr;
+  const T* K = nullptr;
+  const uint8_t* mask = nullptr;
+  double scale = 1.0;
+  double theta = 1.0;
+  bool per_problem = false;
+};
+
 struct CouplingParams {
   const double* T;  // nullptr: no coupling
   double kappa_P, c_light, a_rad, c_v;
@@ -139,14 +157,15 @@ void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const doub
 // w: weight of the coarse-to-fine Dirichlet part (1 D, 0 N, alpha R); alpha: Robin
 // weight of batch patch faces whose mode is Robin; kp and ob: the diffusivity law and
 // the box faces' Dirichlet values (no patch table).
+// mask: bit d of slot i set when its face in direction d couples two leaves.
 void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const double* K_coarse,
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
                      double dt, double w, double alpha, const CouplingParams& cp, const CellKParams& kp,
-                     const OuterBC& ob, double* Cp, double* diag, double* b);
+                     const OuterBC& ob, double* Cp, uint8_t* mask, double* diag, double* b);
 // Theta-weighted step (Crank-Nicolson at 1/2) from an assembled backward-Euler
 // level system: b -= (1 - theta) (A E - E) on the leaves, then A = I + theta (A - I).
-void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E, double* Cp, double* diag,
-                       double* b);
+void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E,
+                       const FaceCoefs<double>& A1, double* Cp, double* diag, double* b);
 // Composite system of all levels advanced with one dt (unique time step): per slot
 // the volume-scaled same-level coefficients Cp, interface coefficients cif, the
 // refined-neighbour mask c2f, diagonal and right-hand side; E is the concatenated
@@ -160,8 +179,9 @@ void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, c
 void launch_restrict(hipStream_t s, const DevLevel& F, const double* E_f, double* E_c);
 void launch_fill(hipStream_t s, double* p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float* p, int64_t n, float v);
-void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* diag, float* Cp32,
-                   float* diag32);
+// FP32 copies of an FP64 operator: Cp (stored form) or K (formed), and diag.
+void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* K, const double* diag, float* Cp32,
+                   float* K32, float* diag32);
 
 // -------------------------------------------------------------- PCG sweeps
 // G = number of blocks of every sweep of a solve (<= tiles); partials hold
@@ -171,13 +191,13 @@ int sweep_blocks(int n_tiles, int max_blocks);
 // Every launcher below covers all problems of the plan; sc points at n_prob
 // scalar records.
 template <typename T>
-void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const T* Cp, const T* diag,
+void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag,
                      const T* b, const T* x, T* r, T* p_clear, double* part);
 void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, PcgScalars* sc);
 // t0 / t1 (optional): events that the launch itself records when the kernel
 // starts and ends, so that they time the kernel alone.
 template <typename T>
-void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* Cp,
+void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const FaceCoefs<T>& A,
                    const T* diag, const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc,
                    double* part, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 template <typename T>
@@ -204,12 +224,12 @@ template <typename T>
 int persistent_blocks(const SweepPlan& P, int per_cu_cap);
 template <typename T>
 hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter,
-                                 const T* Cp, const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc,
+                                 const FaceCoefs<T>& A, const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc,
                                  double* part, unsigned* bar, int per_cu_cap);
 void launch_zero_u32(hipStream_t s, unsigned* p, int n);
 void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, double abs_floor, int max_iter,
                          int linf_test);
-void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp,
+void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,
                           const double* diag, const double* b, const double* x, PcgScalars* sc,
                           double* part);
 void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* E,
@@ -220,7 +240,7 @@ void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, con
 // Outer sweep: x_new = x_old + d (d in FP32, may be null), r = b - A x_new in
 // FP64, r32 = (float) r; partials ||r||^2, ||b||^2, max |d| / |x_old|; then the
 // finisher applies the outer stopping test and prepares the inner scalars.
-void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp,
+void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,
                      const double* diag, const double* b, const double* x_old, const float* d,
                      double* x_new, float* r32, const PcgScalars* outer, double* part);
 void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int inner_max,

@@ -109,20 +109,21 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], const bool (&mx)
 
 // r0 = b - A x0, p = 0; partials (r, r / d), ||r||^2, ||b||^2.
 template <typename T>
-__device__ __forceinline__ void body_pcg_init(int vb, DevLevel L, SweepPlan P, const T* __restrict__ Cp,
+__device__ __forceinline__ void body_pcg_init(int vb, DevLevel L, SweepPlan P, const FaceCoefs<T>& A,
                                                      const T* __restrict__ diag, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ p_clear, double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
   const BlockPlan bp = block_plan(P, vb);
+  const T scale = dev::coef_scale(A, L, bp.prob);
   double v[3] = {0.0, 0.0, 0.0};
   for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
     const T di = diag[ii];
-    T ax = apply_stencil<T>(ii, L.nbr, Cp, n, di, x[ii], [&](int j) { return x[j]; });
+    T ax = apply_stencil<T>(ii, L.nbr, A, scale, n, di, x[ii], [&](int j) { return x[j]; });
     if (L.cif) ax -= dev::interface_terms<T>(ii, L, n, [&](int j) { return x[j]; });
     if (valid) {
       const T ri = b[i] - ax;
@@ -170,6 +171,89 @@ __device__ __forceinline__ void body_init_finish(int prob, SweepPlan P, const do
   }
 }
 
+// Phase 2 of the operator sweep with face coefficients formed from K: as the
+// stored form below, but each slot reads its K and face mask, takes its sibling's
+// K by shuffle and gathers K of the out-of-oct neighbours it is coupled to.
+template <typename T, int U2>
+__device__ __forceinline__ void operator_formed(const DevLevel& L, const FaceCoefs<T>& A, T scale, bool first, T tb,
+                                                int s0, int s1, int t0, int t1, const T* pl,
+                                                const T* __restrict__ diag, const T* __restrict__ r,
+                                                const T* __restrict__ p_old, T* __restrict__ q, double& pq) {
+  const int n = L.n_slots;
+  const T th = T(A.theta);
+  const T* __restrict__ K = A.K;
+  for (int tb0 = t0; tb0 < t1; tb0 += U2) {
+    int ii[U2], nbv[U2][3];
+    unsigned mk[U2];
+    T dg[U2], kown[U2];
+    bool valid[U2];
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const int i = (tb0 + u) * kBlock + int(threadIdx.x);
+      valid[u] = (tb0 + u < t1) && i < n;
+      ii[u] = valid[u] ? i : s1 - 1;
+      const int pos = ii[u] & 7, o = ii[u] >> 3;
+      dg[u] = diag[ii[u]];
+      kown[u] = K[ii[u]];
+      mk[u] = A.mask[ii[u]];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) nbv[u][a] = L.nbr[o * 6 + 2 * a + ((pos >> a) & 1)];
+    }
+    // gathers: K of the coupled out-of-oct neighbours, and the inputs of p at
+    // neighbours outside the block's range (lanes that need none read their own)
+    int jv[U2][3];
+    T kj[U2][3], rj[U2][3], dj[U2][3], pj[U2][3];
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const int pos = ii[u] & 7;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int nb = nbv[u][a];
+        const bool cpl = nb >= 0 && ((mk[u] >> (2 * a + ((pos >> a) & 1))) & 1u);
+        const int j = cpl ? ((nb << 3) | (pos ^ (1 << a))) : ii[u];
+        jv[u][a] = cpl ? j : -1;
+        const int jo = (j >= s0 && j < s1) ? ii[u] : j;
+        kj[u][a] = K[j];
+        rj[u][a] = r[jo];
+        dj[u][a] = diag[jo];
+        pj[u][a] = p_old[jo];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const int pos = ii[u] & 7;
+      const T pi = valid[u] ? pl[ii[u] - s0] : T(0);
+      const T Ki = kown[u];
+      T acc = dg[u] * pi;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int bit = 1 << a;
+        const T p_sib = __shfl_xor(pi, bit, 64);
+        const T K_sib = __shfl_xor(Ki, bit, 64);
+        const int my = (pos >> a) & 1;
+        const T c_in = ((mk[u] >> (2 * a + 1 - my)) & 1u) ? dev::face_coef(Ki, K_sib, scale, th) : T(0);
+        acc -= c_in * p_sib;
+        const int j = jv[u][a];
+        if (j >= 0) {
+          const T c_out = dev::face_coef(Ki, kj[u][a], scale, th);
+          T pn;
+          if (j >= s0 && j < s1) {
+            pn = pl[j - s0];
+          } else {
+            const T z = rj[u][a] / dj[u][a];
+            pn = first ? z : fma(tb, pj[u][a], z);
+          }
+          acc -= c_out * pn;
+        }
+      }
+      if (valid[u]) {
+        q[ii[u]] = acc;
+        pq += double(pi) * double(acc);
+      }
+    }
+  }
+}
+
 // Operator sweep of iteration `it`: p_it = z + beta p_{it-1} with z = r / d formed
 // on the fly (p_1 = z), q = A p_it, partial (p, q).
 //
@@ -180,7 +264,7 @@ __device__ __forceinline__ void body_init_finish(int prob, SweepPlan P, const do
 // alternate, so p_{it-1} is never overwritten during the sweep).
 template <typename T>
 __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int it,
-                                                   const T* __restrict__ Cp, const T* __restrict__ diag,
+                                                   const FaceCoefs<T>& A, const T* __restrict__ diag,
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
                                                    T* __restrict__ p_new, T* __restrict__ q,
                                                    PcgScalars* scs, double* part) {
@@ -247,6 +331,14 @@ __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int
   // phase 2: the operator, U2 tiles per trip
   constexpr int U2 = 2;
   double v[1] = {0.0};
+  if (!A.Cp) {  // coefficients formed from K
+    operator_formed<T, U2>(L, A, dev::coef_scale(A, L, bp.prob), first, tb, s0, s1, t0, t1, pl, diag, r, p_old, q,
+                           v[0]);
+    const bool mx[1] = {false};
+    write_partials<1>(v, mx, part, lds, vb);
+    return;
+  }
+  const T* __restrict__ Cp = A.Cp;
   for (int tb0 = t0; tb0 < t1; tb0 += U2) {
     int ii[U2], nbv[U2][3];
     T dg[U2], cown[U2][3];
@@ -413,19 +505,20 @@ __device__ __forceinline__ void body_check(int prob, SweepPlan P, int it_last, P
   if (threadIdx.x == 0) record_stop(sc, s, it_last, P);
 }
 
-__device__ __forceinline__ void body_true_residual(int vb, DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+__device__ __forceinline__ void body_true_residual(int vb, DevLevel L, SweepPlan P, const FaceCoefs<double>& A,
                                                           const double* __restrict__ diag,
                                                           const double* __restrict__ b,
                                                           const double* __restrict__ x, double* part) {
   __shared__ double lds[kLds];
   const int n = L.n_slots;
   const BlockPlan bp = block_plan(P, vb);
+  const double scale = dev::coef_scale(A, L, bp.prob);
   double v[1] = {0.0};
   for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
-    double ax = apply_stencil<double>(ii, L.nbr, Cp, n, diag[ii], x[ii], [&](int j) { return x[j]; });
+    double ax = apply_stencil<double>(ii, L.nbr, A, scale, n, diag[ii], x[ii], [&](int j) { return x[j]; });
     if (L.cif) ax -= dev::interface_terms<double>(ii, L, n, [&](int j) { return x[j]; });
     if (valid) {
       const double ri = b[i] - ax;
@@ -477,7 +570,7 @@ __device__ __forceinline__ void body_finish(int prob, SweepPlan P, int kind, con
 }
 
 // ------------------------------------------------------------ mixed precision
-__device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+__device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, const FaceCoefs<double>& A,
                                                      const double* __restrict__ diag,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x_old,
@@ -492,13 +585,14 @@ __device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, c
     return;
   }
   auto xv = [&](int j) -> double { return d ? x_old[j] + double(d[j]) : x_old[j]; };
+  const double scale = dev::coef_scale(A, L, bp.prob);
   double v[3] = {0.0, 0.0, 0.0};
   for (int t = bp.t0; t < bp.t1; ++t) {
     const int i = t * kBlock + int(threadIdx.x);
     const bool valid = i < n;
     const int ii = valid ? i : n - 1;
     const double xi = xv(ii);
-    const double ax = apply_stencil<double>(ii, L.nbr, Cp, n, diag[ii], xi, xv);
+    const double ax = apply_stencil<double>(ii, L.nbr, A, scale, n, diag[ii], xi, xv);
     if (valid) {
       const double ri = b[i] - ax;
       x_new[i] = xi;
@@ -590,20 +684,20 @@ __device__ __forceinline__ void body_inner_init(int vb, DevLevel L, SweepPlan P,
 
 // ------------------------------------------------------------ kernels
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, SweepPlan P, const T* __restrict__ Cp,
+__global__ __launch_bounds__(kBlock) void k_pcg_init(DevLevel L, SweepPlan P, FaceCoefs<T> A,
                                                      const T* __restrict__ diag, const T* __restrict__ b,
                                                      const T* __restrict__ x, T* __restrict__ r,
                                                      T* __restrict__ p_clear, double* part) {
-  body_pcg_init<T>(int(blockIdx.x), L, P, Cp, diag, b, x, r, p_clear, part);
+  body_pcg_init<T>(int(blockIdx.x), L, P, A, diag, b, x, r, p_clear, part);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pass_a(DevLevel L, SweepPlan P, int it,
-                                                   const T* __restrict__ Cp, const T* __restrict__ diag,
+                                                   FaceCoefs<T> A, const T* __restrict__ diag,
                                                    const T* __restrict__ r, const T* __restrict__ p_old,
                                                    T* __restrict__ p_new, T* __restrict__ q,
                                                    PcgScalars* scs, double* part) {
-  body_pass_a<T>(int(blockIdx.x), L, P, it, Cp, diag, r, p_old, p_new, q, scs, part);
+  body_pass_a<T>(int(blockIdx.x), L, P, it, A, diag, r, p_old, p_new, q, scs, part);
 }
 
 // Couplings of the composite system to other levels, one thread per listed row:
@@ -637,11 +731,11 @@ __global__ __launch_bounds__(kBlock) void k_pass_b(DevLevel L, SweepPlan P, int 
   body_pass_b<T>(int(blockIdx.x), L, P, it, diag, p, q, x, r, scs, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+__global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, SweepPlan P, FaceCoefs<double> A,
                                                           const double* __restrict__ diag,
                                                           const double* __restrict__ b,
                                                           const double* __restrict__ x, double* part) {
-  body_true_residual(int(blockIdx.x), L, P, Cp, diag, b, x, part);
+  body_true_residual(int(blockIdx.x), L, P, A, diag, b, x, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, const double* __restrict__ E,
@@ -650,14 +744,14 @@ __global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, 
   body_post_solve(int(blockIdx.x), L, P, E, rho, cp, dt, T_out, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, const double* __restrict__ Cp,
+__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, FaceCoefs<double> A,
                                                      const double* __restrict__ diag,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x_old,
                                                      const float* __restrict__ d, double* __restrict__ x_new,
                                                      float* __restrict__ r32, const PcgScalars* outer,
                                                      double* part) {
-  body_ir_sweep(int(blockIdx.x), L, P, Cp, diag, b, x_old, d, x_new, r32, outer, part);
+  body_ir_sweep(int(blockIdx.x), L, P, A, diag, b, x_old, d, x_new, r32, outer, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, SweepPlan P, const float* __restrict__ diag32,
@@ -692,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_finish(SweepPlan P, int first, do
 // sweeps.  A barrier that times out sets *abort and the block returns; the
 // others then time out at their next barrier, so the launch always ends.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan P, int max_iter, const T* Cp,
+__global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan P, int max_iter, FaceCoefs<T> A,
                                                            const T* diag, T* x, T* r, T* p0, T* p1, T* q,
                                                            PcgScalars* scs, double* part, unsigned* bar,
                                                            unsigned spin_limit) {
@@ -703,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan
     T* pn = (it & 1) ? p1 : p0;
     const T* po = (it & 1) ? p0 : p1;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
-      body_pass_a<T>(vb, L, P, it, Cp, diag, r, po, pn, q, scs, part);
+      body_pass_a<T>(vb, L, P, it, A, diag, r, po, pn, q, scs, part);
     if (!grid_barrier(bar, nb, epoch, spin_limit)) {
       if (threadIdx.x == 0) __hip_atomic_store(bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
@@ -743,9 +837,9 @@ __global__ __launch_bounds__(kBlock) void k_zero_u32(unsigned* p, int n) {
 
 // ------------------------------------------------------------ launchers
 template <typename T>
-void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const T* Cp, const T* diag,
+void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag,
                      const T* b, const T* x, T* r, T* p_clear, double* part) {
-  hipLaunchKernelGGL(k_pcg_init<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, Cp, diag, b, x, r, p_clear, part);
+  hipLaunchKernelGGL(k_pcg_init<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, A, diag, b, x, r, p_clear, part);
 }
 
 void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, PcgScalars* sc) {
@@ -753,15 +847,15 @@ void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, P
 }
 
 template <typename T>
-void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* Cp, const T* diag,
+void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const FaceCoefs<T>& A, const T* diag,
                    const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc, double* part, hipEvent_t t0,
                    hipEvent_t t1) {
   const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
   if (t0)
-    hipExtLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), uint32_t(lds), s, t0, t1, 0u, L, P, it, Cp, diag,
+    hipExtLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), uint32_t(lds), s, t0, t1, 0u, L, P, it, A, diag,
                           r, p_old, p_new, q, sc, part);
   else
-    hipLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), lds, s, L, P, it, Cp, diag, r, p_old, p_new, q, sc,
+    hipLaunchKernelGGL(k_pass_a<T>, dim3(P.G), dim3(kBlock), lds, s, L, P, it, A, diag, r, p_old, p_new, q, sc,
                        part);
 }
 
@@ -799,9 +893,9 @@ void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc
   hipLaunchKernelGGL(k_check, dim3(P.n_prob), dim3(kBlock), 0, s, P, it_last, sc, part);
 }
 
-void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp,
+void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,
                           const double* diag, const double* b, const double* x, PcgScalars* sc, double* part) {
-  hipLaunchKernelGGL(k_true_residual, dim3(P.G), dim3(kBlock), 0, s, L, P, Cp, diag, b, x, part);
+  hipLaunchKernelGGL(k_true_residual, dim3(P.G), dim3(kBlock), 0, s, L, P, A, diag, b, x, part);
   hipLaunchKernelGGL(k_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, 0, part, sc);
 }
 
@@ -811,10 +905,10 @@ void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, con
   hipLaunchKernelGGL(k_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, 1, part, sc);
 }
 
-void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const double* Cp, const double* diag,
+void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A, const double* diag,
                      const double* b, const double* x_old, const float* d, double* x_new, float* r32,
                      const PcgScalars* outer, double* part) {
-  hipLaunchKernelGGL(k_ir_sweep, dim3(P.G), dim3(kBlock), 0, s, L, P, Cp, diag, b, x_old, d, x_new, r32, outer,
+  hipLaunchKernelGGL(k_ir_sweep, dim3(P.G), dim3(kBlock), 0, s, L, P, A, diag, b, x_old, d, x_new, r32, outer,
                      part);
 }
 
@@ -864,7 +958,8 @@ template int persistent_blocks<double>(const SweepPlan&, int);
 template int persistent_blocks<float>(const SweepPlan&, int);
 
 template <typename T>
-hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter, const T* Cp,
+hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter,
+                                 const FaceCoefs<T>& A,
                                  const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc, double* part,
                                  unsigned* bar, int per_cu_cap) {
   const int res = resident_blocks<T>(P, per_cu_cap);
@@ -877,29 +972,30 @@ hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPl
   SweepPlan Pv = P;
   T* p0 = p[0];
   T* p1 = p[1];
-  void* args[] = {&Lv, &Pv, &max_iter, (void*)&Cp, (void*)&diag, &x, &r, &p0, &p1, &q, &sc, &part, &bar,
+  FaceCoefs<T> Av = A;
+  void* args[] = {&Lv, &Pv, &max_iter, &Av, (void*)&diag, &x, &r, &p0, &p1, &q, &sc, &part, &bar,
                   &spin_limit};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_pcg_persistent<T>), dim3(grid), dim3(kBlock),
                                     args, unsigned(lds), s);
 }
 
 template hipError_t launch_pcg_persistent<double>(hipStream_t, const DevLevel&, const SweepPlan&, int,
-                                                  const double*, const double*, double*, double*, double* const*,
+                                                  const FaceCoefs<double>&, const double*, double*, double*, double* const*,
                                                   double*, PcgScalars*, double*, unsigned*, int);
 template hipError_t launch_pcg_persistent<float>(hipStream_t, const DevLevel&, const SweepPlan&, int,
-                                                 const float*, const float*, float*, float*, float* const*,
+                                                 const FaceCoefs<float>&, const float*, float*, float*, float* const*,
                                                  float*, PcgScalars*, double*, unsigned*, int);
 
-template void launch_pcg_init<double>(hipStream_t, const DevLevel&, const SweepPlan&, const double*,
+template void launch_pcg_init<double>(hipStream_t, const DevLevel&, const SweepPlan&, const FaceCoefs<double>&,
                                       const double*, const double*, const double*, double*, double*,
                                       double*);
-template void launch_pass_a<double>(hipStream_t, const DevLevel&, const SweepPlan&, int, const double*,
+template void launch_pass_a<double>(hipStream_t, const DevLevel&, const SweepPlan&, int, const FaceCoefs<double>&,
                                     const double*, const double*, const double*, double*, double*,
                                     PcgScalars*, double*, hipEvent_t, hipEvent_t);
 template void launch_pass_b<double>(hipStream_t, const DevLevel&, const SweepPlan&, int, const double*,
                                     const double*, const double*, double*, double*, PcgScalars*, double*,
                                     hipEvent_t, hipEvent_t);
-template void launch_pass_a<float>(hipStream_t, const DevLevel&, const SweepPlan&, int, const float*,
+template void launch_pass_a<float>(hipStream_t, const DevLevel&, const SweepPlan&, int, const FaceCoefs<float>&,
                                    const float*, const float*, const float*, float*, float*, PcgScalars*,
                                    double*, hipEvent_t, hipEvent_t);
 template void launch_pass_b<float>(hipStream_t, const DevLevel&, const SweepPlan&, int, const float*,

@@ -88,13 +88,16 @@ __global__ __launch_bounds__(kBlock) void k_cell_K(DevLevel L, const double* __r
 // Theta-weighted step from the backward-Euler system (A1, b1): the right-hand side
 // loses (1 - theta) (A1 - I) E^n (same-level fluxes at the old time; the ghost
 // values are the same at both times), then ...
-__global__ __launch_bounds__(kBlock) void k_theta_rhs(DevLevel L, const double* __restrict__ Cp,
+__global__ __launch_bounds__(kBlock) void k_theta_rhs(DevLevel L, FaceCoefs<double> A1,
                                                       const double* __restrict__ diag,
                                                       const double* __restrict__ E, double theta,
                                                       double* __restrict__ b) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
+  // every lane of a wave takes part in the operator's shuffles
+  const int ii = i < L.n_slots ? i : L.n_slots - 1;
+  const double ax = dev::apply_stencil<double>(ii, L.nbr, A1, A1.scale, L.n_slots, diag[ii], E[ii],
+                                               [&](int j) { return E[j]; });
   if (i >= L.n_slots || L.child[i] != -1) return;
-  const double ax = dev::apply_stencil<double>(i, L.nbr, Cp, L.n_slots, diag[i], E[i], [&](int j) { return E[j]; });
   b[i] -= (1.0 - theta) * (ax - E[i]);
 }
 
@@ -112,7 +115,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
     DevLevel L, const double* __restrict__ K, const double* __restrict__ Kc,
     const double* __restrict__ E, const double* __restrict__ Ec, const double* __restrict__ rho,
     const double* __restrict__ reg, double coef, double w, double alpha, CouplingParams cp, CellKParams kp,
-    OuterBC ob, double dt, double* __restrict__ Cp, double* __restrict__ diag, double* __restrict__ b) {
+    OuterBC ob, double dt, double* __restrict__ Cp, uint8_t* __restrict__ mask, double* __restrict__ diag,
+    double* __restrict__ b) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int n = L.n_slots;
   if (i >= n) return;
@@ -120,6 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
     Cp[i] = 0.0;
     Cp[size_t(n) + i] = 0.0;
     Cp[2 * size_t(n) + i] = 0.0;
+    mask[i] = 0;
     diag[i] = 1.0;
     b[i] = E[i];
     return;
@@ -129,6 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
   const double Ki = K[i];
   double d = 1.0, bb = E[i];
   double cplus[3] = {0.0, 0.0, 0.0};
+  unsigned m = 0;
 #pragma unroll
   for (int dir = 0; dir < 6; ++dir) {
     const int j = same_level_nb(L.nbr, i, dir);
@@ -140,6 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
         bb += w * C * E[j] + (1.0 - w) * Fin;
       } else {
         d += C;
+        m |= 1u << dir;
         if (dir & 1) cplus[dir >> 1] = C;
       }
     } else {
@@ -175,6 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(
   Cp[i] = cplus[0];
   Cp[size_t(n) + i] = cplus[1];
   Cp[2 * size_t(n) + i] = cplus[2];
+  mask[i] = uint8_t(m);
   diag[i] = d;
   b[i] = bb;
 }
@@ -305,14 +313,18 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* p, int64_t n, T v) {
 
 // FP32 copies of the operator for the inner solve of the mixed-precision form.
 __global__ __launch_bounds__(kBlock) void k_to_f32(int64_t n, const double* __restrict__ Cp,
+                                                   const double* __restrict__ K,
                                                    const double* __restrict__ diag,
-                                                   float* __restrict__ Cp32,
+                                                   float* __restrict__ Cp32, float* __restrict__ K32,
                                                    float* __restrict__ diag32) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
-  Cp32[i] = float(Cp[i]);
-  Cp32[n + i] = float(Cp[n + i]);
-  Cp32[2 * n + i] = float(Cp[2 * n + i]);
+  if (Cp) {
+    Cp32[i] = float(Cp[i]);
+    Cp32[n + i] = float(Cp[n + i]);
+    Cp32[2 * n + i] = float(Cp[2 * n + i]);
+  }
+  if (K) K32[i] = float(K[i]);
   diag32[i] = float(diag[i]);
 }
 
@@ -355,10 +367,10 @@ void launch_cell_K(hipStream_t s, const DevLevel& L, const double* E, const doub
 void launch_assemble(hipStream_t s, const DevLevel& L, const double* K, const double* K_coarse,
                      const double* E, const double* E_coarse, const double* rho, const double* reg,
                      double dt, double w, double alpha, const CouplingParams& cp, const CellKParams& kp,
-                     const OuterBC& ob, double* Cp, double* diag, double* b) {
+                     const OuterBC& ob, double* Cp, uint8_t* mask, double* diag, double* b) {
   const double coef = dt / (L.dx * L.dx);
   hipLaunchKernelGGL(k_assemble, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, K, K_coarse, E,
-                     E_coarse, rho, reg, coef, w, alpha, cp, kp, ob, dt, Cp, diag, b);
+                     E_coarse, rho, reg, coef, w, alpha, cp, kp, ob, dt, Cp, mask, diag, b);
 }
 
 void launch_assemble_composite(hipStream_t s, const DevLevel& C, const double* K, const double* E,
@@ -368,9 +380,9 @@ void launch_assemble_composite(hipStream_t s, const DevLevel& C, const double* K
                      Cp, cif, c2f, diag, b);
 }
 
-void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E, double* Cp, double* diag,
-                       double* b) {
-  hipLaunchKernelGGL(k_theta_rhs, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, Cp, diag, E, theta, b);
+void launch_theta_step(hipStream_t s, const DevLevel& L, double theta, const double* E,
+                       const FaceCoefs<double>& A1, double* Cp, double* diag, double* b) {
+  hipLaunchKernelGGL(k_theta_rhs, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, A1, diag, E, theta, b);
   hipLaunchKernelGGL(k_theta_scale, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L.n_slots, theta, Cp, diag);
 }
 
@@ -396,9 +408,9 @@ void launch_fill_f32(hipStream_t s, float* p, int64_t n, float v) {
   hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
 }
 
-void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* diag, float* Cp32,
-                   float* diag32) {
-  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, Cp, diag, Cp32, diag32);
+void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* K, const double* diag, float* Cp32,
+                   float* K32, float* diag32) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, Cp, K, diag, Cp32, K32, diag32);
 }
 
 }  // namespace amrfld

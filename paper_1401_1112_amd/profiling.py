@@ -34,7 +34,7 @@ def run_copy(mib: int, reps: int) -> None:
     print(f"copied {mib} MiB x {reps}", flush=True)
 
 
-def run_batch(patches: int, steps: int, mode: str, per_cu: int) -> None:
+def run_batch(patches: int, steps: int, mode: str, per_cu: int, form_coefs: bool = False) -> None:
     """The batched workload (seeded patches, n in [8, 128]) for one warm-up step and
     `steps` timed steps, host-polled or as persistent launches (optionally in a graph)."""
     import time
@@ -46,6 +46,7 @@ def run_batch(patches: int, steps: int, mode: str, per_cu: int) -> None:
     from .solver import BatchSolver
     ps, alpha = patch_batch(4000, patches)
     kw = {} if mode == "polled" else {"persistent": True, "graph": mode == "graph", "persistent_per_cu": per_cu}
+    kw["form_coefs"] = form_coefs
     bs = BatchSolver(robin_alpha=alpha, **kw)
     h = bs.upload(ps)
     bs.run(h, 1, 1e-10)
@@ -56,12 +57,12 @@ def run_batch(patches: int, steps: int, mode: str, per_cu: int) -> None:
     el = time.perf_counter() - t0
     st = bs.stats()
     ci = sum(x["n_leaf"] * x["iters"] for x in st)
-    print(f"batch {mode}: {patches} patches, {steps} steps in {el:.3f} s, {ci / el:.3e} cell-iterations/s, "
+    print(f"batch {mode}{' formed' if form_coefs else ''}: {patches} patches, {steps} steps in {el:.3f} s, {ci / el:.3e} cell-iterations/s, "
           f"{st[0]['sweep_blocks']} sweep blocks, {st[0]['launch_blocks']} launch blocks", flush=True)
     bs.close()
 
 
-def run_collapse(steps: int, mode: str, precision: str) -> None:
+def run_collapse(steps: int, mode: str, precision: str, form_coefs: bool = False) -> None:
     """The collapse-like hierarchy (levels 6..13, ~41 M cells, coupled E-T): one warm-up
     and `steps` timed coarse steps from the same state, host-polled or one persistent
     launch per solve."""
@@ -75,7 +76,7 @@ def run_collapse(steps: int, mode: str, precision: str) -> None:
     from .solver import solver_from_problem
     p = config_collapse()
     prec = L.MIXED if precision == "mixed" else L.FP64
-    s = solver_from_problem(p, precision=prec, persistent=(mode == "persistent"))
+    s = solver_from_problem(p, precision=prec, persistent=(mode == "persistent"), form_coefs=form_coefs)
     fields = {lv: tuple(t.clone() for t in s._fields[lv]) for lv in s.levels}
 
     def step():
@@ -92,7 +93,7 @@ def run_collapse(steps: int, mode: str, precision: str) -> None:
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
     st = s.stats()
-    print(f"collapse {precision} {mode}: {el * 1e3:.1f} ms per coarse step, {len(st)} solves, "
+    print(f"collapse {precision} {mode}{' formed' if form_coefs else ''}: {el * 1e3:.1f} ms per coarse step, {len(st)} solves, "
           f"{sum(x['iters'] for x in st)} PCG iterations, {sum(x['outer_iters'] for x in st)} refinement sweeps",
           flush=True)
     s.close()
@@ -186,21 +187,23 @@ def main(argv=None):
     b.add_argument("--steps", type=int, default=2)
     b.add_argument("--mode", choices=("polled", "persistent", "graph"), default="polled")
     b.add_argument("--per-cu", type=int, default=0)
+    b.add_argument("--form-coefs", action="store_true")
     cl = sub.add_parser("collapse")
     cl.add_argument("--steps", type=int, default=1)
     cl.add_argument("--mode", choices=("polled", "persistent"), default="polled")
     cl.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
+    cl.add_argument("--form-coefs", action="store_true")
     u = sub.add_parser("unique")
     u.add_argument("--steps", type=int, default=1)
     a = ap.parse_args(argv)
     if a.cmd == "unique":
         run_unique(a.steps)
     elif a.cmd == "collapse":
-        run_collapse(a.steps, a.mode, a.precision)
+        run_collapse(a.steps, a.mode, a.precision, a.form_coefs)
     elif a.cmd == "copy":
         run_copy(a.mib, a.reps)
     elif a.cmd == "batch":
-        run_batch(a.patches, a.steps, a.mode, a.per_cu)
+        run_batch(a.patches, a.steps, a.mode, a.per_cu, a.form_coefs)
     else:
         print(summarize(a.dir))
     return 0

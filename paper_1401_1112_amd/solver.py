@@ -12,8 +12,8 @@ class HierarchySolver:
     def __init__(self, base_level, octs, *, robin_alpha=0.5, max_iter=10000, precision=L.FP64,
                  linf_test=True, abs_floor=1e-14, a_rad=1.0, c_v=1.0, nsub=None, check_every=0,
                  true_residual=True, time_sweeps=0, inner_tol=1e-4, max_outer=30, max_blocks=0,
-                 persistent=False, persistent_per_cu=0, theta=1.0, K_exp=0.0, outer=None, device="cuda:0",
-                 stream=None):
+                 persistent=False, persistent_per_cu=0, theta=1.0, K_exp=0.0, outer=None, form_coefs=False,
+                 device="cuda:0", stream=None):
         L.load()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -39,6 +39,7 @@ class HierarchySolver:
         o.persistent_per_cu = int(persistent_per_cu)
         o.theta = float(theta)
         o.K_exp = float(K_exp)
+        o.form_coefs = int(bool(form_coefs))
         for d, v in (outer or {}).items():  # box face direction -> Dirichlet energy held there
             o.outer_mode[int(d)] = 1
             o.outer_value[int(d)] = float(v)
@@ -125,8 +126,9 @@ class HierarchySolver:
     def last_error(self):
         return L.amrfld_last_error(self.ctx)
 
-    def set_launch(self, max_blocks=0, persistent=False, persistent_per_cu=0):
-        self._check(L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu))
+    def set_launch(self, max_blocks=0, persistent=False, persistent_per_cu=0, form_coefs=False):
+        self._check(L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu,
+                                        int(bool(form_coefs))))
 
 
 def sample_problem_fields(solver: HierarchySolver, problem):
@@ -160,8 +162,8 @@ class BatchSolver:
 
     def __init__(self, *, robin_alpha=0.5, max_iter=10000, linf_test=True, abs_floor=1e-14,
                  inner_tol=1e-4, max_outer=30, max_blocks=0, time_sweeps=0, true_residual=True,
-                 check_every=0, persistent=False, graph=False, persistent_per_cu=0, device="cuda:0",
-                 stream=None):
+                 check_every=0, persistent=False, graph=False, persistent_per_cu=0, form_coefs=False,
+                 device="cuda:0", stream=None):
         L.load()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -180,6 +182,7 @@ class BatchSolver:
         o.persistent = int(bool(persistent))
         o.graph = int(bool(graph))
         o.persistent_per_cu = int(persistent_per_cu)
+        o.form_coefs = int(bool(form_coefs))
         o.stream = self.stream.cuda_stream
         self.ctx = L.amrfld_create(o)
 
@@ -246,7 +249,7 @@ class BatchSolver:
     def last_error(self):
         return L.amrfld_last_error(self.ctx)
 
-    def set_launch(self, max_blocks=0, persistent=False, persistent_per_cu=0):
-        st = L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu)
+    def set_launch(self, max_blocks=0, persistent=False, persistent_per_cu=0, form_coefs=False):
+        st = L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu, int(bool(form_coefs)))
         if st != L.OK:
             raise L.AmrfldError(st, L.amrfld_last_error(self.ctx))

@@ -69,3 +69,18 @@ def test_shipped_table_keys_match_the_benchmark_workloads():
     keys = set(d["entries"])
     assert A.workload_key("levels", [262144, 1250000, 1250000, 1250000], 0) in keys
     assert A.workload_key("batch", [int(max(2, n)) for n in patch_sizes(4000, 512)], 0) in keys
+
+
+def test_shipped_entries_are_candidates():
+    # every shipped choice is one of the shapes its tuner times
+    table = json.load(open(A.SHIPPED))
+    cands = {"levels": A.LEVEL_CANDIDATES, "batch": A.BATCH_SHAPES, "level-shapes": A.LEVEL_SHAPES}
+    for key, e in table["entries"].items():
+        assert e["best"] in [dict(c) for c in cands[key.split("|")[0]]], key
+        assert json.dumps(e["best"], sort_keys=True) in e["ms"], key
+
+
+def test_shipped_table_can_be_skipped(monkeypatch):
+    monkeypatch.setenv("AMRFLD_TUNE_SHIPPED", "0")
+    key = next(iter(json.load(open(A.SHIPPED))["entries"]))
+    assert A._shipped(key, arch="gfx950") is None

@@ -1,0 +1,85 @@
+"""Face coefficients formed in every sweep from the cells' diffusivities
+(amrfld_opts.form_coefs) against the three coefficients stored per cell: the formed
+coefficient is the assembly's own expression, so every FP64 solve must give the same
+iteration counts and the same bits.  The FP32 inner operator of the mixed form is formed
+in FP32 from FP32 diffusivities, so there the two forms agree to the refinement's
+tolerance, not bitwise.  Parity of the stored form (the default) with the oracle is what
+every other GPU test checks."""
+import numpy as np
+import pytest
+
+from synth.configs import config_equilibrium, config_tiny, patch_batch
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"dirichlet": 0, "neumann": 1, "robin": 2}
+
+
+def _run_levels(p, mode, steps, **kw):
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    s = solver_from_problem(p, **kw)
+    its = []
+    for _ in range(steps):
+        s.advance(p.dt_coarse, mode, p.tol)
+        its.append([x["iters"] for x in s.stats()])
+    out = {l: to_numpy(s.E(l)) for l in p.hierarchy.levels}
+    s.close()
+    return out, its
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("mode", ["dirichlet", "neumann", "robin"])
+@pytest.mark.parametrize("kmode", ["lp", "const", "minerbo"])
+def test_formed_equals_stored_levels(seed, mode, kmode):
+    p = config_tiny(seed, base_level=3, max_level=5, p_refine=0.5, kmode=kmode, tol=1e-12)
+    a, ia = _run_levels(p, MODES[mode], 2, form_coefs=True)
+    b, ib = _run_levels(p, MODES[mode], 2)
+    assert ia == ib
+    assert all(np.array_equal(a[l], b[l]) for l in a)
+
+
+@pytest.mark.parametrize("variant", ["theta", "power_outer", "persistent"])
+def test_formed_equals_stored_variants(variant):
+    if variant == "power_outer":
+        p = config_equilibrium(max_level=5, tol=1e-12, n_coarse_steps=2)
+        kw = {}
+    else:
+        p = config_tiny(2, base_level=3, max_level=5, p_refine=0.5, tol=1e-12)
+        kw = {"theta": 0.5} if variant == "theta" else {"persistent": True}
+    a, ia = _run_levels(p, 0, 2, form_coefs=True, **kw)
+    b, ib = _run_levels(p, 0, 2, **kw)
+    assert ia == ib
+    assert all(np.array_equal(a[l], b[l]) for l in a)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_formed_equals_stored_batch(persistent):
+    from paper_1401_1112_amd.solver import BatchSolver
+    patches, alpha = patch_batch(4300, 14, n_min=2, n_max=32)
+    out = []
+    for formed in (True, False):
+        bs = BatchSolver(robin_alpha=alpha, persistent=persistent, form_coefs=formed)
+        h = bs.upload(patches)
+        bs.run(h, 2, 1e-10)
+        out.append((bs.result(h), [x["iters"] for x in bs.stats()]))
+        bs.close()
+    (a, ia), (b, ib) = out
+    assert ia == ib
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_mixed_formed_and_stored_both_meet_threshold():
+    from paper_1401_1112_amd import MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    p = config_tiny(3, base_level=3, max_level=5, p_refine=0.5, tol=1e-10)
+    res = []
+    for formed in (True, False):
+        s = solver_from_problem(p, precision=MIXED, form_coefs=formed)
+        s.advance(p.dt_coarse, 0, p.tol)
+        for st in s.stats():
+            thr = max(p.tol * st["rnorm0"], p.abs_floor * st["bnorm"])
+            assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= thr * (1 + 1e-12), st
+        res.append({l: to_numpy(s.E(l)) for l in p.hierarchy.levels})
+        s.close()
+    for l in res[0]:
+        assert np.linalg.norm(res[0][l] - res[1][l]) <= 1e-8 * np.linalg.norm(res[1][l])

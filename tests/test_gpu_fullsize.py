@@ -181,3 +181,20 @@ def test_patch_batch_full_size_persistent_bitwise(batch512):
         assert mode in (1, 2)
         assert ia == ib
         assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_lognormal_formed_coefficients_equal_stored_bitwise(lognormal, fp64_step):
+    # face coefficients formed from K in every sweep against the stored ones (the
+    # benchmark's default), at full size: same counts, same bits
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    gpu, counts, _ = fp64_step
+    p = lognormal
+    s = solver_from_problem(p, form_coefs=True)
+    s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+    assert [(st["level"], st["iters"]) for st in s.stats()] == counts
+    for l in p.hierarchy.levels:
+        e, cells = gpu[l]
+        assert np.array_equal(s.cells(l), cells)
+        assert np.array_equal(to_numpy(s.E(l)), e)
+    s.close()
