@@ -132,7 +132,13 @@ def _cpu_baseline(p, budget_s=30.0):
             done.append(f"L{lvl}:{st['iters']}it")
             if t_solve >= budget_s:
                 break
+    model = ""
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": cell_it / t_solve, "unit": "cell-iterations/s", "cores": 1, "kind": "oracle",
+            "host_cpu": f"{model} ({os.cpu_count()} logical CPUs visible)",
             "sample": (f"first {len(done)} of 15 level solves of one coarse step ({', '.join(done)}), "
                        f"{cell_it:.3e} cell-iterations in {t_solve:.1f} s, numpy/scipy CSR, 1 thread"),
             "seconds": t_solve}
