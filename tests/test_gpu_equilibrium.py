@@ -185,3 +185,23 @@ def test_power_law_rejected_for_patches():
     st = bs.run(h, 1, 1e-10, raise_on_error=False)
     bs.close()
     assert st == E_INVALID
+
+
+def test_equilibrium_mixed_precision():
+    # the FP32 inner solves with FP64 refinement on the power law and held faces: every
+    # solve meets its threshold on the FP64 true residual, and the step agrees with FP64
+    from paper_1401_1112_amd import BC_DIRICHLET, MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    p = config_equilibrium(max_level=6, tol=1e-10)
+    out = []
+    for prec in (None, MIXED):
+        s = solver_from_problem(p, **({} if prec is None else {"precision": prec}))
+        for _ in range(3):
+            s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+            for st in s.stats():
+                thr = max(p.tol * st["rnorm0"], p.abs_floor * st["bnorm"])
+                assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= 1.05 * thr, st
+        out.append({l: to_numpy(s.E(l)) for l in p.hierarchy.levels})
+        s.close()
+    for l in out[0]:
+        assert np.linalg.norm(out[1][l] - out[0][l]) <= 1e-8 * np.linalg.norm(out[0][l])

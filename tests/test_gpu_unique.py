@@ -146,3 +146,9 @@ def test_unique_full_size_lognormal():
         print(f"level {l}: unique vs adaptive relative L2 {d:.2e}")
         assert d < 0.1
     a.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_unique_parity_minerbo(seed):
+    # the composite system with the Minerbo limiter of the collapse runs
+    _parity(config_tiny(seed, base_level=3, max_level=5, p_refine=0.5, kmode="minerbo", tol=1e-12), 2)
