@@ -80,7 +80,11 @@ typedef struct {
   int max_blocks;        /* blocks per PCG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
   int persistent;        /* 1 = all PCG iterations of a solve (batch form: of a step) in one cooperative
                             launch, where the device can run it; else host-polled sweeps */
-  int graph;             /* batch form with persistent: 1 = capture all steps in one hipGraph */
+  int graph;             /* with persistent: the batch form captures all its steps in one hipGraph;
+                            amrfld_advance_subcycled (FP64) captures one coarse step, all its level
+                            solves each in one persistent launch, and replays it while dt, bc_mode,
+                            tol, the context's parameters and its device buffers stay the same
+                            (set_coeffs, set_launch and build_level force a new capture) */
   void* stream;          /* hipStream_t */
   int persistent_per_cu; /* persistent launch: resident blocks per compute unit (0 = as many as fit) */
   double theta;          /* time weighting of the level solves: 1 backward Euler (default), 1/2

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <cmath>
 #include <cstring>
@@ -32,16 +33,24 @@ void check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Counts device allocations and frees: a captured graph holds raw pointers, so it
+// is replayed only while this count is the one it was captured at.
+std::atomic<uint64_t> g_alloc_epoch{0};
+
 template <class T>
 T* dalloc(int64_t n, const char* what) {
   void* p = nullptr;
   if (n <= 0) n = 1;
   check(hipMalloc(&p, size_t(n) * sizeof(T)), what);
+  g_alloc_epoch.fetch_add(1);
   return static_cast<T*>(p);
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (p) {
+    (void)hipFree(p);
+    g_alloc_epoch.fetch_add(1);
+  }
 }
 
 struct LevelState {
@@ -102,7 +111,7 @@ struct BatchState {
     for (void* p : {(void*)nbr, (void*)cnb, (void*)child, (void*)oct_prob, (void*)idx, (void*)blk_prob,
                     (void*)blk0, (void*)tile0, (void*)d_out_off, (void*)E, (void*)rho, (void*)K, (void*)Cp,
                     (void*)diag, (void*)b, (void*)pp, (void*)src, (void*)mask})
-      if (p) (void)hipFree(p);
+      dfree(p);
     nbr = cnb = child = oct_prob = idx = blk_prob = blk0 = tile0 = nullptr;
     d_out_off = nullptr;
     E = rho = K = Cp = diag = b = nullptr;
@@ -138,9 +147,28 @@ struct BatchState {
   }
 };
 
+// One coarse step of the subcycled driver captured as a graph (FP64, persistent
+// solves), replayed while its parameters and every device buffer stay the same.
+struct StepGraph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  double dt = 0.0, tol = 0.0;
+  int mode = -1;
+  uint64_t alloc_epoch = 0, param_epoch = 0;
+  void reset() {
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (g) (void)hipGraphDestroy(g);
+    ex = nullptr;
+    g = nullptr;
+    mode = -1;
+  }
+};
+
 struct amrfld_ctx {
   amrfld_opts o{};
   std::string err;
+  uint64_t param_epoch = 0;  // bumped by every call that changes what a captured step bakes in
+  StepGraph step_graph;
   int finest = -1;
   std::vector<LevelState> lev;  // index: level - base
   int64_t ws_n = 0;
@@ -651,6 +679,174 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
     return fail(c, status, "non-finite value in the residual of level " + std::to_string(level));
   if (status == AMRFLD_E_NOCONV)
     return fail(c, status, "PCG did not converge within max_iter on level " + std::to_string(level));
+  return AMRFLD_OK;
+}
+
+// The solves of one coarse step in the order of step(): level, dt and whether the
+// finer level is restricted into it first.
+struct ScheduledSolve {
+  int level;
+  double dt;
+  bool restrict_first;
+};
+
+void schedule(const amrfld_ctx* c, int level, double dt, std::vector<ScheduledSolve>& out) {
+  bool restricted = false;
+  if (level < c->finest) {
+    const int ns = c->nsub(level + 1);
+    for (int k = 0; k < ns; ++k) schedule(c, level + 1, dt / ns, out);
+    restricted = true;
+  }
+  out.push_back({level, dt, restricted});
+}
+
+// The kernels of one level solve with its PCG in one persistent launch, enqueued
+// without host synchronisation (scalars in sc; the barrier words of c->bar, whose
+// abort flag is left for the caller to read).
+hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int mode, double tol, PcgScalars* sc) {
+  LevelState& L = c->L(level);
+  LevelState* Lc = level > c->o.base_level ? &c->L(level - 1) : nullptr;
+  const DevLevel D = L.dev();
+  if (Lc) {
+    const double* Ecc = level - 1 > c->o.base_level ? c->L(level - 2).E : nullptr;
+    launch_cell_K(st, Lc->dev(), Lc->E, Lc->rho, Ecc, kparams(*Lc), outer_bc(c), Lc->K);
+  }
+  launch_cell_K(st, D, L.E, L.rho, Lc ? Lc->E : nullptr, kparams(L), outer_bc(c), L.K);
+  const double w = mode == AMRFLD_BC_DIRICHLET ? 1.0 : mode == AMRFLD_BC_NEUMANN ? 0.0 : c->o.robin_alpha;
+  const CouplingParams cp = cparams(c, L);
+  launch_assemble(st, D, L.K, Lc ? Lc->K : nullptr, L.E, Lc ? Lc->E : nullptr, L.rho, L.reg, dt, w,
+                  c->o.robin_alpha, cp, kparams(L), outer_bc(c), L.Cp, L.mask, L.diag, L.b);
+  const double scale = dt / (D.dx * D.dx);
+  if (c->o.theta != 1.0)
+    launch_theta_step(st, D, c->o.theta, L.E, face_coefs(c, L.Cp, L.K, L.mask, scale, 1.0, false), L.Cp, L.diag,
+                      L.b);
+  const FaceCoefs<double> Aop = face_coefs(c, L.Cp, L.K, L.mask, scale, c->o.theta, false);
+  const int n_tiles = tiles_of(D.n_slots);
+  const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
+  SweepPlan Pp = P;
+  Pp.done_count = c->bar + kBarDone;
+  launch_init_scalars(st, sc, 1, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
+  launch_zero_u32(st, c->bar, kBarAbort);  // arrivals, releases, stop count; not the abort flag
+  launch_pcg_init<double>(st, D, P, Aop, L.diag, L.b, L.E, c->r, c->p[0], c->partials);
+  launch_init_finish(st, P, c->partials, sc);
+  const hipError_t e = launch_pcg_persistent<double>(st, D, Pp, c->o.max_iter, Aop, L.diag, L.E, c->r, c->p, c->q,
+                                                     sc, c->partials, c->bar, c->o.persistent_per_cu);
+  if (e != hipSuccess) return e;
+  if (c->o.true_residual) launch_true_residual(st, D, P, Aop, L.diag, L.b, L.E, sc, c->partials);
+  launch_post_solve(st, D, P, L.E, L.rho, cp, dt, L.T, sc, c->partials);
+  if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN))
+    launch_flux_register(st, D, L.K, Lc->K, L.E, Lc->E, dt, Lc->reg, int(Lc->t.n_slots()));
+  if (L.reg) launch_fill(st, L.reg, 6 * L.t.n_slots(), 0.0);
+  return hipGetLastError();
+}
+
+// One coarse step as a graph of persistent level solves: captured on first use and
+// replayed while dt, mode, tol, the context's parameters and its device buffers are
+// those it was captured with.  AMRFLD_E_STATE: not available here (mixed precision,
+// no cooperative launch, capture refused); the caller then runs the step eagerly.
+amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double tol) {
+  if (!c->o.graph || !c->o.persistent || c->o.precision != AMRFLD_FP64) return AMRFLD_E_STATE;
+  std::vector<ScheduledSolve> sched;
+  schedule(c, c->o.base_level, dt_coarse, sched);
+  const int n = int(sched.size());
+  // everything the captured kernels touch exists before the capture
+  int64_t max_slots = 0;
+  for (int l = c->o.base_level; l <= c->finest; ++l) {
+    upload_tables(c, c->L(l));
+    max_slots = std::max<int64_t>(max_slots, c->L(l).t.n_slots());
+    if (l < c->finest && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN)) ensure_reg(c, c->L(l));
+  }
+  ensure_workspace(c, max_slots);
+  ensure_scalars(c, n);
+  if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
+  for (int l = c->o.base_level; l <= c->finest; ++l) {
+    const int nt = tiles_of(c->L(l).t.n_slots());
+    SweepPlan P = single_plan(sweep_blocks(nt, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), nt);
+    if (persistent_blocks<double>(P, c->o.persistent_per_cu) <= 0) return AMRFLD_E_STATE;
+  }
+  const hipStream_t us = c->stream();
+  StepGraph& sg = c->step_graph;
+  const uint64_t epoch = g_alloc_epoch.load();
+  if (!(sg.ex && sg.dt == dt_coarse && sg.tol == tol && sg.mode == mode && sg.alloc_epoch == epoch &&
+        sg.param_epoch == c->param_epoch)) {
+    sg.reset();
+    if (!c->cap_stream) check(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "stream");
+    for (auto& e : c->cap_ev)
+      if (!e) check(hipEventCreate(&e), "event");
+    check(hipEventRecord(c->cap_ev[0], us), "event");
+    check(hipStreamWaitEvent(c->cap_stream, c->cap_ev[0], 0), "event");
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e_rec = e;
+    if (e == hipSuccess) {
+      launch_zero_u32(c->cap_stream, c->bar, kBarWords);
+      int k = 0;
+      for (const ScheduledSolve& op : sched) {
+        if (e_rec != hipSuccess) break;
+        if (op.restrict_first) {
+          LevelState& F = c->L(op.level + 1);
+          launch_restrict(c->cap_stream, F.dev(), F.E, c->L(op.level).E);
+        }
+        e_rec = record_solve(c, c->cap_stream, op.level, op.dt, mode, tol, c->sc + k++);
+      }
+    }
+    const hipError_t e_end = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &sg.g) : e;
+    if (e_rec == hipSuccess && e_end == hipSuccess && sg.g) e = hipGraphInstantiate(&sg.ex, sg.g, nullptr, nullptr, 0);
+    else e = hipErrorNotSupported;
+    if (e != hipSuccess) {
+      sg.reset();
+      (void)hipGetLastError();
+      return AMRFLD_E_STATE;
+    }
+    sg.dt = dt_coarse;
+    sg.tol = tol;
+    sg.mode = mode;
+    sg.alloc_epoch = epoch;
+    sg.param_epoch = c->param_epoch;
+  }
+  check(hipEventRecord(c->ev[0], us), "event");
+  check(hipGraphLaunch(sg.ex, us), "graph launch");
+  check(hipEventRecord(c->ev[3], us), "event");
+  check(hipStreamSynchronize(us), "sync");
+  float total_ms = 0.f;
+  check(hipEventElapsedTime(&total_ms, c->ev[0], c->ev[3]), "event");
+  unsigned aborted = 0;
+  check(hipMemcpy(&aborted, c->bar + kBarAbort, sizeof(unsigned), hipMemcpyDeviceToHost), "abort flag");
+  read_scalars(c, c->h_sc, c->sc, n);
+  amrfld_status worst = AMRFLD_OK;
+  std::string worst_msg;
+  for (int k = 0; k < n; ++k) {
+    const PcgScalars& h = c->h_sc[k];
+    const LevelState& L = c->L(sched[k].level);
+    const int nt = tiles_of(L.t.n_slots());
+    const SweepPlan P = single_plan(sweep_blocks(nt, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), nt);
+    amrfld_stats st{};
+    st.level = sched[k].level;
+    st.iters = h.iter;
+    st.converged = h.converged;
+    st.n_leaf = L.t.n_leaf;
+    st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
+    st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+    st.linf_change = h.linf;
+    st.min_E = h.min_E;
+    st.dt = sched[k].dt;
+    st.ms = total_ms / n;
+    st.pcg_ms = -1.0;
+    st.rnorm0 = h.rnorm0;
+    st.bnorm = h.bnorm;
+    st.sweep_blocks = P.G;
+    st.launch_blocks = persistent_blocks<double>(P, c->o.persistent_per_cu);
+    st.launch_mode = 2;
+    st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
+    if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
+      worst = amrfld_status(st.status);
+      worst_msg = (st.status == AMRFLD_E_NONFINITE ? "non-finite value in the residual of level "
+                                                   : "PCG did not converge within max_iter on level ") +
+                  std::to_string(sched[k].level);
+    }
+    c->stats.push_back(st);
+  }
+  if (aborted) return fail(c, AMRFLD_E_DEVICE, "persistent sweep: a grid barrier timed out");
+  if (worst != AMRFLD_OK) return fail(c, worst, worst_msg);
   return AMRFLD_OK;
 }
 
@@ -1354,6 +1550,7 @@ amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
 void amrfld_destroy(amrfld_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream());
+  c->step_graph.reset();
   for (auto& L : c->lev) L.release();
   if (c->batch) {
     c->batch->release();
@@ -1380,6 +1577,7 @@ void amrfld_destroy(amrfld_ctx* c) {
 
 amrfld_status amrfld_build_level(amrfld_ctx* c, int level, int64_t n_oct, const int32_t* oct_ijk) {
   if (!c) return AMRFLD_E_INVALID;
+  ++c->param_epoch;
   if (!oct_ijk) return fail(c, AMRFLD_E_INVALID, "oct_ijk is NULL");
   const int expect = c->finest < 0 ? c->o.base_level : c->finest + 1;
   if (level != expect)
@@ -1475,6 +1673,7 @@ amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, con
     L.c_light = c_light;
     L.K_exp = c->o.K_exp;
     L.has_fields = true;
+    ++c->param_epoch;
     return AMRFLD_OK;
   });
 }
@@ -1505,7 +1704,11 @@ amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_m
   const amrfld_status rt = check_theta(c, bc_mode);
   if (rt != AMRFLD_OK) return rt;
   c->stats.clear();
-  return guarded(c, [&]() { return step(c, c->o.base_level, dt_coarse, bc_mode, tol); });
+  return guarded(c, [&]() {
+    const amrfld_status g = advance_graph(c, dt_coarse, bc_mode, tol);
+    if (g != AMRFLD_E_STATE) return g;
+    return step(c, c->o.base_level, dt_coarse, bc_mode, tol);
+  });
 }
 
 amrfld_status amrfld_advance_unique(amrfld_ctx* c, double dt_coarse, double tol) {
@@ -1591,6 +1794,7 @@ amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, i
   c->o.persistent = persistent ? 1 : 0;
   c->o.persistent_per_cu = persistent_per_cu;
   c->o.form_coefs = form_coefs ? 1 : 0;
+  ++c->param_epoch;
   c->err.clear();
   return AMRFLD_OK;
 }

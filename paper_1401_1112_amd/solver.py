@@ -13,7 +13,7 @@ class HierarchySolver:
                  linf_test=True, abs_floor=1e-14, a_rad=1.0, c_v=1.0, nsub=None, check_every=0,
                  true_residual=True, time_sweeps=0, inner_tol=1e-4, max_outer=30, max_blocks=0,
                  persistent=False, persistent_per_cu=0, theta=1.0, K_exp=0.0, outer=None, form_coefs=False,
-                 device="cuda:0", stream=None):
+                 graph=False, device="cuda:0", stream=None):
         L.load()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -40,6 +40,7 @@ class HierarchySolver:
         o.theta = float(theta)
         o.K_exp = float(K_exp)
         o.form_coefs = int(bool(form_coefs))
+        o.graph = int(bool(graph))
         for d, v in (outer or {}).items():  # box face direction -> Dirichlet energy held there
             o.outer_mode[int(d)] = 1
             o.outer_value[int(d)] = float(v)
