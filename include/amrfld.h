@@ -159,7 +159,8 @@ amrfld_status amrfld_level_info(const amrfld_ctx* c, int level, int64_t* n_slots
  * limiter, Sect. 2.1), AMRFLD_K_MINERBO (the same with the Minerbo limiter of
  * the collapse runs, Sect. 5.1) or AMRFLD_K_POWER (K = K_const E^K_exp, K_exp from
  * the options, lagged at the start of each solve; E > 0 unless K_exp is an
- * integer).  The values are copied (stream-ordered) before return. */
+ * integer).  The values are copied (stream-ordered) before return.  Arrays that are
+ * not device memory are rejected with AMRFLD_E_INVALID. */
 amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, const double* E,
                                 const double* T, double kappa_R, double kappa_P, double c_light,
                                 int kmode, double K_const);
@@ -206,6 +207,8 @@ typedef struct {
  * blocks return at once).  precision: AMRFLD_FP64 or AMRFLD_MIXED; tol as in
  * amrfld_solve_level.  E_out: DEVICE float64 array receiving the final energies
  * of all patches concatenated in patch order (sum of n^3 values, x fastest).
+ * Patch fields or E_out that are not device memory are rejected with
+ * AMRFLD_E_INVALID before any launch.
  * Stats: one entry per (step, patch), the patch index in the `level` field.
  * The batch layout is kept in the context and reused while the sizes repeat. */
 amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* patches, int n_steps,
@@ -227,7 +230,8 @@ amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* 
 amrfld_status amrfld_advance_unique(amrfld_ctx* c, double dt_coarse, double tol);
 
 /* Copy a level's E (and T when T_out is not NULL) to DEVICE arrays of n_slots
- * float64 in slot order (stream-ordered). */
+ * float64 in slot order (stream-ordered); other memory is rejected with
+ * AMRFLD_E_INVALID. */
 amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double* T_out);
 
 /* Stats of the solves made by the last solve / advance / batch call, in order.

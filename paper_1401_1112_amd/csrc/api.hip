@@ -181,6 +181,7 @@ struct amrfld_ctx {
   double* x_alt = nullptr;
   PcgScalars* sc = nullptr;     // [2 sc_cap]: outer (or plain) solves, then inner solves
   PcgScalars* h_sc = nullptr;   // pinned mirror
+  PcgScalars* h_sc_dev = nullptr;  // the mirror as the device addresses it
   int sc_cap = 0;
   struct BatchState* batch = nullptr;
   struct CompositeState* comp = nullptr;  // unique-time-step system of all levels (built on first use)
@@ -201,6 +202,17 @@ struct amrfld_ctx {
 };
 
 namespace {
+
+// Caller arrays that a kernel reads or writes must be device memory (a host
+// pointer would fault in the kernel): checked before any launch.
+bool device_ptr(const void* p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
 
 amrfld_status fail(amrfld_ctx* c, amrfld_status s, const std::string& m) {
   if (c) c->err = m;
@@ -381,21 +393,32 @@ void ensure_scalars(amrfld_ctx* c, int n_prob) {
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   c->sc = nullptr;
   c->h_sc = nullptr;
+  c->h_sc_dev = nullptr;
   c->sc_cap = 0;
   c->sc = dalloc<PcgScalars>(2 * int64_t(n_prob), "scalars");
-  check(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), 2 * size_t(n_prob) * sizeof(PcgScalars), 0),
+  check(hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), 2 * size_t(n_prob) * sizeof(PcgScalars),
+                      hipHostMallocMapped | hipHostMallocCoherent),
         "pinned scalars");
+  check(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_sc_dev), c->h_sc, 0), "mapped scalars");
   c->sc_cap = n_prob;
+}
+
+// The device view of a slice of the pinned mirror, or nullptr outside it.
+PcgScalars* mapped(amrfld_ctx* c, const PcgScalars* host, int count) {
+  if (!c->h_sc_dev || host < c->h_sc || host + count > c->h_sc + 2 * int64_t(c->sc_cap)) return nullptr;
+  return c->h_sc_dev + (host - c->h_sc);
 }
 
 void read_scalars(amrfld_ctx* c, PcgScalars* host, const PcgScalars* dev, int count) {
   const hipStream_t s = c->stream();
-  check(hipMemcpyAsync(host, dev, count * sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
+  if (PcgScalars* m = mapped(c, host, count)) launch_copy_scalars(s, dev, m, count, true);
+  else check(hipMemcpyAsync(host, dev, count * sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
   check(hipStreamSynchronize(s), "sync");
 }
 
 void write_scalars(amrfld_ctx* c, PcgScalars* dev, const PcgScalars* host, int count) {
-  check(hipMemcpyAsync(dev, host, count * sizeof(PcgScalars), hipMemcpyHostToDevice, c->stream()), "scalars");
+  if (PcgScalars* m = mapped(c, host, count)) launch_copy_scalars(c->stream(), m, dev, count, false);
+  else check(hipMemcpyAsync(dev, host, count * sizeof(PcgScalars), hipMemcpyHostToDevice, c->stream()), "scalars");
 }
 
 bool all_done(const PcgScalars* h, int n) {
@@ -584,7 +607,7 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
     budget -= std::max(1, after - before);
   }
   for (int q = 0; q < np; ++q) (*outer_iters)[q] = c->h_sc[q].iter;
-  if (x_cur != A.x) check(hipMemcpyAsync(A.x, x_cur, A.n * sizeof(double), hipMemcpyDeviceToDevice, s), "copy x");
+  if (x_cur != A.x) launch_copy_f64(s, A.x, x_cur, A.n);
 }
 
 // One backward-Euler step of one level (Sect. 3.3.4).
@@ -636,8 +659,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   }
   if (L.reg) launch_fill(s, L.reg, 6 * L.t.n_slots(), 0.0);
   check(hipEventRecord(c->ev[3], s), "event");
-  check(hipMemcpyAsync(c->h_sc, c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
-  check(hipStreamSynchronize(s), "sync");
+  read_scalars(c, c->h_sc, c->sc, 1);
   check(hipGetLastError(), "kernels");
 
   const PcgScalars& h = *c->h_sc;
@@ -1043,10 +1065,9 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
     LevelState& L = c->L(base + k);
     const double* Ec = k > 0 ? c->L(base + k - 1).E : nullptr;
     launch_cell_K(s, L.dev(), L.E, L.rho, Ec, kparams(L), outer_bc(c), C.K + C.off[k]);
-    const size_t bytes = size_t(L.t.n_slots()) * sizeof(double);
-    check(hipMemcpyAsync(C.x + C.off[k], L.E, bytes, hipMemcpyDeviceToDevice, s), "gather");
-    check(hipMemcpyAsync(C.rho + C.off[k], L.rho, bytes, hipMemcpyDeviceToDevice, s), "gather");
-    if (coupled) check(hipMemcpyAsync(C.T + C.off[k], L.T, bytes, hipMemcpyDeviceToDevice, s), "gather");
+    launch_copy_f64(s, C.x + C.off[k], L.E, L.t.n_slots());
+    launch_copy_f64(s, C.rho + C.off[k], L.rho, L.t.n_slots());
+    if (coupled) launch_copy_f64(s, C.T + C.off[k], L.T, L.t.n_slots());
     const double dx = 1.0 / double(int64_t(1) << (base + k));
     PatchParams& P = C.pp_host[k];
     P.dx = dx;
@@ -1080,8 +1101,7 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   int64_t n_leaf = 0;
   for (int k = 0; k < C.n_levels; ++k) {
     LevelState& L = c->L(base + k);
-    check(hipMemcpyAsync(L.E, C.x + C.off[k], size_t(L.t.n_slots()) * sizeof(double), hipMemcpyDeviceToDevice, s),
-          "scatter");
+    launch_copy_f64(s, L.E, C.x + C.off[k], L.t.n_slots());
     const int tl = tiles_of(L.t.n_slots());
     launch_post_solve(s, L.dev(), single_plan(sweep_blocks(tl, B), tl), L.E, L.rho, cparams(c, L), dt, L.T,
                       c->sc + 1 + k, c->partials);
@@ -1655,15 +1675,17 @@ amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, con
   if ((kmode == AMRFLD_K_CONST || kmode == AMRFLD_K_POWER) && !(K_const >= 0.0 && std::isfinite(K_const)))
     return fail(c, AMRFLD_E_INVALID, "K_const must be finite and >= 0");
   if (T && !(kappa_P >= 0.0 && c_light > 0.0)) return fail(c, AMRFLD_E_INVALID, "kappa_P >= 0 and c_light > 0 needed with T");
+  if (!device_ptr(rho) || !device_ptr(E) || (T && !device_ptr(T)))
+    return fail(c, AMRFLD_E_INVALID, "rho, E and T must be device arrays");
   return guarded(c, [&]() -> amrfld_status {
     LevelState& L = c->L(level);
     const int64_t n = L.t.n_slots();
     const hipStream_t s = c->stream();
-    check(hipMemcpyAsync(L.rho, rho, n * 8, hipMemcpyDeviceToDevice, s), "set rho");
-    check(hipMemcpyAsync(L.E, E, n * 8, hipMemcpyDeviceToDevice, s), "set E");
+    launch_copy_f64(s, L.rho, rho, n);
+    launch_copy_f64(s, L.E, E, n);
     if (T) {
       if (!L.T) L.T = dalloc<double>(n, "fields");
-      check(hipMemcpyAsync(L.T, T, n * 8, hipMemcpyDeviceToDevice, s), "set T");
+      launch_copy_f64(s, L.T, T, n);
     }
     L.has_T = T != nullptr;
     L.kmode = kmode;
@@ -1729,6 +1751,7 @@ amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* 
                                  double tol, int precision, double* E_out) {
   if (!c) return AMRFLD_E_INVALID;
   if (n_prob < 1 || !patches || !E_out) return fail(c, AMRFLD_E_INVALID, "n_prob >= 1, patches and E_out are required");
+  if (!device_ptr(E_out)) return fail(c, AMRFLD_E_INVALID, "E_out must be a device array");
   if (n_steps < 1) return fail(c, AMRFLD_E_INVALID, "n_steps must be >= 1");
   if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
   if (precision != AMRFLD_FP64 && precision != AMRFLD_MIXED) return fail(c, AMRFLD_E_INVALID, "unknown precision");
@@ -1740,6 +1763,7 @@ amrfld_status amrfld_solve_batch(amrfld_ctx* c, int n_prob, const amrfld_patch* 
     if (p.n < 2 || p.n > 1024 || (p.n & 1)) return fail(c, AMRFLD_E_INVALID, at + "n must be even, 2..1024");
     if (!(p.dx > 0.0) || !(p.dt > 0.0)) return fail(c, AMRFLD_E_INVALID, at + "dx and dt must be positive");
     if (!p.rho || !p.E) return fail(c, AMRFLD_E_INVALID, at + "rho and E are required");
+    if (!device_ptr(p.rho) || !device_ptr(p.E)) return fail(c, AMRFLD_E_INVALID, at + "rho and E must be device arrays");
     if (p.kmode != AMRFLD_K_CONST && p.kmode != AMRFLD_K_LP && p.kmode != AMRFLD_K_MINERBO)
       return fail(c, AMRFLD_E_INVALID, at + "unknown kmode");
     if (p.kmode != AMRFLD_K_CONST && !(p.kappa_R > 0.0 && p.c_light > 0.0))
@@ -1766,10 +1790,12 @@ amrfld_status amrfld_get_E(const amrfld_ctx* c, int level, double* E_out, double
   if (!E_out && !T_out) return fail(m, AMRFLD_E_INVALID, "no output");
   const LevelState& L = c->L(level);
   if (T_out && !L.has_T) return fail(m, AMRFLD_E_STATE, "level has no temperature");
+  if ((E_out && !device_ptr(E_out)) || (T_out && !device_ptr(T_out)))
+    return fail(m, AMRFLD_E_INVALID, "E_out and T_out must be device arrays");
   return guarded(m, [&]() -> amrfld_status {
     const int64_t n = L.t.n_slots();
-    if (E_out) check(hipMemcpyAsync(E_out, L.E, n * 8, hipMemcpyDeviceToDevice, c->stream()), "get E");
-    if (T_out) check(hipMemcpyAsync(T_out, L.T, n * 8, hipMemcpyDeviceToDevice, c->stream()), "get T");
+    if (E_out) launch_copy_f64(c->stream(), E_out, L.E, n);
+    if (T_out) launch_copy_f64(c->stream(), T_out, L.T, n);
     return AMRFLD_OK;
   });
 }

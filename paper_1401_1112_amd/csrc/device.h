@@ -178,6 +178,9 @@ void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, c
                           int n_slots_c);
 void launch_restrict(hipStream_t s, const DevLevel& F, const double* E_f, double* E_c);
 void launch_fill(hipStream_t s, double* p, int64_t n, double v);
+// dst[i] = src[i] for n device doubles (a plain streaming copy; the runtime's
+// generic copy runs far below HBM rate at these sizes).
+void launch_copy_f64(hipStream_t s, double* dst, const double* src, int64_t n);
 void launch_fill_f32(hipStream_t s, float* p, int64_t n, float v);
 // FP32 copies of an FP64 operator: Cp (stored form) or K (formed), and diag.
 void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* K, const double* diag, float* Cp32,
@@ -227,6 +230,11 @@ hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPl
                                  const FaceCoefs<T>& A, const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc,
                                  double* part, unsigned* bar, int per_cu_cap);
 void launch_zero_u32(hipStream_t s, unsigned* p, int n);
+// Copies count scalar records between device memory and the device-mapped view of
+// pinned host memory (to_host: then makes the stores visible to the host), so that
+// reading or setting the scalars costs one small kernel instead of a copy engine
+// transfer.
+void launch_copy_scalars(hipStream_t s, const PcgScalars* src, PcgScalars* dst, int count, bool to_host);
 void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, double abs_floor, int max_iter,
                          int linf_test);
 void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,

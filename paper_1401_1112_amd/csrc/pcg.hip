@@ -828,6 +828,13 @@ __global__ __launch_bounds__(kBlock) void k_init_scalars(PcgScalars* sc, int n, 
   sc[i] = z;
 }
 
+__global__ __launch_bounds__(kBlock) void k_copy_scalars(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                                                         int n_words, int to_host) {
+  const int i = int(blockIdx.x * kBlock + threadIdx.x);
+  if (i < n_words) dst[i] = src[i];
+  if (to_host) __threadfence_system();
+}
+
 __global__ __launch_bounds__(kBlock) void k_zero_u32(unsigned* p, int n) {
   const int i = int(blockIdx.x * kBlock + threadIdx.x);
   if (i < n) p[i] = 0u;
@@ -927,6 +934,15 @@ void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, doubl
                          int linf_test) {
   hipLaunchKernelGGL(k_init_scalars, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, n, tol, abs_floor,
                      max_iter, linf_test);
+}
+
+void launch_copy_scalars(hipStream_t s, const PcgScalars* src, PcgScalars* dst, int count, bool to_host) {
+  static_assert(sizeof(PcgScalars) % sizeof(uint64_t) == 0, "scalar records are whole words");
+  const int n_words = count * int(sizeof(PcgScalars) / sizeof(uint64_t));
+  if (n_words <= 0) return;
+  hipLaunchKernelGGL(k_copy_scalars, dim3((n_words + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     reinterpret_cast<const uint64_t*>(src), reinterpret_cast<uint64_t*>(dst), n_words,
+                     to_host ? 1 : 0);
 }
 
 void launch_zero_u32(hipStream_t s, unsigned* p, int n) {

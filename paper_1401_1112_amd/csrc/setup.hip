@@ -305,6 +305,19 @@ __global__ __launch_bounds__(kBlock) void k_restrict(DevLevel F, const double* _
   Ec[F.parent[o]] = s * 0.125;
 }
 
+// Two doubles per thread, consecutive threads on consecutive pairs.
+__global__ __launch_bounds__(kBlock) void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src,
+                                                     int64_t n) {
+  const int64_t i = 2 * (int64_t(blockIdx.x) * kBlock + threadIdx.x);
+  if (i + 1 < n) {
+    const double a = src[i], b = src[i + 1];
+    dst[i] = a;
+    dst[i + 1] = b;
+  } else if (i < n) {
+    dst[i] = src[i];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(T* p, int64_t n, T v) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -396,6 +409,11 @@ void launch_flux_register(hipStream_t s, const DevLevel& F, const double* K_f, c
 
 void launch_restrict(hipStream_t s, const DevLevel& F, const double* E_f, double* E_c) {
   hipLaunchKernelGGL(k_restrict, dim3(grid_for(F.n_oct)), dim3(kBlock), 0, s, F, E_f, E_c);
+}
+
+void launch_copy_f64(hipStream_t s, double* dst, const double* src, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy_f64, dim3(int((n + 2 * kBlock - 1) / (2 * kBlock))), dim3(kBlock), 0, s, dst, src, n);
 }
 
 void launch_fill(hipStream_t s, double* p, int64_t n, double v) {
