@@ -46,6 +46,23 @@ CASES = {
 }
 
 
+def _theta_case():
+    p = config_tiny(4, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-12)
+    p.theta = 0.5
+    return p
+
+
+@pytest.mark.parametrize("form_coefs", [False, True])
+def test_graph_theta_and_formed_coefficients(form_coefs):
+    # the Crank-Nicolson step (Dirichlet interfaces) captured and replayed, with stored
+    # or formed face coefficients
+    p = _theta_case()
+    dts = [p.dt_coarse] * 3
+    graph = _run(p, 0, dts, persistent=True, graph=True, form_coefs=form_coefs)
+    assert all(m == {2} for _, _, m in graph)
+    _same(graph, _run(p, 0, dts))
+
+
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_graph_replays_equal_eager(case, mode):

@@ -78,3 +78,29 @@ def test_theta_rejections():
     s.close()
     with pytest.raises(AmrfldError):
         HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, theta=0.3)
+
+
+def test_crank_nicolson_persistent_and_mixed():
+    # the theta-weighted step through the other solve forms: one persistent launch per
+    # solve gives the host-polled result bitwise; FP32 inner solves with FP64 refinement
+    # meet the threshold on the FP64 true residual and agree with FP64
+    from paper_1401_1112_amd import MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    p = config_tiny(1, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-10)
+    p.theta = 0.5
+    out = {}
+    for name, kw in (("polled", {}), ("persistent", {"persistent": True}), ("mixed", {"precision": MIXED})):
+        s = solver_from_problem(p, **kw)
+        for _ in range(2):
+            s.advance(p.dt_coarse, 0, p.tol)
+            for st in s.stats():
+                thr = max(p.tol * st["rnorm0"], p.abs_floor * st["bnorm"])
+                assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= 1.05 * thr, (name, st)
+        out[name] = ({l: to_numpy(s.E(l)) for l in p.hierarchy.levels}, [x["iters"] for x in s.stats()])
+        s.close()
+    a, ia = out["polled"]
+    b, ib = out["persistent"]
+    assert ia == ib and all(np.array_equal(a[l], b[l]) for l in a)
+    m, _ = out["mixed"]
+    for l in a:
+        assert np.linalg.norm(m[l] - a[l]) <= 1e-8 * np.linalg.norm(a[l])
