@@ -187,6 +187,12 @@ def _mixed_form(p, s64, init, ms64, args):
         s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
         return s.stats()
 
+    inner = {"inner_tol": 1e-2, "tuned": False}
+    if not args.no_tune:
+        # the inner tolerance: the split between FP32 inner iterations and FP64 refinement
+        from paper_1401_1112_amd.autotune import tune_refinement
+        best, times, cached = tune_refinement(s, step, [s.info(l)[0] for l in s.levels], "levels")
+        inner = {"inner_tol": best["inner_tol"], "tuned": True, "source": cached, "candidate_ms_per_step": times}
     step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -206,7 +212,7 @@ def _mixed_form(p, s64, init, ms64, args):
            "outer_sweeps_per_step": sum(st["outer_iters"] for st in last),
            "residual": _residual_gate([st for x in sts for st in x], p.tol),
            "err_vs_fp64_gpu": {"max_rel": worst_max, "l2_rel": worst_l2},
-           "inner_tol": 1e-4}
+           "inner_tol": inner}
     s.close()
     return out
 
@@ -441,6 +447,19 @@ def _batched_form(args):
         forms.append(("fp64_tuned", {"persistent": bool(best["persistent"]), "graph": True,
                                      "persistent_per_cu": best["persistent_per_cu"],
                                      "form_coefs": bool(best.get("form_coefs", 0))}, 0))
+        # the mixed form's inner tolerance, host-polled sweeps
+        from paper_1401_1112_amd.autotune import tune_refinement
+        print("bench: tuning the batch inner tolerance", file=sys.stderr, flush=True)
+        bs = BatchSolver(robin_alpha=alpha, form_coefs=bool(best.get("form_coefs", 0)))
+        h = bs.upload(patches)
+        best_in, times_in, cached_in = tune_refinement(bs, lambda: bs.run(h, 1, tol, MIXED),
+                                                       [p.n for p in patches], "batch")
+        bs.close()
+        del h
+        torch.cuda.empty_cache()
+        out["tuned_inner_tol"] = {"best": best_in, "source": cached_in, "candidate_ms_per_step": times_in}
+        forms.append(("mixed_tuned", {"form_coefs": bool(best.get("form_coefs", 0)),
+                                      "inner_tol": best_in["inner_tol"]}, MIXED))
     results = {}
     for name, kw, prec in forms:
         print(f"bench: batched form {name}", file=sys.stderr, flush=True)
@@ -492,6 +511,10 @@ def _batched_form(args):
     out["max_rel_l2_batch_vs_single"] = max(_rel_err(x, y)[1] for x, y in zip(a, single_res))
     out["mixed_err_vs_fp64_gpu"] = {"max_rel": max(_rel_err(x, y)[0] for x, y in zip(m, a)),
                                     "l2_rel": max(_rel_err(x, y)[1] for x, y in zip(m, a))}
+    if "mixed_tuned" in results:
+        mt = results["mixed_tuned"][0]
+        out["mixed_tuned_err_vs_fp64_gpu"] = {"max_rel": max(_rel_err(x, y)[0] for x, y in zip(mt, a)),
+                                              "l2_rel": max(_rel_err(x, y)[1] for x, y in zip(mt, a))}
     return out
 
 
@@ -544,10 +567,18 @@ def _collapse_form(args):
         print(f"bench: collapse form {name}", file=sys.stderr, flush=True)
         if first is not None:
             s, first = first, None
-        elif isinstance(pers, dict):  # the tuned shape
+        elif isinstance(pers, dict):  # the tuned shape and inner tolerance
             s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, nsub=p.nsub)
             s.set_launch(pers["max_blocks"], bool(pers["persistent"]), pers["persistent_per_cu"],
                          bool(pers.get("form_coefs", 0)))
+            from paper_1401_1112_amd.autotune import tune_refinement
+
+            def tune_step():
+                reset(s)
+                s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+
+            best_in, times_in, cached_in = tune_refinement(s, tune_step, list(slots.values()), "collapse")
+            out["tuned_inner_tol"] = {"best": best_in, "source": cached_in, "candidate_ms_per_step": times_in}
         else:
             s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, persistent=pers,
                                 nsub=p.nsub, max_blocks=args.max_blocks)

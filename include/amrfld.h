@@ -75,7 +75,7 @@ typedef struct {
   int check_every;       /* PCG iterations between host convergence checks; 0 = auto */
   int true_residual;     /* 1: compute ||b - A x|| after each solve for the stats */
   int time_sweeps;       /* N > 0: time the two sweeps of every N-th PCG iteration with HIP events */
-  double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner solve; default 1e-4 */
+  double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner solve; default 1e-2 */
   int max_outer;         /* AMRFLD_MIXED: refinement sweeps cap; default 30 */
   int max_blocks;        /* blocks per PCG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
   int persistent;        /* 1 = all PCG iterations of a solve (batch form: of a step) in one cooperative
@@ -249,6 +249,14 @@ amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_
  * last bits. */
 amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, int persistent_per_cu,
                                 int form_coefs);
+
+/* Inner tolerance and refinement-sweep cap of the AMRFLD_MIXED form for the
+ * following calls (as amrfld_opts.inner_tol and max_outer); not a step of the
+ * method: every result still meets the FP64 stopping rule, only the split of the
+ * work between FP32 inner iterations and FP64 refinement sweeps changes, and the
+ * best split depends on the workload (the autotuner times it).  inner_tol outside
+ * (0, 1) or max_outer < 1: AMRFLD_E_INVALID, nothing changes. */
+amrfld_status amrfld_set_refinement(amrfld_ctx* c, double inner_tol, int max_outer);
 
 /* Message of the last failure on this context ("" if none). */
 const char* amrfld_last_error(const amrfld_ctx* c);

@@ -84,6 +84,7 @@ SIGNATURES = [
     ("amrfld_get_E", _I, [_P, _I, _P, _P]),
     ("amrfld_last_stats", _I, [_P, ctypes.POINTER(amrfld_stats), _I, ctypes.POINTER(_I)]),
     ("amrfld_set_launch", _I, [_P, _I, _I, _I, _I]),
+    ("amrfld_set_refinement", _I, [_P, ctypes.c_double, _I]),
     ("amrfld_last_error", ctypes.c_char_p, [_P]),
     ("amrfld_create_error", ctypes.c_char_p, []),
 ]
@@ -197,6 +198,10 @@ def amrfld_last_stats(ctx, max_n=None):
     arr = (amrfld_stats * max(count, 1))()
     load().amrfld_last_stats(ctx, arr, count, ctypes.byref(n))
     return [arr[k].as_dict() for k in range(count)]
+
+
+def amrfld_set_refinement(ctx, inner_tol, max_outer):
+    return load().amrfld_set_refinement(ctx, float(inner_tol), int(max_outer))
 
 
 def amrfld_set_launch(ctx, max_blocks, persistent, persistent_per_cu, form_coefs):

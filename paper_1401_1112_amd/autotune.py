@@ -38,6 +38,7 @@ LEVEL_SHAPES = (
     {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 0, "form_coefs": 0},
     {"max_blocks": 1024, "persistent": 1, "persistent_per_cu": 1, "form_coefs": 0},
 )
+INNER_TOLS = (1e-2, 1e-3, 1e-4, 1e-5)
 BATCH_SHAPES = (
     {"persistent": 0, "persistent_per_cu": 0, "form_coefs": 0},
     {"persistent": 0, "persistent_per_cu": 0, "form_coefs": 1},
@@ -173,3 +174,11 @@ def tune_level_shapes(solver, run, sizes, precision, repeats=2, use_cache=True):
                 lambda c: solver.set_launch(c["max_blocks"], c["persistent"], c["persistent_per_cu"],
                                             c.get("form_coefs", 0)), run,
                 repeats, solver.stream, use_cache)
+
+
+def tune_refinement(solver, run, sizes, kind="levels", repeats=2, use_cache=True):
+    """Inner tolerance of the mixed-precision form (FP32 inner solves inside FP64
+    refinement): every candidate meets the same FP64 stopping rule, and the split of the
+    work that is fastest depends on the workload."""
+    return tune(workload_key("refinement-" + kind, sizes, 1), [{"inner_tol": t} for t in INNER_TOLS],
+                lambda c: solver.set_refinement(c["inner_tol"]), run, repeats, solver.stream, use_cache)

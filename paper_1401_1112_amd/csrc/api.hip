@@ -1506,7 +1506,7 @@ void amrfld_default_opts(amrfld_opts* o) {
   o->c_v = 1.0;
   o->check_every = 0;
   o->true_residual = 1;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 1e-2;
   o->max_outer = 30;
   o->max_blocks = 0;
   o->stream = nullptr;
@@ -1820,6 +1820,19 @@ amrfld_status amrfld_set_launch(amrfld_ctx* c, int max_blocks, int persistent, i
   c->o.persistent = persistent ? 1 : 0;
   c->o.persistent_per_cu = persistent_per_cu;
   c->o.form_coefs = form_coefs ? 1 : 0;
+  ++c->param_epoch;
+  c->err.clear();
+  return AMRFLD_OK;
+}
+
+amrfld_status amrfld_set_refinement(amrfld_ctx* c, double inner_tol, int max_outer) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (!(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1) {
+    c->err = "set_refinement: inner_tol in (0, 1) and max_outer >= 1 are required";
+    return AMRFLD_E_INVALID;
+  }
+  c->o.inner_tol = inner_tol;
+  c->o.max_outer = max_outer;
   ++c->param_epoch;
   c->err.clear();
   return AMRFLD_OK;

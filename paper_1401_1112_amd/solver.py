@@ -11,7 +11,7 @@ from . import _lib as L
 class HierarchySolver:
     def __init__(self, base_level, octs, *, robin_alpha=0.5, max_iter=10000, precision=L.FP64,
                  linf_test=True, abs_floor=1e-14, a_rad=1.0, c_v=1.0, nsub=None, check_every=0,
-                 true_residual=True, time_sweeps=0, inner_tol=1e-4, max_outer=30, max_blocks=0,
+                 true_residual=True, time_sweeps=0, inner_tol=1e-2, max_outer=30, max_blocks=0,
                  persistent=False, persistent_per_cu=0, theta=1.0, K_exp=0.0, outer=None, form_coefs=False,
                  graph=False, device="cuda:0", stream=None):
         L.load()
@@ -131,6 +131,9 @@ class HierarchySolver:
         self._check(L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu,
                                         int(bool(form_coefs))))
 
+    def set_refinement(self, inner_tol, max_outer=30):
+        self._check(L.amrfld_set_refinement(self.ctx, inner_tol, max_outer))
+
 
 def sample_problem_fields(solver: HierarchySolver, problem):
     """Sample a problem's fields in the library's cell order and upload them."""
@@ -162,7 +165,7 @@ class BatchSolver:
     """Independent patches advanced together (amrfld_solve_batch)."""
 
     def __init__(self, *, robin_alpha=0.5, max_iter=10000, linf_test=True, abs_floor=1e-14,
-                 inner_tol=1e-4, max_outer=30, max_blocks=0, time_sweeps=0, true_residual=True,
+                 inner_tol=1e-2, max_outer=30, max_blocks=0, time_sweeps=0, true_residual=True,
                  check_every=0, persistent=False, graph=False, persistent_per_cu=0, form_coefs=False,
                  device="cuda:0", stream=None):
         L.load()
@@ -249,6 +252,11 @@ class BatchSolver:
 
     def last_error(self):
         return L.amrfld_last_error(self.ctx)
+
+    def set_refinement(self, inner_tol, max_outer=30):
+        st = L.amrfld_set_refinement(self.ctx, inner_tol, max_outer)
+        if st != L.OK:
+            raise L.AmrfldError(st, L.amrfld_last_error(self.ctx))
 
     def set_launch(self, max_blocks=0, persistent=False, persistent_per_cu=0, form_coefs=False):
         st = L.amrfld_set_launch(self.ctx, max_blocks, int(bool(persistent)), persistent_per_cu, int(bool(form_coefs)))

@@ -74,7 +74,9 @@ def test_shipped_table_keys_match_the_benchmark_workloads():
 def test_shipped_entries_are_candidates():
     # every shipped choice is one of the shapes its tuner times
     table = json.load(open(A.SHIPPED))
-    cands = {"levels": A.LEVEL_CANDIDATES, "batch": A.BATCH_SHAPES, "level-shapes": A.LEVEL_SHAPES}
+    inner = tuple({"inner_tol": t} for t in A.INNER_TOLS)
+    cands = {"levels": A.LEVEL_CANDIDATES, "batch": A.BATCH_SHAPES, "level-shapes": A.LEVEL_SHAPES,
+             "refinement-levels": inner, "refinement-batch": inner, "refinement-collapse": inner}
     for key, e in table["entries"].items():
         assert e["best"] in [dict(c) for c in cands[key.split("|")[0]]], key
         assert json.dumps(e["best"], sort_keys=True) in e["ms"], key

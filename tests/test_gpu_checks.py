@@ -44,3 +44,28 @@ def test_host_arrays_rejected_for_patches():
     assert bs.run(h, 1, 1e-10) == 0  # still usable
     assert torch.isfinite(h["out"]).all()
     bs.close()
+
+
+@pytest.mark.parametrize("inner_tol", [1e-2, 1e-5])
+def test_refinement_split_keeps_the_fp64_threshold(inner_tol):
+    # any inner tolerance only moves work between FP32 inner iterations and FP64
+    # refinement sweeps: every solve still meets the FP64 stopping rule
+    from paper_1401_1112_amd import E_INVALID, MIXED, _lib as L
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    from synth.configs import config_tiny
+    p = config_tiny(2, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-10)
+    ref = solver_from_problem(p)
+    ref.advance(p.dt_coarse, 0, p.tol)
+    s = solver_from_problem(p, precision=MIXED)
+    assert L.amrfld_set_refinement(s.ctx, 0.0, 30) == E_INVALID
+    assert L.amrfld_set_refinement(s.ctx, 1e-4, 0) == E_INVALID
+    s.set_refinement(inner_tol)
+    s.advance(p.dt_coarse, 0, p.tol)
+    for st in s.stats():
+        thr = max(p.tol * st["rnorm0"], p.abs_floor * st["bnorm"])
+        assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= thr * (1 + 1e-12), st
+    for l in p.hierarchy.levels:
+        a, b = to_numpy(s.E(l)), to_numpy(ref.E(l))
+        assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
+    s.close()
+    ref.close()
