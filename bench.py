@@ -200,6 +200,11 @@ def _mixed_form(p, s64, init, ms64, args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     cell_it = sum(st["n_leaf"] * st["iters"] for x in sts for st in x)
+    # the FP64 reference: the same step from the same state (s64 may hold another form's result)
+    for lvl in s64.levels:
+        rho, E = init[lvl]
+        s64.set_fields(lvl, rho, E, kmode=1)
+    s64.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
     worst_max, worst_l2 = 0.0, 0.0
     for lvl in s.levels:
         a, b = to_numpy(s.E(lvl)), to_numpy(s64.E(lvl))
