@@ -23,7 +23,9 @@
  *   - Every call returns an amrfld_status; nothing aborts or throws across the
  *     ABI.  amrfld_last_error() gives a message for the last failure.
  *   - Arguments are validated before any device work; on AMRFLD_E_INVALID no
- *     state has changed.
+ *     state has changed.  A level, batch layout or composite system whose
+ *     allocation fails (AMRFLD_E_NOMEM) is not kept in part: the call can be
+ *     made again.
  *   - Device pointers are HIP device addresses on the current device; host
  *     pointers are ordinary CPU memory.  Caller buffers are borrowed for the
  *     duration of the call only.  The library owns its tables, fields and
@@ -261,7 +263,8 @@ amrfld_status amrfld_set_refinement(amrfld_ctx* c, double inner_tol, int max_out
 /* Message of the last failure on this context ("" if none). */
 const char* amrfld_last_error(const amrfld_ctx* c);
 
-/* Message of the last failure of amrfld_create (no context exists then). */
+/* Message of the calling thread's last failure of amrfld_create (no context exists
+   then); valid until that thread's next amrfld_create. */
 const char* amrfld_create_error(void);
 
 #ifdef __cplusplus

@@ -56,7 +56,7 @@ void dfree(void* p) {
 struct LevelState {
   LevelTables t;
   int32_t *nbr = nullptr, *cnb = nullptr, *parent = nullptr, *child = nullptr;
-  bool child_dirty = true;
+  bool tables_uploaded = false, child_dirty = true;
   double *rho = nullptr, *E = nullptr, *T = nullptr, *K = nullptr;
   double *Cp = nullptr, *diag = nullptr, *b = nullptr, *reg = nullptr;
   uint8_t* mask = nullptr;  // per slot: faces that couple two leaves of the level
@@ -85,10 +85,11 @@ struct LevelState {
     nbr = cnb = parent = child = nullptr;
     rho = E = T = K = Cp = diag = b = reg = nullptr;
     mask = nullptr;
+    tables_uploaded = false;
   }
 };
 
-std::string g_create_error;
+thread_local std::string g_create_error;  // the calling thread's last amrfld_create failure
 
 }  // namespace
 
@@ -252,6 +253,7 @@ void ensure_workspace(amrfld_ctx* c, int64_t n) {
   if (g > c->partial_n) {
     dfree(c->partials);
     c->partials = nullptr;
+    c->partial_n = 0;
     c->partials = dalloc<double>(g, "partials");
     c->partial_n = g;
   }
@@ -277,17 +279,34 @@ void ensure_workspace32(amrfld_ctx* c, int64_t n) {
   c->ws32_n = n;
 }
 
+// The level's device tables: allocated all together (a failed allocation leaves
+// none), copied until one upload has succeeded.
 void upload_tables(amrfld_ctx* c, LevelState& L) {
   const hipStream_t s = c->stream();
+  const int64_t n_oct = L.t.n_oct;
   if (!L.nbr) {
-    const int64_t n_oct = L.t.n_oct;
-    L.nbr = dalloc<int32_t>(6 * n_oct, "tables");
-    L.cnb = dalloc<int32_t>(6 * n_oct, "tables");
-    L.parent = dalloc<int32_t>(n_oct, "tables");
-    L.child = dalloc<int32_t>(8 * n_oct, "tables");
+    int32_t *nbr = nullptr, *cnb = nullptr, *parent = nullptr, *child = nullptr;
+    try {
+      nbr = dalloc<int32_t>(6 * n_oct, "tables");
+      cnb = dalloc<int32_t>(6 * n_oct, "tables");
+      parent = dalloc<int32_t>(n_oct, "tables");
+      child = dalloc<int32_t>(8 * n_oct, "tables");
+    } catch (...) {
+      for (void* p : {(void*)nbr, (void*)cnb, (void*)parent, (void*)child}) dfree(p);
+      throw;
+    }
+    L.nbr = nbr;
+    L.cnb = cnb;
+    L.parent = parent;
+    L.child = child;
+    L.tables_uploaded = false;
+    L.child_dirty = true;
+  }
+  if (!L.tables_uploaded) {
     check(hipMemcpyAsync(L.nbr, L.t.nbr.data(), 6 * n_oct * 4, hipMemcpyHostToDevice, s), "upload");
     check(hipMemcpyAsync(L.cnb, L.t.cnb.data(), 6 * n_oct * 4, hipMemcpyHostToDevice, s), "upload");
     check(hipMemcpyAsync(L.parent, L.t.parent.data(), n_oct * 4, hipMemcpyHostToDevice, s), "upload");
+    L.tables_uploaded = true;
   }
   if (L.child_dirty) {
     check(hipMemcpyAsync(L.child, L.t.child.data(), 8 * L.t.n_oct * 4, hipMemcpyHostToDevice, s),
@@ -945,10 +964,25 @@ void upload(amrfld_ctx* c, T** dst, const std::vector<T>& v, const char* what) {
 }
 
 // The composite slot space of the context's levels (rebuilt after a level changes).
+void build_composite_into(amrfld_ctx* c, CompositeState* C);
+
+// The composite slot space, built once for the current levels; a failed build
+// leaves none behind.
 void build_composite(amrfld_ctx* c) {
   if (c->comp) return;
   CompositeState* C = new CompositeState();
+  try {
+    build_composite_into(c, C);
+  } catch (...) {
+    (void)hipStreamSynchronize(c->stream());  // copies from host vectors that are gone
+    C->release();
+    delete C;
+    throw;
+  }
   c->comp = C;
+}
+
+void build_composite_into(amrfld_ctx* c, CompositeState* C) {
   const int base = c->o.base_level;
   C->n_levels = c->finest - base + 1;
   C->off.assign(C->n_levels + 1, 0);
@@ -1166,15 +1200,31 @@ amrfld_status advance_unique(amrfld_ctx* c, double dt_coarse, double tol) {
 // Morton-ordered octs of each patch, tile-aligned slot ranges (padding slots are
 // identity rows), neighbour tables within each patch, and the block plan: each
 // patch gets enough blocks for at most `tpb` tiles per block.
+void build_batch_into(amrfld_ctx* c, BatchState* B, const std::vector<int>& sizes);
+
+// The batch layout for these patch sizes, kept while they repeat; a failed build
+// leaves no layout behind.
 void build_batch(amrfld_ctx* c, const std::vector<int>& sizes) {
   BatchState* B = c->batch;
   if (B && B->sizes == sizes) return;
   if (B) {
     B->release();
+    B->sizes.clear();
   } else {
     B = c->batch = new BatchState();
   }
+  try {
+    build_batch_into(c, B, sizes);
+  } catch (...) {
+    (void)hipStreamSynchronize(c->stream());  // copies from host vectors that are gone
+    B->release();
+    B->sizes.clear();
+    throw;
+  }
   B->sizes = sizes;
+}
+
+void build_batch_into(amrfld_ctx* c, BatchState* B, const std::vector<int>& sizes) {
   B->n_prob = int(sizes.size());
   std::vector<int64_t> oct0(B->n_prob + 1, 0), tile0(B->n_prob + 1, 0);
   B->out_off.assign(B->n_prob + 1, 0);
@@ -1417,7 +1467,12 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
   }
   ensure_scalars(c, np);
   const SweepPlan P = B.plan();
-  const int saved_precision = c->o.precision;
+  // the batch's precision for this call only, restored on every way out
+  struct PrecisionScope {
+    amrfld_opts& o;
+    int saved;
+    ~PrecisionScope() { o.precision = saved; }
+  } scope{c->o, c->o.precision};
   c->o.precision = precision;
   amrfld_status worst = AMRFLD_OK;
   std::string worst_msg;
@@ -1483,7 +1538,6 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     }
     if (worst == AMRFLD_E_NONFINITE) break;
   }
-  c->o.precision = saved_precision;
   if (worst != AMRFLD_OK) return fail(c, worst, worst_msg);
   return AMRFLD_OK;
 }
@@ -1613,31 +1667,38 @@ amrfld_status amrfld_build_level(amrfld_ctx* c, int level, int64_t n_oct, const 
     if (coarser) coarse_copy = *coarser;
     const std::string why = build_level_tables(level, base, n_oct, oct_ijk, coarser ? &coarse_copy : nullptr, &t);
     if (!why.empty()) return fail(c, AMRFLD_E_INVALID, why);
+    // the level's device arrays and tables first: a failure leaves the context as it was
+    LevelState fresh;
+    fresh.t = std::move(t);
+    const int64_t n = fresh.t.n_slots();
+    try {
+      fresh.rho = dalloc<double>(n, "fields");
+      fresh.E = dalloc<double>(n, "fields");
+      fresh.K = dalloc<double>(n, "fields");
+      fresh.Cp = dalloc<double>(3 * n, "fields");
+      fresh.mask = dalloc<uint8_t>(n, "fields");
+      fresh.diag = dalloc<double>(n, "fields");
+      fresh.b = dalloc<double>(n, "fields");
+      upload_tables(c, fresh);
+    } catch (...) {
+      (void)hipStreamSynchronize(c->stream());
+      fresh.release();
+      throw;
+    }
     if (coarser) {
       *coarser = std::move(coarse_copy);
       c->L(level - 1).child_dirty = true;
     }
-    LevelState& L = c->L(level);
-    L.release();
-    L.t = std::move(t);
-    L.child_dirty = true;
     if (c->comp) {  // the composite slot space no longer matches the levels
       c->comp->release();
       delete c->comp;
       c->comp = nullptr;
     }
-    const int64_t n = L.t.n_slots();
-    L.rho = dalloc<double>(n, "fields");
-    L.E = dalloc<double>(n, "fields");
-    L.K = dalloc<double>(n, "fields");
-    L.Cp = dalloc<double>(3 * n, "fields");
-    L.mask = dalloc<uint8_t>(n, "fields");
-    L.diag = dalloc<double>(n, "fields");
-    L.b = dalloc<double>(n, "fields");
-    L.has_fields = false;
+    LevelState& L = c->L(level);
+    L.release();
+    L = std::move(fresh);
     c->finest = level;
-    upload_tables(c, L);
-    if (coarser) upload_tables(c, c->L(level - 1));
+    if (coarser) upload_tables(c, c->L(level - 1));  // its child table (allocated with that level)
     return AMRFLD_OK;
   });
 }

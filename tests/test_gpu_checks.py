@@ -69,3 +69,34 @@ def test_refinement_split_keeps_the_fp64_threshold(inner_tol):
         assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(b)
     s.close()
     ref.close()
+
+
+def test_oversized_batch_rejected_on_every_call():
+    # two patches of 1024^3 cells exceed the 32-bit slot space: the layout build fails
+    # before any launch, leaves no layout behind, and the same call fails the same way
+    # again; a batch that fits then runs on the same context
+    import torch
+    from paper_1401_1112_amd import E_INVALID, _lib as L
+    from paper_1401_1112_amd.solver import BatchSolver
+    n = 1024
+    rho = torch.ones(n ** 3, dtype=torch.float64, device="cuda")
+    E = torch.ones(n ** 3, dtype=torch.float64, device="cuda")
+    out = torch.empty(2 * n ** 3, dtype=torch.float64, device="cuda")
+    structs = []
+    for _ in range(2):
+        st = L.amrfld_patch()
+        st.n, st.dx, st.dt = n, 1.0 / n, 1e-3
+        st.rho, st.E = rho.data_ptr(), E.data_ptr()
+        st.kmode, st.K_const, st.kappa_R, st.c_light = L.K_CONST, 1.0, 1.0, 1.0
+        structs.append(st)
+    patches, alpha = patch_batch(5, 3, n_min=4, n_max=8)
+    bs = BatchSolver(robin_alpha=alpha)
+    for _ in range(2):
+        assert L.amrfld_solve_batch(bs.ctx, structs, 1, 1e-10, 0, out) == E_INVALID
+        assert "32-bit" in str(L.amrfld_last_error(bs.ctx))
+    del rho, E, out
+    torch.cuda.empty_cache()
+    h = bs.upload(patches)
+    assert bs.run(h, 2, 1e-10) == 0
+    assert torch.isfinite(h["out"]).all()
+    bs.close()
