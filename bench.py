@@ -33,8 +33,6 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per slot (FP64): pass A reads r, p_old, diag, 3 face
 # coefficients and the per-oct neighbour table (24 B per oct = 3 B per slot),
 # writes p_new and q; pass B reads x, r, p, q, diag and writes x, r.
-# pass A's algorithmic bytes per slot as the method states them: read r, p, d and the
-# three face coefficients, the neighbour table (24 B per oct), write p and q
 PASS_A_BYTES = 3 * 8 + 3 * 8 + 3 + 2 * 8
 # what it moves with the coefficients formed from K: K (8 B) and the face mask (1 B)
 # instead of the three coefficients
@@ -767,6 +765,7 @@ def main(argv=None):
             "cell_iterations_per_step": sum(st["n_leaf"] * st["iters"] for st in per_step),
         },
         "pcg_only_cell_it_per_s": cell_it / (pcg_ms * 1e-3) if pcg_ms > 0 else None,
+        "residual": _residual_gate([st for sts in all_stats for st in sts], p.tol),
         "device_solve_ms_per_step": solve_ms / args.steps,
         "generation_s": round(t_gen, 1),
         "launch": launch,
