@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <type_traits>
 #include <cmath>
 #include <cstring>
@@ -15,6 +16,7 @@
 
 #include "../../include/amrfld.h"
 #include "device.h"
+#include "signal.h"
 #include "tables.h"
 
 using namespace amrfld;
@@ -184,6 +186,9 @@ struct amrfld_ctx {
   PcgScalars* h_sc = nullptr;   // pinned mirror
   PcgScalars* h_sc_dev = nullptr;  // the mirror as the device addresses it
   int sc_cap = 0;
+  uint64_t* h_seq = nullptr;      // pinned completion word of scalar reads
+  uint64_t* h_seq_dev = nullptr;  // the word as the device addresses it
+  uint64_t seq = 0;               // value of the last scalar read
   struct BatchState* batch = nullptr;
   struct CompositeState* comp = nullptr;  // unique-time-step system of all levels (built on first use)
   unsigned* bar = nullptr;  // grid barrier counter, generation, done counter, abort flag
@@ -420,6 +425,18 @@ void ensure_scalars(amrfld_ctx* c, int n_prob) {
         "pinned scalars");
   check(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->h_sc_dev), c->h_sc, 0), "mapped scalars");
   c->sc_cap = n_prob;
+  if (!c->h_seq) {
+    uint64_t* w = nullptr;
+    check(hipHostMalloc(reinterpret_cast<void**>(&w), 64, hipHostMallocMapped | hipHostMallocCoherent),
+          "pinned completion word");
+    *w = c->seq;
+    uint64_t* wd = nullptr;
+    const hipError_t e = hipHostGetDevicePointer(reinterpret_cast<void**>(&wd), w, 0);
+    if (e != hipSuccess) (void)hipHostFree(w);
+    check(e, "mapped completion word");
+    c->h_seq = w;
+    c->h_seq_dev = wd;
+  }
 }
 
 // The device view of a slice of the pinned mirror, or nullptr outside it.
@@ -428,11 +445,35 @@ PcgScalars* mapped(amrfld_ctx* c, const PcgScalars* host, int count) {
   return c->h_sc_dev + (host - c->h_sc);
 }
 
+// Brings count scalar records from the device to the host and waits for them.  Into
+// the pinned mirror, a one-block kernel copies them and then stores a new value to a
+// pinned completion word, which the host reads in a loop: the wait ends within a
+// microsecond or so of the copy, where a blocking stream wait takes tens of
+// microseconds to wake the thread, once per convergence check.  After 50 ms of
+// polling the host blocks on the stream instead.  Every kernel before the copy has
+// finished on return; the copy kernel itself may still be retiring.
 void read_scalars(amrfld_ctx* c, PcgScalars* host, const PcgScalars* dev, int count) {
   const hipStream_t s = c->stream();
-  if (PcgScalars* m = mapped(c, host, count)) launch_copy_scalars(s, dev, m, count, true);
-  else check(hipMemcpyAsync(host, dev, count * sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
-  check(hipStreamSynchronize(s), "sync");
+  PcgScalars* m = mapped(c, host, count);
+  if (!m || !c->h_seq) {
+    check(hipMemcpyAsync(host, dev, count * sizeof(PcgScalars), hipMemcpyDeviceToHost, s), "scalars");
+    check(hipStreamSynchronize(s), "sync");
+    return;
+  }
+  static_assert(sizeof(PcgScalars) % 8 == 0, "scalar records are copied as 8-byte words");
+  const uint64_t want = ++c->seq;
+  launch_scalars_to_host(s, dev, m, count * int(sizeof(PcgScalars) / 8), c->h_seq_dev, want);
+  check(hipGetLastError(), "scalars");
+  const auto t0 = std::chrono::steady_clock::now();
+  while (__atomic_load_n(c->h_seq, __ATOMIC_ACQUIRE) != want) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+      check(hipStreamSynchronize(s), "sync");
+      if (__atomic_load_n(c->h_seq, __ATOMIC_ACQUIRE) != want)
+        throw HipError("scalars: completion word not written by a finished stream");
+      break;
+    }
+    __builtin_ia32_pause();
+  }
 }
 
 void write_scalars(amrfld_ctx* c, PcgScalars* dev, const PcgScalars* host, int count) {
@@ -483,8 +524,12 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
   int chunk = c->o.check_every > 0 ? c->o.check_every : 8;
   const bool autochunk = c->o.check_every <= 0;
   const int period = c->o.time_sweeps;
-  read_scalars(c, sc_host, sc_dev, np);
-  while (!all_done(sc_host, np) && launched < max_iter) {
+  // the first batch is enqueued behind the start sweeps without waiting for them: a
+  // problem they already stopped makes its launches return at once, and the host
+  // copy of the scalars is only read after a batch
+  bool first = true;
+  while ((first || !all_done(sc_host, np)) && launched < max_iter) {
+    first = false;
     const int k = std::min(chunk, max_iter - launched);
     if (period > 0) {
       while (int(c->sweep_ev.size()) < 4 * ((launched + k) / period + 1)) {
@@ -537,6 +582,7 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
     for (int it = period; it <= max_done && 4 * (it / period) <= int(c->sweep_ev.size()); it += period) {
       const int kk = it / period - 1;
       float ta = 0.f, tb = 0.f;
+      check(hipEventSynchronize(c->sweep_ev[4 * kk + 3]), "event");
       check(hipEventElapsedTime(&ta, c->sweep_ev[4 * kk], c->sweep_ev[4 * kk + 1]), "event");
       check(hipEventElapsedTime(&tb, c->sweep_ev[4 * kk + 2], c->sweep_ev[4 * kk + 3]), "event");
       ls->a_ms += ta;
@@ -704,6 +750,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   st.launch_blocks = ls.persistent ? ls.launch_blocks : P.G;
   st.launch_mode = ls.persistent ? 1 : 0;
   float ms = 0.f, pms = 0.f;
+  check(hipEventSynchronize(c->ev[3]), "event");  // passed already: the scalars were read after it
   check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
   check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
   st.ms = ms;
@@ -1165,6 +1212,7 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   st.sweep_blocks = P.G;
   st.launch_blocks = P.G;
   float ms = 0.f, pms = 0.f;
+  check(hipEventSynchronize(c->ev[3]), "event");  // passed already: the scalars were read after it
   check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
   check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
   st.ms = ms;
@@ -1502,6 +1550,7 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     read_scalars(c, c->h_sc, c->sc, np);
     check(hipGetLastError(), "kernels");
     float ms = 0.f, pms = 0.f;
+    check(hipEventSynchronize(c->ev[3]), "event");  // passed already: the scalars were read after it
     check(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]), "event");
     check(hipEventElapsedTime(&pms, c->ev[1], c->ev[2]), "event");
     for (int q = 0; q < np; ++q) {
@@ -1643,6 +1692,7 @@ void amrfld_destroy(amrfld_ctx* c) {
                   (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
     dfree(p);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
+  if (c->h_seq) (void)hipHostFree(c->h_seq);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->sweep_ev) (void)hipEventDestroy(e);
