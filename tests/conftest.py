@@ -7,6 +7,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 for p in (ROOT, os.path.join(ROOT, "tests")):
     if p not in sys.path:
         sys.path.insert(0, p)
+# a directory holding a copy of the oracle package with one planted mistake, ahead of
+# the repository's own (set only by the pin-sensitivity tests for their subprocesses)
+_PLANTED = os.environ.get("AMRFLD_PLANTED_ORACLE")
+if _PLANTED:
+    sys.path.insert(0, _PLANTED)
 
 
 def pytest_configure(config):

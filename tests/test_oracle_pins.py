@@ -65,6 +65,27 @@ def test_constant_K_value_enters_as_scale():
     assert np.linalg.norm(_grid_of(o, level, o.E[level]) - ref) / np.linalg.norm(ref) < 1e-13
 
 
+def test_face_mean_exact_for_layered_diffusivity():
+    # Series conduction: with K constant inside each cell and the face value the harmonic
+    # mean, the cell-centred scheme is exact, each cell adding dx / K to the resistance.
+    # A slab with seeded K per x column and energies held at x = 0 and 1 (LP law with
+    # rho kappa_R = 1e10 keeps lambda at 1/3 to ~1e-10, so K = c / (3 rho kappa_R) is set
+    # per cell through rho) must reach the series-resistance profile at the cell centres.
+    level, n = 3, 8
+    ijk = np.array([(i, j, k) for k in range(4) for j in range(4) for i in range(4)], dtype=np.int32)
+    Kx = 0.25 + 0.75 * np.random.default_rng(7).random(n)
+    scale = 1e10
+    o = Oracle(level, {level: ijk}, kmode="lp", kappa_R=1.0, c_light=3.0 * scale, outer={0: 4.0, 1: 0.5})
+    c = o.cells(level)
+    o.set_fields(level, scale / Kx[c[:, 0]], np.ones(len(c)))
+    o.solve_level(level, 1e12, DIRICHLET, solver="dense")  # dt far beyond the relaxation time
+    half = 0.5 / n / Kx  # resistance of half a cell
+    F = (4.0 - 0.5) / (2.0 * half.sum())
+    centre = 4.0 - F * (np.cumsum(2.0 * half) - half)
+    got = _grid_of(o, level, o.E[level])
+    assert np.max(np.abs(got - centre[:, None, None])) <= 1e-8 * 4.0
+
+
 # ------------------------------------------------------- P2: hand-derived rows
 def _two_level_oracle():
     octs = {1: np.array([[0, 0, 0]], dtype=np.int32), 2: np.array([[0, 0, 0]], dtype=np.int32)}
