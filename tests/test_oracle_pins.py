@@ -86,6 +86,23 @@ def test_face_mean_exact_for_layered_diffusivity():
     assert np.max(np.abs(got - centre[:, None, None])) <= 1e-8 * 4.0
 
 
+def test_lp_diffusivity_is_c_over_3_rho_kappa_in_the_diffusion_limit():
+    # Optically thick limit of the LP law (R -> 0, lambda -> 1/3): K = c / (3 rho kappa_R).
+    # With rho kappa_R = 2e10 and c = 6e10 (K = 1 to ~1e-10) one backward-Euler step of a
+    # seeded field on a uniform level is the DCT closed form with C = dt / dx^2.
+    level = 3
+    dx = 1.0 / (1 << level)
+    ijk = np.array([(i, j, k) for k in range(4) for j in range(4) for i in range(4)], dtype=np.int32)
+    o = Oracle(level, {level: ijk}, kmode="lp", kappa_R=2.0, c_light=6e10, abs_floor=1e-16)
+    c = o.cells(level)
+    E0 = 1.0 + 0.1 * np.random.default_rng(11).random(len(c))
+    o.set_fields(level, np.full(len(c), 1e10), E0)
+    b = _grid_of(o, level, o.E[level])
+    o.solve_level(level, 4.0 * dx * dx, DIRICHLET, tol=1e-14)
+    ref = _dct_solution(b, 4.0)
+    assert np.linalg.norm(_grid_of(o, level, o.E[level]) - ref) / np.linalg.norm(ref) < 1e-9
+
+
 # ------------------------------------------------------- P2: hand-derived rows
 def _two_level_oracle():
     octs = {1: np.array([[0, 0, 0]], dtype=np.int32), 2: np.array([[0, 0, 0]], dtype=np.int32)}

@@ -45,6 +45,9 @@ CASES = {
     "LP limiter denominator with R instead of R^2": (
         "fld_oracle.py", "return (2.0 + R) / (6.0 + 3.0 * R + R * R)", "return (2.0 + R) / (6.0 + 3.0 * R + R)",
         [PINS + "test_lp_limiter_values_and_limits"]),
+    "LP diffusivity without kappa_R": (
+        "fld_oracle.py", "return self.c * lam / (rho * self.kappa_R)", "return self.c * lam / rho",
+        [PINS + "test_lp_diffusivity_is_c_over_3_rho_kappa_in_the_diffusion_limit"]),
     "Minerbo upper branch with sqrt(1 + R)": (
         "fld_oracle.py", "high = 1.0 / (1.0 + R + np.sqrt(1.0 + 2.0 * R))", "high = 1.0 / (1.0 + R + np.sqrt(1.0 + R))",
         ["tests/test_variants_oracle.py::test_minerbo_exact_values"]),
