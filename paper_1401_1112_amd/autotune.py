@@ -95,6 +95,7 @@ def _load() -> dict:
 def _store(d: dict) -> None:
     """Write the cache atomically; an unwritable location only loses the cache."""
     path = cache_path()
+    tmp = None
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path), suffix=".tmp")
@@ -102,7 +103,11 @@ def _store(d: dict) -> None:
             json.dump(d, f, indent=1, sort_keys=True)
         os.replace(tmp, path)
     except OSError:
-        pass
+        if tmp is not None and os.path.exists(tmp):
+            try:
+                os.unlink(tmp)
+            except OSError:
+                pass
 
 
 def time_candidates(candidates, apply, run, repeats=3, stream=None):
