@@ -58,6 +58,18 @@ Readings where the paper is silent or ambiguous:
 Every function below is a direct statement of one of these steps, with no
 blocking, fusion or reordering; numpy and scipy primitives (sparse matrix
 products, Cholesky) serve as single steps.
+
+Parity unpinned (readings that no closed form, invariant or printed value fixes;
+the library makes the same choice, so only self-consistency is checked):
+
+* ``grad_E``: the coarser neighbour taken as uniform over its cell (no transverse
+  interpolation) when it enters the gradient at 3 dx / 2.
+* ``cell_K`` on a refined neighbour: its diffusivity from the restricted E and the
+  density sampled at its centre.
+* ``K_of_value`` / ``_outer_C`` for a non-constant law: the diffusivity of the
+  value held at a box face (the factor 2 and the half-cell distance are pinned by
+  the linear fixed point, the harmonic mean with the law's value only by the
+  near-second-order approach to the stationary profile).
 """
 from __future__ import annotations
 

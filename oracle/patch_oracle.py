@@ -10,6 +10,10 @@ taken with the boundary cell's own diffusivity, so the harmonic mean is K_i).
 The diffusivity and the gradient for R follow the level oracle (the boundary
 neighbour is the cell itself at distance dx).  Arrays are indexed [i, j, k]
 with i along x.
+
+Parity unpinned: the boundary coefficient C = K_i dt / dx^2 with the cell's own
+diffusivity (patches are not in the paper; the closed forms pin the rows, not this
+choice of the outside diffusivity).
 """
 from __future__ import annotations
 
