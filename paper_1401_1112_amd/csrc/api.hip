@@ -447,10 +447,9 @@ PcgScalars* mapped(amrfld_ctx* c, const PcgScalars* host, int count) {
 
 // Brings count scalar records from the device to the host and waits for them.  Into
 // the pinned mirror, a one-block kernel copies them and then stores a new value to a
-// pinned completion word, which the host reads in a loop: the wait ends within a
-// microsecond or so of the copy, where a blocking stream wait takes tens of
-// microseconds to wake the thread, once per convergence check.  After 50 ms of
-// polling the host blocks on the stream instead.  Every kernel before the copy has
+// pinned completion word, which the host reads in a loop: the wait ends as soon as
+// the word lands, where a blocking stream wait adds the thread's wake-up to every
+// convergence check.  After 50 ms of polling the host blocks on the stream instead.  Every kernel before the copy has
 // finished on return; the copy kernel itself may still be retiring.
 void read_scalars(amrfld_ctx* c, PcgScalars* host, const PcgScalars* dev, int count) {
   const hipStream_t s = c->stream();
