@@ -31,8 +31,10 @@
  *     duration of the call only.  The library owns its tables, fields and
  *     workspace (device memory, freed by amrfld_destroy).
  *   - Work is ordered on opts.stream (a hipStream_t, NULL = the null stream).
- *     Solve calls return after the solve has finished on that stream
- *     (convergence is known on return); set/get calls are stream-ordered.
+ *     Solve calls return after every kernel of the solve has finished
+ *     (convergence is known on return; only the small kernel that handed the
+ *     scalars to the host may still be retiring, which later work on the
+ *     stream orders behind); set/get calls are stream-ordered.
  *   - A context is not thread-safe: one host thread at a time.
  *   - Per-cell arrays use the library's cell order for that level ("slot"
  *     order): octs sorted by Morton key of their coordinates, 8 cells per oct,
