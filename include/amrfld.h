@@ -210,7 +210,8 @@ typedef struct {
  * with per-patch reductions, scalars and convergence (a converged patch's
  * blocks return at once).  precision: AMRFLD_FP64 or AMRFLD_MIXED; tol as in
  * amrfld_solve_level.  E_out: DEVICE float64 array receiving the final energies
- * of all patches concatenated in patch order (sum of n^3 values, x fastest).
+ * of all patches concatenated in patch order (sum of n^3 values, x fastest),
+ * written by a kernel enqueued on opts.stream before return (stream-ordered).
  * Patch fields or E_out that are not device memory are rejected with
  * AMRFLD_E_INVALID before any launch.
  * Stats: one entry per (step, patch), the patch index in the `level` field.
