@@ -93,3 +93,11 @@ def test_create_rejects_bad_power_law_and_box_faces(field, value):
     ctx = ctypes.c_void_p()
     assert L.load().amrfld_create(ctypes.byref(o), ctypes.byref(ctx)) == L.E_INVALID
     assert b"K_exp" in L.load().amrfld_create_error() or b"outer" in L.load().amrfld_create_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback: without the built HIP library every entry point of the package raises
+    from paper_1401_1112_amd import _lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        L.load(str(tmp_path / "libamrfld.so"))
