@@ -22,7 +22,7 @@ def _named_files(doc):
     text = open(os.path.join(ROOT, doc)).read()
     for tok in re.findall(r"`([^`\s]+)`", text):
         path = tok.split("::")[0]
-        if re.search(r"\.(py|hip|h|cpp|json|txt|md|so)$|/$", path):
+        if re.search(r"\.(py|hip|h|cpp|json|txt|md)$|/$", path):
             yield from _expand(path)
 
 
