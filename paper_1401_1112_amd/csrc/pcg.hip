@@ -212,7 +212,7 @@ __device__ __forceinline__ void operator_formed(const DevLevel& L, const FaceCoe
         const bool cpl = nb >= 0 && ((mk[u] >> (2 * a + ((pos >> a) & 1))) & 1u);
         const int j = cpl ? ((nb << 3) | (pos ^ (1 << a))) : ii[u];
         jv[u][a] = cpl ? j : -1;
-        const int jo = (j >= s0 && j < s1) ? ii[u] : j;
+        const int jo = (j >= s0 && j < s1) ? s0 : j;  // as in the stored form below
         kj[u][a] = K[j];
         rj[u][a] = r[jo];
         dj[u][a] = diag[jo];
@@ -369,7 +369,10 @@ __device__ __forceinline__ void body_pass_a(int vb, DevLevel L, SweepPlan P, int
         const int j = nb >= 0 ? ((nb << 3) | (pos ^ (1 << a))) : ii[u];
         jv[u][a] = j;
         const bool inr = j >= s0 && j < s1;
-        const int jo = inr ? ii[u] : j;  // no gather needed inside the range
+        // no gather needed inside the range: those lanes read the range's first slot
+        // (one line, cached) rather than their own, whose lines the first phase read
+        // long enough ago to have left L2
+        const int jo = inr ? s0 : j;
         // the coefficient of a -face lives at the neighbour; cells on the + side of
         // their oct use their own (already loaded) coefficient instead
         const int jc = ((pos >> a) & 1) ? ii[u] : j;
