@@ -2,7 +2,9 @@
 with g++ prints the tables of seeded balanced hierarchies, which must equal tables
 derived here by brute force from the oct coordinates (Morton order, same-level
 neighbour octs, parent cells, coarse neighbour cells at faces towards a coarser leaf,
-child marks and leaf counts); malformed hierarchies are rejected with a reason."""
+child marks and leaf counts); malformed hierarchies are rejected with a reason.  Every
+case runs twice: with a plain build and with AddressSanitizer and UndefinedBehaviorSanitizer
+(any report aborts the harness, which fails the test)."""
 import os
 import shutil
 import struct
@@ -20,11 +22,16 @@ OFF = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
-    exe = str(tmp_path_factory.mktemp("tables") / "tables_dump")
-    subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "host", "tables_dump.cpp"),
-                    os.path.join(CSRC, "tables.cpp"), "-o", exe], check=True)
+SANITIZE = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+@pytest.fixture(scope="module", params=["plain", "asan_ubsan"])
+def harness(request, tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("tables") / f"tables_dump_{request.param}")
+    extra = SANITIZE if request.param == "asan_ubsan" else []
+    subprocess.run(["g++", "-O1", "-std=c++17"] + extra + ["-I", CSRC,
+                    os.path.join(ROOT, "tests", "host", "tables_dump.cpp"), os.path.join(CSRC, "tables.cpp"),
+                    "-o", exe], check=True)
     return exe
 
 
@@ -36,7 +43,11 @@ def _dump(harness, tmp_path, levels):
             a = np.ascontiguousarray(np.asarray(octs, dtype=np.int32).reshape(-1, 3))
             f.write(struct.pack("<iq", lvl, len(a)))
             f.write(a.tobytes())
-    out = subprocess.run([harness, str(path)], check=True, capture_output=True, text=True).stdout.splitlines()
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=86",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1:exitcode=87")
+    run = subprocess.run([harness, str(path)], capture_output=True, text=True, env=env)
+    assert run.returncode == 0, (run.returncode, run.stderr[-4000:])
+    out = run.stdout.splitlines()
     if out and out[0].startswith("ERR"):
         return out[0]
     tabs, k = {}, 0
