@@ -1,15 +1,20 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py times.
 
+Protocol (as for the small cases): with equal iteration counts in every solve the
+results agree to 1e-12 relative L2; where a count differs (a near-tie of a residual with
+its stopping threshold, the two sides summing in different orders) both sides are run
+again with every solve fixed at the largest count seen (tol 0, no absolute floor) and
+that comparison is gated at 1e-12.
+
 * fld_lognormal (levels 6..9, 4,012,144 cells): one coarse step (15 level solves) on the
-  GPU and in the oracle; with equal iteration counts every level agrees to 1e-12 relative
-  L2.  A near-tie of a residual with its stopping threshold (the two sides sum in different
-  orders) may move one solve by one iteration; then the step is gated at the bound that
-  both stopping tests guarantee (1e-9).
-* the mixed-precision form of the same step: every solve meets its threshold, checked on
-  the FP64 true residual, and the result agrees with the FP64 solve.
-* the 512-patch batch: one step of all patches in shared sweeps; a seeded sample of patches
-  (the smallest and the largest among them) against the patch oracle, every patch's true
-  residual against its threshold, and the persistent launch bitwise equal to the polled one.
+  GPU and in the oracle, at every block count the tuner may pick.
+* the mixed-precision form of the same step: every solve meets its threshold on the FP64
+  true residual; its error against the FP64 oracle (max and L2, per level) is reported
+  and bounded.
+* the 512-patch batch: three steps of all patches in shared sweeps; a seeded sample of 16
+  patches (the smallest and the largest among them) against the patch oracle step by
+  step, every patch's true residual against its threshold, and the persistent launch
+  bitwise equal to the polled one.
 """
 import numpy as np
 import pytest
@@ -58,25 +63,52 @@ def _gpu_step(s, p, max_blocks):
     return gpu, [(st["level"], st["iters"]) for st in s.stats()], s.stats()
 
 
+_FIXED = {}
+
+
+def _oracle_fixed(p, n_fix):
+    """The oracle's coarse step with every solve run for exactly n_fix iterations."""
+    if n_fix not in _FIXED:
+        o = oracle_from_problem(p, max_iter=n_fix, abs_floor=0.0)
+        o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, 0.0)
+        _FIXED[n_fix] = o
+    return _FIXED[n_fix]
+
+
+def _worst_vs_oracle(p, o, gpu):
+    worst = 0.0
+    for l in p.hierarchy.levels:
+        e, cells = gpu[l]
+        worst = max(worst, _rel(e, align(l, o.cells(l), o.E[l], cells)))
+    return worst
+
+
 # every launch shape the autotuner may pick for the level solves
 @pytest.mark.parametrize("max_blocks", [256, 512, 1024, 2048, 4096])
 def test_lognormal_full_step_parity(lognormal, oracle_step, gpu_solver, max_blocks):
     o, counts_o = oracle_step
     gpu, counts_g, _ = _gpu_step(gpu_solver, lognormal, max_blocks)
     assert [l for l, _ in counts_g] == [l for l, _ in counts_o]
-    diff = [(i, g, h) for i, ((_, g), (_, h)) in enumerate(zip(counts_g, counts_o)) if g != h]
-    worst = 0.0
-    for l in lognormal.hierarchy.levels:
-        e, cells = gpu[l]
-        ref = align(l, o.cells(l), o.E[l], cells)
-        worst = max(worst, _rel(e, ref))
-    print(f"max_blocks {max_blocks}: iteration counts {counts_g}; differing solves {diff}; "
+    worst = _worst_vs_oracle(lognormal, o, gpu)
+    print(f"max_blocks {max_blocks}: iteration counts {counts_g} (oracle {counts_o}); "
           f"worst relative L2 {worst:.3e}")
-    if not diff:
+    if counts_g == counts_o:
         assert worst <= 1e-12
-    else:
-        assert len(diff) <= 2 and all(abs(g - h) <= 1 for _, g, h in diff), diff
-        assert worst <= 1e-9
+        return
+    # near-tie at a stopping threshold: both sides with every solve at the largest count
+    from paper_1401_1112_amd import BC_DIRICHLET
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    n_fix = max(it for _, it in counts_g + counts_o)
+    of = _oracle_fixed(lognormal, n_fix)
+    s = solver_from_problem(lognormal, max_iter=n_fix, abs_floor=0.0, max_blocks=max_blocks)
+    s.advance(lognormal.dt_coarse, BC_DIRICHLET, 0.0, raise_on_error=False)
+    g2 = {l: (to_numpy(s.E(l)), s.cells(l)) for l in lognormal.hierarchy.levels}
+    c2 = [st["iters"] for st in s.stats()]
+    s.close()
+    assert c2 == [h["iters"] for h in of.history] == [n_fix] * len(c2)
+    worst2 = _worst_vs_oracle(lognormal, of, g2)
+    print(f"max_blocks {max_blocks}: fixed count {n_fix}, worst relative L2 {worst2:.3e}")
+    assert worst2 <= 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -93,10 +125,13 @@ def test_lognormal_full_step_residuals(lognormal, fp64_step):
         assert st["converged"] == 1 and st["true_rel_res"] * st["rnorm0"] <= 1.05 * thr, st
 
 
-def test_lognormal_mixed_full_step(lognormal, fp64_step):
+def test_lognormal_mixed_full_step(lognormal, fp64_step, oracle_step):
+    # the precision form: every solve stops on the FP64 true residual; its error
+    # against the FP64 oracle and against the FP64 GPU solve, per level after the step
     from paper_1401_1112_amd import BC_DIRICHLET, MIXED
     from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
     gpu, _, _ = fp64_step
+    o, _ = oracle_step
     p = lognormal
     s = solver_from_problem(p, precision=MIXED)
     s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
@@ -106,7 +141,13 @@ def test_lognormal_mixed_full_step(lognormal, fp64_step):
     for l in p.hierarchy.levels:
         e, cells = gpu[l]
         assert np.array_equal(s.cells(l), cells)
-        assert _rel(to_numpy(s.E(l)), e) <= 1e-8
+        m = to_numpy(s.E(l))
+        ref = align(l, o.cells(l), o.E[l], cells)
+        err_max = float(np.abs(m - ref).max() / np.abs(ref).max())
+        err_l2 = _rel(m, ref)
+        print(f"mixed level {l}: vs FP64 oracle max {err_max:.3e} L2 {err_l2:.3e}; "
+              f"vs FP64 GPU L2 {_rel(m, e):.3e}")
+        assert err_l2 <= 1e-8 and _rel(m, e) <= 1e-8
     s.close()
 
 
@@ -136,32 +177,50 @@ def batch512():
     return patch_batch(4000, 512)
 
 
-def test_patch_batch_full_size_sampled(batch512):
+def _batch_sample_vs_oracle(patches, alpha, sample, steps, tol, max_iter, abs_floor):
+    """The whole batch on the GPU for `steps` steps, the sampled patches in the patch
+    oracle; per sampled patch: per-step counts of both sides and the relative L2
+    difference at the end, plus the GPU stats."""
     from paper_1401_1112_amd.solver import BatchSolver
-    patches, alpha = batch512
-    bs = BatchSolver(robin_alpha=alpha)
+    bs = BatchSolver(robin_alpha=alpha, max_iter=max_iter, abs_floor=abs_floor)
     h = bs.upload(patches)
-    bs.run(h, 1, 1e-10)
+    bs.run(h, steps, tol, raise_on_error=False)
     res = bs.result(h)
     st = bs.stats()
     bs.close()
-    for q, x in enumerate(st):
-        thr = max(1e-10 * x["rnorm0"], 1e-14 * x["bnorm"])
-        assert x["converged"] == 1 and x["true_rel_res"] * x["rnorm0"] <= 1.05 * thr, (q, x)
+    n = len(patches)
+    out = {}
+    for q in sample:
+        p = patches[q]
+        e, hist = patch_advance(p.rho, p.E, p.dx, p.dt, p.face_mode, p.face_ghost, p.face_flux, steps, tol,
+                                alpha=alpha, max_iter=max_iter, abs_floor=abs_floor)
+        out[q] = ([st[k * n + q]["iters"] for k in range(steps)], [x["iters"] for x in hist], _rel(res[q], e))
+    return out, st
+
+
+def test_patch_batch_full_size_sampled(batch512):
+    patches, alpha = batch512
+    steps = 3
     sizes = np.array([p.n for p in patches])
     rng = np.random.default_rng(512)
     sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))}
-                    | set(int(i) for i in rng.choice(len(patches), 4, replace=False)))
-    for q in sample:
-        p = patches[q]
-        e, hist = patch_advance(p.rho, p.E, p.dx, p.dt, p.face_mode, p.face_ghost, p.face_flux, 1, 1e-10,
-                                alpha=alpha)
-        r = _rel(res[q], e)
-        print(f"patch {q} n={p.n}: iterations gpu {st[q]['iters']} oracle {hist[0]['iters']}, rel L2 {r:.3e}")
-        if st[q]["iters"] == hist[0]["iters"]:
-            assert r <= 1e-12
-        else:
-            assert abs(st[q]["iters"] - hist[0]["iters"]) <= 1 and r <= 1e-9
+                    | set(int(i) for i in rng.choice(len(patches), 14, replace=False)))
+    out, st = _batch_sample_vs_oracle(patches, alpha, sample, steps, 1e-10, 10000, 1e-14)
+    for k, x in enumerate(st):
+        thr = max(1e-10 * x["rnorm0"], 1e-14 * x["bnorm"])
+        assert x["converged"] == 1 and x["true_rel_res"] * x["rnorm0"] <= 2.5 * thr, (k, x)
+    for q, (ig, io, r) in out.items():
+        print(f"patch {q} n={patches[q].n}: iterations gpu {ig} oracle {io}, rel L2 {r:.3e}")
+    if all(ig == io for ig, io, _ in out.values()):
+        assert max(r for _, _, r in out.values()) <= 1e-12
+        return
+    # near-tie at a stopping threshold: every solve fixed at the largest count seen
+    n_fix = max(max(ig + io) for ig, io, _ in out.values())
+    out2, _ = _batch_sample_vs_oracle(patches, alpha, sample, steps, 0.0, n_fix, 0.0)
+    for q, (ig, io, r) in out2.items():
+        print(f"patch {q} fixed count {n_fix}: rel L2 {r:.3e}")
+        assert ig == io == [n_fix] * steps
+    assert max(r for _, _, r in out2.values()) <= 1e-12
 
 
 def test_patch_batch_full_size_persistent_bitwise(batch512):

@@ -20,19 +20,30 @@ def test_minerbo_amr_parity(seed, mode):
     print(f"minerbo seed {seed} {mode}: {_parity_protocol(p, MODES[mode], steps=2)}")
 
 
-def test_minerbo_batch_parity():
+def _minerbo_batch(patches, alpha, tol, max_iter, abs_floor):
     from paper_1401_1112_amd import K_MINERBO
     from paper_1401_1112_amd.solver import BatchSolver
-    patches, alpha = patch_batch(5100, 6, n_min=4, n_max=16)
-    s = BatchSolver(robin_alpha=alpha)
-    res, _ = s.solve(patches, 1, 1e-12, kmode=K_MINERBO)
+    s = BatchSolver(robin_alpha=alpha, max_iter=max_iter, abs_floor=abs_floor)
+    res, _ = s.solve(patches, 1, tol, kmode=K_MINERBO, raise_on_error=False)
     it = [x["iters"] for x in s.stats()]
     s.close()
+    out = []
     for q, p in enumerate(patches):
-        e, h = patch_advance(p.rho, p.E, p.dx, p.dt, p.face_mode, p.face_ghost, p.face_flux, 1, 1e-12, alpha=alpha,
-                             kmode="minerbo")
-        r = np.linalg.norm(res[q] - e) / np.linalg.norm(e)
-        assert (it[q] == h[0]["iters"] and r <= 1e-12) or (abs(it[q] - h[0]["iters"]) <= 1 and r <= 1e-9), (q, r)
+        e, h = patch_advance(p.rho, p.E, p.dx, p.dt, p.face_mode, p.face_ghost, p.face_flux, 1, tol, alpha=alpha,
+                             kmode="minerbo", max_iter=max_iter, abs_floor=abs_floor)
+        out.append((it[q], h[0]["iters"], float(np.linalg.norm(res[q] - e) / np.linalg.norm(e))))
+    return out
+
+
+def test_minerbo_batch_parity():
+    # same counts and 1e-12; where a count differs, every solve at the largest count, tol 0
+    patches, alpha = patch_batch(5100, 6, n_min=4, n_max=16)
+    out = _minerbo_batch(patches, alpha, 1e-12, 10000, 1e-14)
+    if any(g != o for g, o, _ in out):
+        n_fix = max(max(g, o) for g, o, _ in out)
+        out = _minerbo_batch(patches, alpha, 0.0, n_fix, 0.0)
+        assert all(g == o == n_fix for g, o, _ in out), out
+    assert max(r for _, _, r in out) <= 1e-12, out
 
 
 @pytest.mark.parametrize("seed", [0, 2])
