@@ -179,6 +179,27 @@ amrfld_status amrfld_set_coeffs(amrfld_ctx* c, int level, const double* rho, con
  * Returns AMRFLD_E_NOCONV if max_iter was reached. */
 amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mode, double tol);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses
+ * that forbid hipMalloc): amrfld_solve_level with the same arguments, kernels,
+ * results and stats, whose PCG workspace (residual, two search-direction buffers,
+ * operator product, block partials, scalar record, persistent-launch barrier words)
+ * lives in a static device array of the library instead of context workspace.  It
+ * makes no device allocation or free; the level's tables and fields come from
+ * amrfld_build_level / amrfld_set_coeffs as usual.
+ * Limits: a level of at most 2^21 slots (about 64 MB of scratch per device, held
+ * from the first amrfld_create on that device until the process ends); FP64 only;
+ * no sweep timing (opts.time_sweeps is ignored).
+ * Errors: AMRFLD_E_INVALID for a larger level, AMRFLD_MIXED precision or bad
+ * arguments (as amrfld_solve_level); AMRFLD_E_STATE when the context's device is
+ * not current or when bc_mode is Neumann / Robin and the coarser level's flux
+ * register does not exist yet (one amrfld_solve_level call in that mode creates
+ * it); AMRFLD_E_DEVICE if the scratch array could not be located on this device.
+ * Every call on one device uses that device's single array and leaves its contents
+ * behind (each solve initialises what it reads): calls that overlap in time on one
+ * device, from any context, stream or thread, race and must be serialised by the
+ * caller. */
+amrfld_status amrfld_solve_level_noalloc(amrfld_ctx* c, int level, double dt, int bc_mode, double tol);
+
 /* One step dt_coarse of the base level with adaptive time-stepping (Sect. 2.2):
  * step(l, dt) = { nsub(l+1) x step(l+1, dt/nsub(l+1)); restrict l+1 into l;
  * solve_level(l, dt) }.  Returns the first non-OK status of its solves. */

@@ -78,6 +78,7 @@ SIGNATURES = [
     ("amrfld_level_info", _I, [_P, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _P]),
     ("amrfld_set_coeffs", _I, [_P, _I, _P, _P, _P, _D, _D, _D, _I, _D]),
     ("amrfld_solve_level", _I, [_P, _I, _D, _I, _D]),
+    ("amrfld_solve_level_noalloc", _I, [_P, _I, _D, _I, _D]),
     ("amrfld_advance_subcycled", _I, [_P, _D, _I, _D]),
     ("amrfld_advance_unique", _I, [_P, _D, _D]),
     ("amrfld_solve_batch", _I, [_P, _I, ctypes.POINTER(amrfld_patch), _I, _D, _I, _P]),
@@ -170,6 +171,10 @@ def amrfld_set_coeffs(ctx, level, rho, E, T=None, kappa_R=1.0, kappa_P=1.0, c_li
 
 def amrfld_solve_level(ctx, level, dt, bc_mode, tol):
     return load().amrfld_solve_level(ctx, int(level), float(dt), int(bc_mode), float(tol))
+
+
+def amrfld_solve_level_noalloc(ctx, level, dt, bc_mode, tol):
+    return load().amrfld_solve_level_noalloc(ctx, int(level), float(dt), int(bc_mode), float(tol))
 
 
 def amrfld_advance_subcycled(ctx, dt, bc_mode, tol):

@@ -9,6 +9,7 @@
 #include <type_traits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -39,8 +40,13 @@ void check(hipError_t e, const char* what) {
 // is replayed only while this count is the one it was captured at.
 std::atomic<uint64_t> g_alloc_epoch{0};
 
+// Set while the no-allocation solve runs on this thread: any device allocation or
+// free reached from it is a library bug, reported as an error instead of made.
+thread_local bool g_no_alloc = false;
+
 template <class T>
 T* dalloc(int64_t n, const char* what) {
+  if (g_no_alloc) throw std::logic_error(std::string(what) + ": device allocation in the no-allocation solve");
   void* p = nullptr;
   if (n <= 0) n = 1;
   check(hipMalloc(&p, size_t(n) * sizeof(T)), what);
@@ -50,9 +56,63 @@ T* dalloc(int64_t n, const char* what) {
 
 void dfree(void* p) {
   if (p) {
+    if (g_no_alloc) throw std::logic_error("device free in the no-allocation solve");
     (void)hipFree(p);
     g_alloc_epoch.fetch_add(1);
   }
+}
+
+// ----------------------------------------------------------- static scratch
+// Workspace of amrfld_solve_level_noalloc in a file-scope device array, for callers
+// that cannot allocate device memory: the PCG vectors r, p (two buffers) and q of up
+// to kScratchSlots slots, the block partials of that many slots' sweeps, one scalar
+// record and the barrier words of the persistent launch.  Every sub-buffer starts on
+// a 256-byte boundary.  Each device holds its own copy for the life of the process.
+constexpr int64_t kScratchSlots = int64_t(1) << 21;
+constexpr int64_t kScratchPartials = 4 * ((kScratchSlots + kBlock - 1) / kBlock);
+constexpr int64_t kScratchScalarDoubles = 32;            // one PcgScalars, padded to 256 B
+constexpr int64_t kScratchBarDoubles = kBarWords / 2;    // kBarWords unsigned words
+constexpr int64_t kScratchOffPartials = 4 * kScratchSlots;
+constexpr int64_t kScratchOffScalars = kScratchOffPartials + kScratchPartials;
+constexpr int64_t kScratchOffBar = kScratchOffScalars + kScratchScalarDoubles;
+constexpr int64_t kScratchDoubles = kScratchOffBar + kScratchBarDoubles;
+static_assert(sizeof(PcgScalars) <= kScratchScalarDoubles * sizeof(double), "scalar record fits its slot");
+static_assert(kScratchSlots % 32 == 0 && kScratchPartials % 32 == 0, "sub-buffers stay 256-byte aligned");
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// The device address of `scratch` on each device, taken once per device with that
+// device current (in host code the array's name is no device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_done[dev]) return;
+  double* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+  if (e != hipSuccess) (void)hipGetLastError();
+  g_scratch_done[dev] = true;
+}
+
+double* scratch_of(int dev, std::string* why) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *why = "device index out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    *why = "the device scratch was not set up on this device (create the context with it current)";
+    return nullptr;
+  }
+  if (!g_scratch_ptr[dev]) *why = std::string("device scratch: ") + hipGetErrorString(g_scratch_err[dev]);
+  return g_scratch_ptr[dev];
 }
 
 struct LevelState {
@@ -170,6 +230,7 @@ struct StepGraph {
 struct amrfld_ctx {
   amrfld_opts o{};
   std::string err;
+  int device = 0;  // current device when the context was created
   uint64_t param_epoch = 0;  // bumped by every call that changes what a captured step bakes in
   StepGraph step_graph;
   int finest = -1;
@@ -1590,6 +1651,47 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
   return AMRFLD_OK;
 }
 
+// The level solve with its PCG workspace (r, both p buffers, q, block partials,
+// the scalar record, the barrier words) in the device scratch array instead of the
+// context's workspace, which it neither grows nor frees.  The context's pointers are
+// swapped for the duration of the call and restored on every way out; allocations
+// are refused meanwhile (g_no_alloc).
+amrfld_status solve_one_noalloc(amrfld_ctx* c, double* scr, int level, double dt, int mode, double tol) {
+  struct Swap {
+    amrfld_ctx* c;
+    double *r, *p0, *p1, *q, *partials;
+    int64_t ws_n, partial_n;
+    PcgScalars* sc;
+    unsigned* bar;
+    int time_sweeps;
+    ~Swap() {
+      c->r = r;
+      c->p[0] = p0;
+      c->p[1] = p1;
+      c->q = q;
+      c->partials = partials;
+      c->ws_n = ws_n;
+      c->partial_n = partial_n;
+      c->sc = sc;
+      c->bar = bar;
+      c->o.time_sweeps = time_sweeps;
+      g_no_alloc = false;
+    }
+  } keep{c, c->r, c->p[0], c->p[1], c->q, c->partials, c->ws_n, c->partial_n, c->sc, c->bar, c->o.time_sweeps};
+  c->r = scr;
+  c->p[0] = scr + kScratchSlots;
+  c->p[1] = scr + 2 * kScratchSlots;
+  c->q = scr + 3 * kScratchSlots;
+  c->partials = scr + kScratchOffPartials;
+  c->ws_n = kScratchSlots;
+  c->partial_n = kScratchPartials;
+  c->sc = reinterpret_cast<PcgScalars*>(scr + kScratchOffScalars);
+  c->bar = reinterpret_cast<unsigned*>(scr + kScratchOffBar);
+  c->o.time_sweeps = 0;  // sweep timing would create events
+  g_no_alloc = true;
+  return solve_one(c, level, dt, mode, tol);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1658,8 +1760,11 @@ amrfld_status amrfld_create(const amrfld_opts* o, amrfld_ctx** out) {
     c = new amrfld_ctx();
     c->o = *o;
     c->lev.resize(o->max_level - o->base_level + 1);
+    check(hipGetDevice(&c->device), "device");
+    resolve_scratch(c->device);
     ensure_scalars(c, 1);
     for (auto& e : c->ev) check(hipEventCreate(&e), "event");
+    c->stats.reserve(64);
   } catch (const std::exception& e) {
     g_create_error = e.what();
     amrfld_destroy(c);
@@ -1821,6 +1926,36 @@ amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mod
   if (rt != AMRFLD_OK) return rt;
   c->stats.clear();
   return guarded(c, [&]() { return solve_one(c, level, dt, bc_mode, tol); });
+}
+
+amrfld_status amrfld_solve_level_noalloc(amrfld_ctx* c, int level, double dt, int bc_mode, double tol) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, AMRFLD_E_INVALID, "dt must be positive");
+  if (bc_mode < 0 || bc_mode > 2) return fail(c, AMRFLD_E_INVALID, "unknown bc_mode");
+  if (!(tol >= 0.0)) return fail(c, AMRFLD_E_INVALID, "tol must be >= 0");
+  if (level < c->o.base_level || level > c->finest) return fail(c, AMRFLD_E_INVALID, "level not built");
+  if (c->L(level).t.n_slots() > kScratchSlots)
+    return fail(c, AMRFLD_E_INVALID, "no-allocation solve: the level has " + std::to_string(c->L(level).t.n_slots()) +
+                                         " slots, above the scratch limit of " + std::to_string(kScratchSlots));
+  if (c->o.precision != AMRFLD_FP64)
+    return fail(c, AMRFLD_E_INVALID, "no-allocation solve: FP64 only (the mixed form needs FP32 workspace)");
+  const amrfld_status r = check_level_ready(c, level);
+  if (r != AMRFLD_OK) return r;
+  const amrfld_status rt = check_theta(c, bc_mode);
+  if (rt != AMRFLD_OK) return rt;
+  if (level > c->o.base_level && bc_mode != AMRFLD_BC_DIRICHLET && !c->L(level - 1).reg)
+    return fail(c, AMRFLD_E_STATE, "no-allocation solve: the coarser level has no flux register yet (one "
+                                   "amrfld_solve_level call in Neumann or Robin mode creates it)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) {
+    (void)hipGetLastError();
+    return fail(c, AMRFLD_E_STATE, "no-allocation solve: the context's device is not current");
+  }
+  std::string why;
+  double* scr = scratch_of(dev, &why);
+  if (!scr) return fail(c, AMRFLD_E_DEVICE, why);
+  c->stats.clear();
+  return guarded(c, [&]() { return solve_one_noalloc(c, scr, level, dt, bc_mode, tol); });
 }
 
 amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_mode, double tol) {
