@@ -83,11 +83,13 @@ typedef struct {
   int max_outer;         /* AMRFLD_MIXED: refinement sweeps cap; default 30 */
   int max_blocks;        /* blocks per PCG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
   int persistent;        /* 1 = all PCG iterations of a solve (batch form: of a step) in one cooperative
-                            launch, where the device can run it; else host-polled sweeps */
+                            launch, where the device can run it; in AMRFLD_MIXED the whole refinement
+                            loop with its inner solves, every decision made on the device; else
+                            host-polled sweeps.  Results are the same bits either way */
   int graph;             /* with persistent: the batch form captures all its steps in one hipGraph;
-                            amrfld_advance_subcycled (FP64) captures one coarse step, all its level
-                            solves each in one persistent launch, and replays it while dt, bc_mode,
-                            tol, the context's parameters and its device buffers stay the same
+                            amrfld_advance_subcycled captures one coarse step, all its level solves
+                            each in one persistent launch, and replays it while dt, bc_mode, tol,
+                            the context's parameters and its device buffers stay the same
                             (set_coeffs, set_launch and build_level force a new capture) */
   void* stream;          /* hipStream_t */
   int persistent_per_cu; /* persistent launch: resident blocks per compute unit (0 = as many as fit) */
@@ -199,6 +201,15 @@ amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mod
  * device, from any context, stream or thread, race and must be serialised by the
  * caller. */
 amrfld_status amrfld_solve_level_noalloc(amrfld_ctx* c, int level, double dt, int bc_mode, double tol);
+
+/* Restrict level fine_level into level fine_level - 1: every refined cell of the
+ * coarser level takes the mean of the energies of its 8 children, the coarse-to-fine
+ * ghost value of Sect. 3.3.2 taken after the fine substeps (Sect. 2.2).
+ * amrfld_advance_subcycled does this itself between levels; a caller that runs its
+ * own schedule of amrfld_solve_level calls makes it where that schedule restricts.
+ * Stream-ordered.  AMRFLD_E_INVALID: fine_level is the base level or not built;
+ * AMRFLD_E_STATE: the fields of either level are not set. */
+amrfld_status amrfld_restrict_level(amrfld_ctx* c, int fine_level);
 
 /* One step dt_coarse of the base level with adaptive time-stepping (Sect. 2.2):
  * step(l, dt) = { nsub(l+1) x step(l+1, dt/nsub(l+1)); restrict l+1 into l;

@@ -79,6 +79,7 @@ SIGNATURES = [
     ("amrfld_set_coeffs", _I, [_P, _I, _P, _P, _P, _D, _D, _D, _I, _D]),
     ("amrfld_solve_level", _I, [_P, _I, _D, _I, _D]),
     ("amrfld_solve_level_noalloc", _I, [_P, _I, _D, _I, _D]),
+    ("amrfld_restrict_level", _I, [_P, _I]),
     ("amrfld_advance_subcycled", _I, [_P, _D, _I, _D]),
     ("amrfld_advance_unique", _I, [_P, _D, _D]),
     ("amrfld_solve_batch", _I, [_P, _I, ctypes.POINTER(amrfld_patch), _I, _D, _I, _P]),
@@ -175,6 +176,10 @@ def amrfld_solve_level(ctx, level, dt, bc_mode, tol):
 
 def amrfld_solve_level_noalloc(ctx, level, dt, bc_mode, tol):
     return load().amrfld_solve_level_noalloc(ctx, int(level), float(dt), int(bc_mode), float(tol))
+
+
+def amrfld_restrict_level(ctx, fine_level):
+    return load().amrfld_restrict_level(ctx, int(fine_level))
 
 
 def amrfld_advance_subcycled(ctx, dt, bc_mode, tol):

@@ -551,9 +551,13 @@ bool all_done(const PcgScalars* h, int n) {
 // already ran: batches of (operator sweep, update sweep) pairs, a stopping check
 // after each batch, the next batch size predicted from the slowest problem's
 // observed convergence rate.  Launches after a problem converged return at once.
+// Returns the largest iteration count of the problems' solves (0: every problem was
+// already stopped).  first_chunk > 0: size of the first batch (a prediction, e.g. the
+// previous inner solve's count), else the default.
 template <typename T>
-void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag, T* x, T* r,
-                    T* const* p, T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls) {
+int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag, T* x, T* r,
+                   T* const* p, T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls,
+                   int first_chunk = 0) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
   if (c->o.persistent && !D.cif) {
@@ -572,16 +576,20 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
         unsigned aborted = 0;
         check(hipMemcpy(&aborted, c->bar + kBarAbort, sizeof(unsigned), hipMemcpyDeviceToHost), "abort flag");
         if (aborted) throw std::runtime_error("persistent sweep: a grid barrier timed out");
-        for (int qq = 0; qq < np; ++qq) ls->iters[qq] += sc_host[qq].iter;
+        int max_done = 0;
+        for (int qq = 0; qq < np; ++qq) {
+          ls->iters[qq] += sc_host[qq].iter;
+          max_done = std::max(max_done, sc_host[qq].iter);
+        }
         ls->persistent = true;
         ls->launch_blocks = blocks;
-        return;
+        return max_done;
       }
       (void)hipGetLastError();  // not launchable here: poll instead
     }
   }
   int launched = 0;
-  int chunk = c->o.check_every > 0 ? c->o.check_every : 8;
+  int chunk = c->o.check_every > 0 ? c->o.check_every : (first_chunk > 0 ? std::min(first_chunk, 256) : 8);
   const bool autochunk = c->o.check_every <= 0;
   const int period = c->o.time_sweeps;
   // the first batch is enqueued behind the start sweeps without waiting for them: a
@@ -650,6 +658,7 @@ void pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const 
       ls->n_timed += 1;
     }
   }
+  return max_done;
 }
 
 PcgScalars make_scalars(double tol, double abs_floor, int max_iter, int linf_test) {
@@ -670,6 +679,49 @@ struct SolveArrays {
   int64_t n;
 };
 
+// The FP32 copy of a solve's operator (launched on s into the FP32 workspace) as the
+// inner sweeps read it.
+FaceCoefs<float> operator_f32(amrfld_ctx* c, hipStream_t s, const SolveArrays& A) {
+  ensure_workspace32(c, A.n);
+  launch_to_f32(s, A.n, A.A.Cp, A.A.K, A.diag, c->Cp32, c->K32, c->diag32);
+  FaceCoefs<float> A32;
+  if (A.A.Cp) {
+    A32.Cp = c->Cp32;
+  } else {
+    A32.K = c->K32;
+    A32.mask = A.A.mask;
+    A32.scale = A.A.scale;
+    A32.theta = A.A.theta;
+    A32.per_problem = A.A.per_problem;
+  }
+  return A32;
+}
+
+MixedArgs mixed_args(amrfld_ctx* c, const SolveArrays& A, const FaceCoefs<float>& A32, PcgScalars* out,
+                     PcgScalars* in, int max_outer) {
+  MixedArgs M;
+  M.A = A.A;
+  M.diag = A.diag;
+  M.b = A.b;
+  M.x = A.x;
+  M.x_alt = c->x_alt;
+  M.A32 = A32;
+  M.diag32 = c->diag32;
+  M.r32 = c->r32;
+  M.d32 = c->d32;
+  M.q32 = c->q32;
+  M.p32[0] = c->p32[0];
+  M.p32[1] = c->p32[1];
+  M.outer = out;
+  M.inner = in;
+  M.part = c->partials;
+  M.bar = c->bar;
+  M.inner_tol = c->o.inner_tol;
+  M.max_outer = max_outer;
+  M.inner_cap = c->o.max_iter;
+  return M;
+}
+
 void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
               LoopStats* ls) {
   const hipStream_t s = c->stream();
@@ -685,23 +737,18 @@ void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveA
 // FP32 inner PCG on A d = r inside an FP64 iterative-refinement loop: the FP64
 // sweep applies x += d and forms the true residual r = b - A x; the inner solve
 // uses FP32 coefficients, vectors and operator arithmetic with FP64 dot products.
-// Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].
+// Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].  Every decision
+// of the loop is made on the device (k_ir_finish): the host enqueues rounds and
+// learns that all problems stopped when a round's inner solves all end after 0
+// iterations, so it reads scalars only inside the inner solves.  With `persistent`
+// the whole solve is one cooperative launch (the same bits).  Once the stream has
+// run, the outer records hold the refinement sweeps (iter) and the inner iterations
+// (inner_total).
 void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
-               LoopStats* ls, std::vector<int>* outer_iters) {
+               LoopStats* ls) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
-  ensure_workspace32(c, A.n);
-  launch_to_f32(s, A.n, A.A.Cp, A.A.K, A.diag, c->Cp32, c->K32, c->diag32);
-  FaceCoefs<float> A32;
-  if (A.A.Cp) {
-    A32.Cp = c->Cp32;
-  } else {
-    A32.K = c->K32;
-    A32.mask = A.A.mask;
-    A32.scale = A.A.scale;
-    A32.theta = A.A.theta;
-    A32.per_problem = A.A.per_problem;
-  }
+  const FaceCoefs<float> A32 = operator_f32(c, s, A);
   for (int q = 0; q < np; ++q) {
     c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
     c->h_sc[np + q] = make_scalars(c->o.inner_tol, 0.0, c->o.max_iter, 0);
@@ -710,28 +757,44 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
   check(hipEventRecord(c->ev[1], s), "event");
   PcgScalars* out = c->sc;
   PcgScalars* in = c->sc + np;
+  const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
+  if (c->o.persistent && !D.cif) {
+    if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
+    SweepPlan Pp = P;
+    Pp.done_count = c->bar + kBarDone;
+    const MixedArgs M = mixed_args(c, A, A32, out, in, max_outer);
+    const int blocks = mixed_persistent_blocks(Pp, c->o.persistent_per_cu);
+    if (blocks > 0) {
+      launch_zero_u32(s, c->bar, kBarWords);
+      if (launch_mixed_persistent(s, D, Pp, M, c->o.persistent_per_cu) == hipSuccess) {
+        unsigned aborted = 0;
+        check(hipMemcpyAsync(&aborted, c->bar + kBarAbort, sizeof(unsigned), hipMemcpyDeviceToHost, s), "abort flag");
+        check(hipStreamSynchronize(s), "abort flag");
+        if (aborted) throw std::runtime_error("persistent sweep: a grid barrier timed out");
+        ls->persistent = true;
+        ls->launch_blocks = blocks;
+        return;
+      }
+      (void)hipGetLastError();  // not launchable here: host-driven launches instead
+    }
+  }
   double* x_cur = A.x;
   double* x_nxt = c->x_alt;
-  const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
-  int budget = c->o.max_iter;
+  int hint = 0;
   for (int outer = 0; outer <= max_outer; ++outer) {
     launch_ir_sweep(s, D, P, A.A, A.diag, A.b, x_cur, outer == 0 ? nullptr : c->d32, x_nxt, c->r32, out,
                     c->partials);
     std::swap(x_cur, x_nxt);
-    launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, std::max(1, budget), out, in, c->partials);
-    read_scalars(c, c->h_sc, out, np);
-    if (all_done(c->h_sc, np) || outer == max_outer || budget <= 0) break;
+    launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, max_outer, out, in, c->partials);
     launch_inner_init(s, D, P, c->diag32, c->r32, c->d32, c->p32[0], out, c->partials);
     launch_init_finish(s, P, c->partials, in);
-    int before = 0;
-    for (int v : ls->iters) before = std::max(before, v);
-    pcg_iterations<float>(c, D, P, A32, c->diag32, c->d32, c->r32, c->p32, c->q32, in, c->h_sc + np,
-                          std::max(1, budget), ls);
-    int after = 0;
-    for (int v : ls->iters) after = std::max(after, v);
-    budget -= std::max(1, after - before);
+    LoopStats inner_ls;
+    inner_ls.iters.assign(np, 0);
+    const int done = pcg_iterations<float>(c, D, P, A32, c->diag32, c->d32, c->r32, c->p32, c->q32, in,
+                                           c->h_sc + np, c->o.max_iter, &inner_ls, hint + 1);
+    if (done == 0) break;  // every refinement loop had stopped before this round's inner solves
+    hint = done;
   }
-  for (int q = 0; q < np; ++q) (*outer_iters)[q] = c->h_sc[q].iter;
   if (x_cur != A.x) launch_copy_f64(s, A.x, x_cur, A.n);
 }
 
@@ -767,10 +830,9 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   ensure_scalars(c, 1);
   LoopStats ls;
   ls.iters.assign(1, 0);
-  std::vector<int> outer_iters(1, 0);
   const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots};
   if (c->o.precision == AMRFLD_MIXED) {
-    pcg_mixed(c, D, P, A, tol, &ls, &outer_iters);
+    pcg_mixed(c, D, P, A, tol, &ls);
   } else {
     pcg_fp64(c, D, P, A, tol, &ls);
   }
@@ -795,8 +857,8 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   st.n_leaf = L.t.n_leaf;
   st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
   if (c->o.precision == AMRFLD_MIXED) {
-    st.iters = ls.iters[0];
-    st.outer_iters = outer_iters[0];
+    st.iters = h.inner_total;
+    st.outer_iters = h.iter;
     st.true_rel_res = st.rel_res;  // the outer residual is the FP64 true residual
   } else {
     st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
@@ -848,10 +910,12 @@ void schedule(const amrfld_ctx* c, int level, double dt, std::vector<ScheduledSo
   out.push_back({level, dt, restricted});
 }
 
-// The kernels of one level solve with its PCG in one persistent launch, enqueued
-// without host synchronisation (scalars in sc; the barrier words of c->bar, whose
-// abort flag is left for the caller to read).
-hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int mode, double tol, PcgScalars* sc) {
+// The kernels of one level solve with its PCG (mixed precision: its whole refinement
+// loop) in one persistent launch, enqueued without host synchronisation (scalars in
+// sc, the inner records of the mixed form in sc_inner; the barrier words of c->bar,
+// whose abort flag is left for the caller to read).
+hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int mode, double tol, PcgScalars* sc,
+                        PcgScalars* sc_inner) {
   LevelState& L = c->L(level);
   LevelState* Lc = level > c->o.base_level ? &c->L(level - 1) : nullptr;
   const DevLevel D = L.dev();
@@ -873,14 +937,24 @@ hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int
   const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
   SweepPlan Pp = P;
   Pp.done_count = c->bar + kBarDone;
+  const bool mixed = c->o.precision == AMRFLD_MIXED;
   launch_init_scalars(st, sc, 1, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
-  launch_zero_u32(st, c->bar, kBarAbort);  // arrivals, releases, stop count; not the abort flag
-  launch_pcg_init<double>(st, D, P, Aop, L.diag, L.b, L.E, c->r, c->p[0], c->partials);
-  launch_init_finish(st, P, c->partials, sc);
-  const hipError_t e = launch_pcg_persistent<double>(st, D, Pp, c->o.max_iter, Aop, L.diag, L.E, c->r, c->p, c->q,
-                                                     sc, c->partials, c->bar, c->o.persistent_per_cu);
+  launch_zero_u32(st, c->bar, kBarAbort);  // arrivals, releases, stop counts; not the abort flag
+  hipError_t e;
+  if (mixed) {
+    const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots};
+    const FaceCoefs<float> A32 = operator_f32(c, st, A);
+    launch_init_scalars(st, sc_inner, 1, c->o.inner_tol, 0.0, c->o.max_iter, 0);
+    const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
+    e = launch_mixed_persistent(st, D, Pp, mixed_args(c, A, A32, sc, sc_inner, max_outer), c->o.persistent_per_cu);
+  } else {
+    launch_pcg_init<double>(st, D, P, Aop, L.diag, L.b, L.E, c->r, c->p[0], c->partials);
+    launch_init_finish(st, P, c->partials, sc);
+    e = launch_pcg_persistent<double>(st, D, Pp, c->o.max_iter, Aop, L.diag, L.E, c->r, c->p, c->q, sc, c->partials,
+                                      c->bar, c->o.persistent_per_cu);
+  }
   if (e != hipSuccess) return e;
-  if (c->o.true_residual) launch_true_residual(st, D, P, Aop, L.diag, L.b, L.E, sc, c->partials);
+  if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Aop, L.diag, L.b, L.E, sc, c->partials);
   launch_post_solve(st, D, P, L.E, L.rho, cp, dt, L.T, sc, c->partials);
   if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN))
     launch_flux_register(st, D, L.K, Lc->K, L.E, Lc->E, dt, Lc->reg, int(Lc->t.n_slots()));
@@ -888,12 +962,14 @@ hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int
   return hipGetLastError();
 }
 
-// One coarse step as a graph of persistent level solves: captured on first use and
-// replayed while dt, mode, tol, the context's parameters and its device buffers are
-// those it was captured with.  AMRFLD_E_STATE: not available here (mixed precision,
-// no cooperative launch, capture refused); the caller then runs the step eagerly.
+// One coarse step as a graph of persistent level solves (FP64 PCG, or the whole
+// mixed-precision refinement loop): captured on first use and replayed while dt,
+// mode, tol, the context's parameters and its device buffers are those it was
+// captured with.  AMRFLD_E_STATE: not available here (no cooperative launch, capture
+// refused); the caller then runs the step eagerly.
 amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double tol) {
-  if (!c->o.graph || !c->o.persistent || c->o.precision != AMRFLD_FP64) return AMRFLD_E_STATE;
+  if (!c->o.graph || !c->o.persistent) return AMRFLD_E_STATE;
+  const bool mixed = c->o.precision == AMRFLD_MIXED;
   std::vector<ScheduledSolve> sched;
   schedule(c, c->o.base_level, dt_coarse, sched);
   const int n = int(sched.size());
@@ -905,12 +981,15 @@ amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double to
     if (l < c->finest && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN)) ensure_reg(c, c->L(l));
   }
   ensure_workspace(c, max_slots);
-  ensure_scalars(c, n);
+  if (mixed) ensure_workspace32(c, max_slots);
+  ensure_scalars(c, n + 1);  // n solves, then the shared inner record of the mixed form
   if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
   for (int l = c->o.base_level; l <= c->finest; ++l) {
     const int nt = tiles_of(c->L(l).t.n_slots());
     SweepPlan P = single_plan(sweep_blocks(nt, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), nt);
-    if (persistent_blocks<double>(P, c->o.persistent_per_cu) <= 0) return AMRFLD_E_STATE;
+    const int pb = mixed ? mixed_persistent_blocks(P, c->o.persistent_per_cu)
+                         : persistent_blocks<double>(P, c->o.persistent_per_cu);
+    if (pb <= 0) return AMRFLD_E_STATE;
   }
   const hipStream_t us = c->stream();
   StepGraph& sg = c->step_graph;
@@ -934,7 +1013,7 @@ amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double to
           LevelState& F = c->L(op.level + 1);
           launch_restrict(c->cap_stream, F.dev(), F.E, c->L(op.level).E);
         }
-        e_rec = record_solve(c, c->cap_stream, op.level, op.dt, mode, tol, c->sc + k++);
+        e_rec = record_solve(c, c->cap_stream, op.level, op.dt, mode, tol, c->sc + k++, c->sc + n);
       }
     }
     const hipError_t e_end = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &sg.g) : e;
@@ -969,11 +1048,12 @@ amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double to
     const SweepPlan P = single_plan(sweep_blocks(nt, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), nt);
     amrfld_stats st{};
     st.level = sched[k].level;
-    st.iters = h.iter;
+    st.iters = mixed ? h.inner_total : h.iter;
+    st.outer_iters = mixed ? h.iter : 0;
     st.converged = h.converged;
     st.n_leaf = L.t.n_leaf;
     st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
-    st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+    st.true_rel_res = mixed ? st.rel_res : (c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0);
     st.linf_change = h.linf;
     st.min_E = h.min_E;
     st.dt = sched[k].dt;
@@ -982,7 +1062,8 @@ amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double to
     st.rnorm0 = h.rnorm0;
     st.bnorm = h.bnorm;
     st.sweep_blocks = P.G;
-    st.launch_blocks = persistent_blocks<double>(P, c->o.persistent_per_cu);
+    st.launch_blocks = mixed ? mixed_persistent_blocks(P, c->o.persistent_per_cu)
+                             : persistent_blocks<double>(P, c->o.persistent_per_cu);
     st.launch_mode = 2;
     st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
     if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
@@ -1421,7 +1502,8 @@ void build_batch_into(amrfld_ctx* c, BatchState* B, const std::vector<int>& size
 // All steps of a batch with one cooperative launch per step for the PCG
 // iterations, optionally captured in one hipGraph.  Returns AMRFLD_E_STATE when
 // the device cannot run the cooperative launch (the caller then polls).
-amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, int n_steps, double tol) {
+amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, int n_steps, double tol,
+                                     int precision) {
   BatchState& B = *c->batch;
   const int np = B.n_prob;
   const DevLevel D = B.dev();
@@ -1430,12 +1512,18 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
   P.done_count = c->bar + kBarDone;
   const unsigned* abort_flag = c->bar + kBarAbort;
   const int per_cu = c->o.persistent_per_cu;
-  if (persistent_blocks<double>(P, per_cu) <= 0) return AMRFLD_E_STATE;
-  ensure_scalars(c, n_steps * np);
+  const bool mixed = precision == AMRFLD_MIXED;
+  if ((mixed ? mixed_persistent_blocks(P, per_cu) : persistent_blocks<double>(P, per_cu)) <= 0) return AMRFLD_E_STATE;
+  // one record per (step, patch), then the inner records of the mixed form (shared by the steps)
+  ensure_scalars(c, n_steps * np + np);
+  if (mixed) ensure_workspace32(c, B.n_slots);
+  PcgScalars* sc_inner = c->sc + int64_t(n_steps) * np;
   CouplingParams cp{};
   cp.T = nullptr;
   const CellKParams kp{1, 1.0, 1.0, 1.0};
   const FaceCoefs<double> Aop = face_coefs(c, B.Cp, B.K, B.mask, 1.0, 1.0, true);
+  const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots};
+  const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
   auto record = [&](hipStream_t st) -> hipError_t {
     launch_zero_u32(st, c->bar, kBarWords);
     for (int step = 0; step < n_steps; ++step) {
@@ -1445,12 +1533,19 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
                       OuterBC{}, B.Cp, B.mask, B.diag, B.b);
       launch_init_scalars(st, sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
       launch_zero_u32(st, c->bar, kBarAbort);
-      launch_pcg_init<double>(st, D, P, Aop, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
-      launch_init_finish(st, P, c->partials, sc);
-      const hipError_t e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, Aop, B.diag, B.E, c->r, c->p,
-                                                         c->q, sc, c->partials, c->bar, per_cu);
+      hipError_t e;
+      if (mixed) {
+        const FaceCoefs<float> A32 = operator_f32(c, st, A);
+        launch_init_scalars(st, sc_inner, np, c->o.inner_tol, 0.0, c->o.max_iter, 0);
+        e = launch_mixed_persistent(st, D, P, mixed_args(c, A, A32, sc, sc_inner, max_outer), per_cu);
+      } else {
+        launch_pcg_init<double>(st, D, P, Aop, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
+        launch_init_finish(st, P, c->partials, sc);
+        e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, Aop, B.diag, B.E, c->r, c->p, c->q, sc,
+                                          c->partials, c->bar, per_cu);
+      }
       if (e != hipSuccess) return e;
-      if (c->o.true_residual) launch_true_residual(st, D, P, Aop, B.diag, B.b, B.E, sc, c->partials);
+      if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Aop, B.diag, B.b, B.E, sc, c->partials);
       launch_post_solve(st, D, P, B.E, B.rho, cp, 0.0, nullptr, sc, c->partials);
     }
     return hipGetLastError();
@@ -1504,11 +1599,13 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       const PcgScalars& h = c->h_sc[int64_t(step) * np + q];
       amrfld_stats st{};
       st.level = q;
-      st.iters = h.iter;
+      st.iters = mixed ? h.inner_total : h.iter;
+      st.outer_iters = mixed ? h.iter : 0;
       st.converged = h.converged;
       st.n_leaf = int64_t(B.sizes[q]) * B.sizes[q] * B.sizes[q];
       st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
-      st.true_rel_res = c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0;
+      st.true_rel_res =
+          mixed ? st.rel_res : (c->o.true_residual ? (h.rnorm0 > 0 ? h.true_rnorm / h.rnorm0 : 0.0) : -1.0);
       st.linf_change = h.linf;
       st.min_E = h.min_E;
       st.dt = pt[q].dt;
@@ -1518,7 +1615,7 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       st.rnorm0 = h.rnorm0;
       st.bnorm = h.bnorm;
       st.sweep_blocks = P.G;
-      st.launch_blocks = persistent_blocks<double>(P, per_cu);
+      st.launch_blocks = mixed ? mixed_persistent_blocks(P, per_cu) : persistent_blocks<double>(P, per_cu);
       st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
       if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
         worst = amrfld_status(st.status);
@@ -1568,8 +1665,8 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
   check(hipMemcpyAsync(B.src, ptr.data(), np * sizeof(void*), hipMemcpyHostToDevice, s), "batch pointers");
   launch_batch_gather(s, D, B.idx, B.src, 0.0, B.E);
   ensure_workspace(c, B.n_slots);
-  if (c->o.persistent && precision == AMRFLD_FP64) {
-    const amrfld_status st = solve_batch_persistent(c, pt, n_steps, tol);
+  if (c->o.persistent) {
+    const amrfld_status st = solve_batch_persistent(c, pt, n_steps, tol, precision);
     if (st != AMRFLD_E_STATE) return st;
     c->stats.clear();  // the device cannot run it: poll instead
   }
@@ -1594,11 +1691,10 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
                     OuterBC{}, B.Cp, B.mask, B.diag, B.b);
     LoopStats ls;
     ls.iters.assign(np, 0);
-    std::vector<int> outer_iters(np, 0);
     const FaceCoefs<double> Aop = face_coefs(c, B.Cp, B.K, B.mask, 1.0, 1.0, true);
     const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots};
     if (precision == AMRFLD_MIXED) {
-      pcg_mixed(c, D, P, A, tol, &ls, &outer_iters);
+      pcg_mixed(c, D, P, A, tol, &ls);
     } else {
       pcg_fp64(c, D, P, A, tol, &ls);
     }
@@ -1617,8 +1713,8 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
       const PcgScalars& h = c->h_sc[q];
       amrfld_stats st{};
       st.level = q;
-      st.iters = ls.iters[q];
-      st.outer_iters = outer_iters[q];
+      st.iters = precision == AMRFLD_MIXED ? h.inner_total : ls.iters[q];
+      st.outer_iters = precision == AMRFLD_MIXED ? h.iter : 0;
       st.converged = h.converged;
       st.n_leaf = int64_t(sizes[q]) * sizes[q] * sizes[q];
       st.rel_res = h.rnorm0 > 0 ? h.rnorm / h.rnorm0 : 0.0;
@@ -1956,6 +2052,21 @@ amrfld_status amrfld_solve_level_noalloc(amrfld_ctx* c, int level, double dt, in
   if (!scr) return fail(c, AMRFLD_E_DEVICE, why);
   c->stats.clear();
   return guarded(c, [&]() { return solve_one_noalloc(c, scr, level, dt, bc_mode, tol); });
+}
+
+amrfld_status amrfld_restrict_level(amrfld_ctx* c, int fine_level) {
+  if (!c) return AMRFLD_E_INVALID;
+  if (fine_level <= c->o.base_level || fine_level > c->finest)
+    return fail(c, AMRFLD_E_INVALID, "fine_level must be a built level above the base level");
+  if (!c->L(fine_level).has_fields || !c->L(fine_level - 1).has_fields)
+    return fail(c, AMRFLD_E_STATE, "fields of both levels must be set");
+  return guarded(c, [&]() -> amrfld_status {
+    LevelState& F = c->L(fine_level);
+    upload_tables(c, F);
+    launch_restrict(c->stream(), F.dev(), F.E, c->L(fine_level - 1).E);
+    check(hipGetLastError(), "restrict");
+    return AMRFLD_OK;
+  });
 }
 
 amrfld_status amrfld_advance_subcycled(amrfld_ctx* c, double dt_coarse, int bc_mode, double tol) {

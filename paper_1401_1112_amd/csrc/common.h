@@ -159,38 +159,89 @@ __device__ __forceinline__ bool block_read_flag(const int* f) {
   return r;
 }
 
-// Grid-wide barrier of a cooperative launch (all blocks resident).  The words
-// live at bar[kBarArrive] (arrivals, only ever incremented) and bar[kBarRelease]
-// (barriers completed), on separate 256-byte lines, both zero at the launch.
-// Every wave first waits until its own stores have reached its XCD's L2 (a
-// block barrier alone does not wait for them); thread 0 then releases the
-// block's writes to the other XCDs (agent-scope release fence: one L2
-// write-back) and arrives.  The block that completes barrier number `epoch`
-// (arrivals reach epoch * n_blocks) acquires the others' writes and publishes
-// the epoch; the rest poll the release word with plain atomic loads and acquire
-// once it moves.  The wait is bounded: after spin_limit polls the block reports
-// failure instead of waiting forever.  `epoch` counts this block's barriers.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned n_blocks, unsigned& epoch,
-                                             unsigned spin_limit) {
+// Grid-wide barrier of a cooperative launch (all blocks resident), in two levels
+// over the XCDs.  Every XCD has its own L2 and blocks of one XCD see each other's
+// stores there once they have completed; another XCD sees them only after that L2
+// has been written back (agent-scope release) and its own copies invalidated
+// (agent-scope acquire).  So a block waits until its own stores have completed and
+// arrives at its XCD's word; the last arrival of an XCD writes back that L2 once
+// for all its blocks and arrives at the global word; the last XCD publishes the
+// barrier number there; each XCD's last arrival, once it sees it, publishes it on
+// its XCD's word, where that XCD's other blocks wait; every block then acquires.
+// Blocks learn their XCD from the hardware register that names it, and the first
+// barrier of a launch (a flat one: every block writes back and arrives at one
+// word) also counts each XCD's blocks.  Arrival words only ever grow; barrier
+// number `epoch` is complete on a word when it reaches epoch times its arrivals.
+// Every wait is bounded: after spin_limit polls the block reports failure instead
+// of waiting forever.  All words live in `bar` (kBarWords, the first kBarAbort
+// zeroed before the launch).
+struct GridSync {
+  unsigned* bar;
+  unsigned n_blocks;
+  unsigned spin_limit;
+  unsigned epoch = 0;    // barriers this block has passed
+  unsigned xcd = 0;      // thread 0: this block's XCD
+  unsigned xcd_size = 0; // thread 0: resident blocks of that XCD
+  unsigned n_xcd = 0;    // thread 0: XCDs with resident blocks
+};
+
+__device__ __forceinline__ unsigned this_xcd() {
+  // HW_REG_XCC_ID: bits [3:0] hold the XCD the wave runs on
+  return __builtin_amdgcn_s_getreg((15 << 11) | 20) & unsigned(kMaxXcd - 1);
+}
+
+__device__ __forceinline__ bool spin_until(unsigned* w, unsigned target, unsigned spin_limit) {
+  unsigned polls = 0;
+  while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++polls > spin_limit) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool grid_barrier(GridSync& gs) {
   __shared__ int ok;
-  ++epoch;
-  __builtin_amdgcn_s_waitcnt(0);
+  ++gs.epoch;
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed (they are in its XCD's L2)
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned old = __hip_atomic_fetch_add(bar + kBarArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned* bar = gs.bar;
     int good = 1;
-    if (old + 1u == epoch * n_blocks) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-      __hip_atomic_store(bar + kBarRelease, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gs.epoch == 1) {
+      // flat: count this XCD's blocks, write back, arrive at one word
+      gs.xcd = this_xcd();
+      __hip_atomic_fetch_add(bar + kBarXcdCount + 64 * gs.xcd, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned old =
+          __hip_atomic_fetch_add(bar + kBarFirstArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1u == gs.n_blocks) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(bar + kBarFirstRelease, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        good = spin_until(bar + kBarFirstRelease, 1u, gs.spin_limit);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      unsigned n = 0;
+      for (int x = 0; x < kMaxXcd; ++x)
+        n += __hip_atomic_load(bar + kBarXcdCount + 64 * x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u;
+      gs.n_xcd = n;
+      gs.xcd_size = __hip_atomic_load(bar + kBarXcdCount + 64 * gs.xcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      unsigned polls = 0;
-      while (__hip_atomic_load(bar + kBarRelease, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++polls > spin_limit) {
-          good = 0;
-          break;
+      const unsigned e = gs.epoch - 1;  // numbering of the two-level barriers
+      const unsigned old =
+          __hip_atomic_fetch_add(bar + kBarXcdArrive + 64 * gs.xcd, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1u == e * gs.xcd_size) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this XCD's stores, written back once
+        const unsigned o2 = __hip_atomic_fetch_add(bar + kBarArrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (o2 + 1u == e * gs.n_xcd) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+          __hip_atomic_store(bar + kBarRelease, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          good = spin_until(bar + kBarRelease, e, gs.spin_limit);
         }
+        __hip_atomic_store(bar + kBarXcdRelease + 64 * gs.xcd, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        good = spin_until(bar + kBarXcdRelease + 64 * gs.xcd, e, gs.spin_limit);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }

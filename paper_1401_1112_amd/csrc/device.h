@@ -11,10 +11,17 @@ constexpr int kBlock = 256;  // threads per block = slots per tile
 constexpr int kMaxTilesPerBlock = 16;
 
 // Words of the persistent launch's control buffer (unsigned), each on its own
-// 256-byte line: grid-barrier arrivals and releases, the count of problems that
-// stopped, and the abort flag.  The first kBarAbort words are zeroed before
-// every persistent launch.
-constexpr int kBarArrive = 0, kBarRelease = 64, kBarDone = 128, kBarAbort = 192, kBarWords = 256;
+// 256-byte line: grid-barrier arrivals (of the XCD groups) and releases, the count
+// of problems whose PCG (or inner PCG) stopped, the count of problems whose
+// refinement loop stopped (mixed precision), the first barrier's arrivals and
+// release, then per XCD (up to kMaxXcd) its count of resident blocks, its arrivals
+// and its release, and last the abort flag.  The first kBarAbort words are zeroed
+// before every persistent launch.
+constexpr int kMaxXcd = 16;
+constexpr int kBarArrive = 0, kBarRelease = 64, kBarDone = 128, kBarOuterDone = 192, kBarFirstArrive = 256,
+              kBarFirstRelease = 320, kBarXcdCount = 384, kBarXcdArrive = kBarXcdCount + 64 * kMaxXcd,
+              kBarXcdRelease = kBarXcdArrive + 64 * kMaxXcd, kBarAbort = kBarXcdRelease + 64 * kMaxXcd,
+              kBarWords = kBarAbort + 64;
 
 // Scalars of one PCG solve in device memory.  The sweeps derive alpha, beta and
 // the stopping decision themselves from the previous sweep's block partials;
@@ -34,7 +41,7 @@ struct PcgScalars {
   int max_iter;
   int linf_test;
   int counted;      // this problem's stop has been added to the plan's done counter
-  int pad_;
+  int inner_total;  // mixed precision, outer record: inner iterations of the refinement so far
 };
 
 // Parameters of one independent patch of a batch: a box of cells of size dx
@@ -247,12 +254,40 @@ void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, con
 // ------------------------------------------- mixed precision (FP32 inner solve)
 // Outer sweep: x_new = x_old + d (d in FP32, may be null), r = b - A x_new in
 // FP64, r32 = (float) r; partials ||r||^2, ||b||^2, max |d| / |x_old|; then the
-// finisher applies the outer stopping test and prepares the inner scalars.
+// finisher applies the outer stopping test, the caps of max_outer sweeps and of the
+// outer record's max_iter inner iterations, and prepares the inner scalars (an
+// inner solve of a stopped problem is off from the start).
 void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,
                      const double* diag, const double* b, const double* x_old, const float* d,
                      double* x_new, float* r32, const PcgScalars* outer, double* part);
-void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int inner_max,
+void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int max_outer,
                       PcgScalars* outer, PcgScalars* inner, const double* part);
+// Arrays and parameters of the whole mixed-precision solve in one persistent launch.
+struct MixedArgs {
+  FaceCoefs<double> A;  // FP64 operator of the refinement sweeps
+  const double* diag = nullptr;
+  const double* b = nullptr;
+  double* x = nullptr;      // iterate: x_0 on entry, the result on return
+  double* x_alt = nullptr;  // second buffer of the refinement sweeps
+  FaceCoefs<float> A32;     // FP32 operator of the inner solves
+  const float* diag32 = nullptr;
+  float *r32 = nullptr, *d32 = nullptr, *q32 = nullptr;
+  float* p32[2] = {nullptr, nullptr};
+  PcgScalars* outer = nullptr;  // n_prob outer records (tol, abs_floor, max_iter, linf_test set)
+  PcgScalars* inner = nullptr;  // n_prob inner records
+  double* part = nullptr;
+  unsigned* bar = nullptr;      // control buffer; its first kBarAbort words zeroed before the launch
+  double inner_tol = 1e-2;
+  int max_outer = 30;
+  int inner_cap = 10000;        // bound of the inner loop (the records' max_iter never exceeds it)
+  unsigned spin_limit = 1u << 26;
+};
+// Blocks of the mixed persistent launch for this plan (0 if the device cannot run it).
+int mixed_persistent_blocks(const SweepPlan& P, int per_cu_cap);
+// P.done_count must be M.bar + kBarDone.  Returns an error if the device cannot run
+// the cooperative launch; bar[kBarAbort] becomes 1 if a grid barrier timed out.
+hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const MixedArgs& M,
+                                   int per_cu_cap);
 // Inner start: d = 0, p = 0; partials (r, r / diag), ||r||^2 of the FP32 residual.
 void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const float* diag32,
                        const float* r32, float* d, float* p_clear, const PcgScalars* outer,

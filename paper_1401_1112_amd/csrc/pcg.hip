@@ -611,8 +611,15 @@ __device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, c
 
 // One block per problem: the outer stopping test, then the inner scalars.  A
 // problem done in an earlier sweep keeps its state and its inner solve is off.
-__device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first, double inner_tol, int inner_max,
-                                                      PcgScalars* outs, PcgScalars* ins, const double* part) {
+// Every decision of the refinement loop is made here, on the device: the FP64
+// stopping test (Sect. 3.3.4 on the true residual), the cap of max_outer refinement
+// sweeps and the cap of the outer record's max_iter inner iterations in all (both
+// end the loop unconverged).  The inner solve that just ended is added to the
+// outer record's count first.  outer_done (or nullptr) counts the problems whose
+// loop has ended, for the persistent launch.
+__device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first, double inner_tol, int max_outer,
+                                               PcgScalars* outs, PcgScalars* ins, const double* part,
+                                               unsigned* outer_done) {
   __shared__ double lds[kLds];
   int b0, Gp;
   problem_blocks(P, prob, b0, Gp);
@@ -621,6 +628,7 @@ __device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first,
   if (out->done) {
     if (threadIdx.x == 0) {
       in->done = 1;
+      in->iter = 0;
       in->counted = 0;
     }
     return;
@@ -639,20 +647,25 @@ __device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first,
     out->thresh = fmax(out->tol * rn, floor_b);
     out->iter = 0;
     out->linf = 0.0;
+    out->inner_total = 0;
     conv = fin && rn <= floor_b;
   } else {
+    out->inner_total += max(1, in->iter);
     out->iter += 1;
     out->linf = linf;
     conv = fin && ((rn <= out->thresh && (!out->linf_test || linf < out->tol)) || rn == 0.0);
   }
+  const int budget = out->max_iter - out->inner_total;
+  const bool stop = !fin || conv || out->iter >= max_outer || budget <= 0;
   out->rnorm = rn;
   out->nonfinite = fin ? 0 : 1;
   out->converged = conv ? 1 : 0;
-  out->done = (!fin || conv) ? 1 : 0;
+  out->done = stop ? 1 : 0;
+  if (stop && outer_done) atomicAdd(outer_done, 1u);
   // the inner solve A d = r stops at a reduction inner_tol of its own residual
   in->tol = inner_tol;
   in->abs_floor = 0.0;
-  in->max_iter = inner_max;
+  in->max_iter = max(1, budget);
   in->linf_test = 0;
   in->done = out->done;
   in->converged = 0;
@@ -776,9 +789,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(SweepPlan P, int kind, const 
   body_finish(int(blockIdx.x), P, kind, part, scs);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_finish(SweepPlan P, int first, double inner_tol, int inner_max,
+__global__ __launch_bounds__(kBlock) void k_ir_finish(SweepPlan P, int first, double inner_tol, int max_outer,
                                                       PcgScalars* outs, PcgScalars* ins, const double* part) {
-  body_ir_finish(int(blockIdx.x), P, first, inner_tol, inner_max, outs, ins, part);
+  body_ir_finish(int(blockIdx.x), P, first, inner_tol, max_outer, outs, ins, part, nullptr);
 }
 
 // All PCG iterations of every problem of the plan in one cooperative launch: the
@@ -795,13 +808,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan
                                                            unsigned spin_limit) {
   __shared__ unsigned n_done;
   const unsigned nb = gridDim.x;
-  unsigned epoch = 0;
+  dev::GridSync gs{bar, nb, spin_limit};
   for (int it = 1; it <= max_iter + 1; ++it) {
     T* pn = (it & 1) ? p1 : p0;
     const T* po = (it & 1) ? p0 : p1;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
       body_pass_a<T>(vb, L, P, it, A, diag, r, po, pn, q, scs, part);
-    if (!grid_barrier(bar, nb, epoch, spin_limit)) {
+    if (!grid_barrier(gs)) {
       if (threadIdx.x == 0) __hip_atomic_store(bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
@@ -812,10 +825,79 @@ __global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan
     if (n_done >= unsigned(P.n_prob)) break;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
       body_pass_b<T>(vb, L, P, it, diag, pn, q, x, r, scs, part);
-    if (!grid_barrier(bar, nb, epoch, spin_limit)) {
+    if (!grid_barrier(gs)) {
       if (threadIdx.x == 0) __hip_atomic_store(bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
+  }
+}
+
+// The whole mixed-precision solve of every problem of the plan in one cooperative
+// launch: rounds of (FP64 refinement sweep, outer stopping test, inner start, inner
+// scalars, FP32 inner PCG iterations) with a grid barrier after each phase, the
+// same bodies in the same order as the host-driven launches, so the results are
+// the same bits.  Every decision is made on the device (body_ir_finish); the loop
+// ends once every problem's refinement has stopped (a count read right after the
+// barrier that follows the outer test) and in any case after max_outer + 1
+// refinement sweeps; an inner solve ends once every problem's inner PCG stopped,
+// and in any case after inner_cap + 1 operator sweeps.  A barrier that times out
+// sets the abort flag and the block returns (the others time out in turn).
+__global__ __launch_bounds__(kBlock) void k_mixed_persistent(DevLevel L, SweepPlan P, MixedArgs M) {
+  __shared__ unsigned n_done;
+  const unsigned nb = gridDim.x;
+  dev::GridSync gs{M.bar, nb, M.spin_limit};
+  unsigned* inner_done = P.done_count;
+  unsigned* outer_done = M.bar + kBarOuterDone;
+  double* x_cur = M.x;
+  double* x_nxt = M.x_alt;
+  auto sync = [&]() -> bool {
+    if (grid_barrier(gs)) return true;
+    if (threadIdx.x == 0) __hip_atomic_store(M.bar + kBarAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  };
+  auto read_count = [&](unsigned* w) {
+    if (threadIdx.x == 0) n_done = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    return n_done;
+  };
+  for (int outer = 0; outer <= M.max_outer; ++outer) {
+    for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
+      body_ir_sweep(vb, L, P, M.A, M.diag, M.b, x_cur, outer == 0 ? nullptr : M.d32, x_nxt, M.r32, M.outer,
+                    M.part);
+    if (!sync()) return;
+    double* t = x_cur;
+    x_cur = x_nxt;
+    x_nxt = t;
+    for (int q = int(blockIdx.x); q < P.n_prob; q += int(nb))
+      body_ir_finish(q, P, outer == 0 ? 1 : 0, M.inner_tol, M.max_outer, M.outer, M.inner, M.part, outer_done);
+    // the inner stop count restarts for this round's inner solves (no block reads it
+    // again before the barrier below)
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      __hip_atomic_store(inner_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!sync()) return;
+    if (read_count(outer_done) >= unsigned(P.n_prob)) break;
+    for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
+      body_inner_init(vb, L, P, M.diag32, M.r32, M.d32, M.p32[0], M.outer, M.part);
+    if (!sync()) return;
+    for (int q = int(blockIdx.x); q < P.n_prob; q += int(nb)) body_init_finish(q, P, M.part, M.inner);
+    if (!sync()) return;
+    for (int it = 1; it <= M.inner_cap + 1; ++it) {
+      float* pn = M.p32[it & 1];
+      const float* po = M.p32[(it & 1) ^ 1];
+      for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
+        body_pass_a<float>(vb, L, P, it, M.A32, M.diag32, M.r32, po, pn, M.q32, M.inner, M.part);
+      if (!sync()) return;
+      // stops are counted only in the operator sweep (see k_pcg_persistent)
+      if (read_count(inner_done) >= unsigned(P.n_prob)) break;
+      for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
+        body_pass_b<float>(vb, L, P, it, M.diag32, pn, M.q32, M.d32, M.r32, M.inner, M.part);
+      if (!sync()) return;
+    }
+  }
+  // the last refinement sweep wrote x_cur: make it the caller's iterate
+  if (x_cur != M.x) {
+    for (int i = int(blockIdx.x) * kBlock + int(threadIdx.x); i < L.n_slots; i += int(nb) * kBlock)
+      M.x[i] = x_cur[i];
   }
 }
 
@@ -922,9 +1004,9 @@ void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const
                      part);
 }
 
-void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int inner_max,
+void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int max_outer,
                       PcgScalars* outer, PcgScalars* inner, const double* part) {
-  hipLaunchKernelGGL(k_ir_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, first, inner_tol, inner_max, outer,
+  hipLaunchKernelGGL(k_ir_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, first, inner_tol, max_outer, outer,
                      inner, part);
 }
 
@@ -995,6 +1077,32 @@ hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPl
   void* args[] = {&Lv, &Pv, &max_iter, &Av, (void*)&diag, &x, &r, &p0, &p1, &q, &sc, &part, &bar,
                   &spin_limit};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_pcg_persistent<T>), dim3(grid), dim3(kBlock),
+                                    args, unsigned(lds), s);
+}
+
+int mixed_persistent_blocks(const SweepPlan& P, int per_cu_cap) {
+  int dev = 0, cus = 0, per_cu = 0, coop = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(float);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_mixed_persistent),
+                                                   kBlock, lds) != hipSuccess)
+    return 0;
+  if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
+  return std::min(P.G, per_cu * cus);
+}
+
+hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const MixedArgs& M,
+                                   int per_cu_cap) {
+  const int grid = mixed_persistent_blocks(P, per_cu_cap);
+  if (grid <= 0) return hipErrorNotSupported;
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(float);
+  DevLevel Lv = L;
+  SweepPlan Pv = P;
+  MixedArgs Mv = M;
+  void* args[] = {&Lv, &Pv, &Mv};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_mixed_persistent), dim3(grid), dim3(kBlock),
                                     args, unsigned(lds), s);
 }
 

@@ -100,6 +100,10 @@ class HierarchySolver:
             self._check(st)
         return st
 
+    def restrict(self, fine_level):
+        """Restrict fine_level into its parent cells (as the driver does between levels)."""
+        self._check(L.amrfld_restrict_level(self.ctx, fine_level))
+
     def advance(self, dt, bc_mode=L.BC_DIRICHLET, tol=1e-10, raise_on_error=True):
         st = L.amrfld_advance_subcycled(self.ctx, dt, bc_mode, tol)
         if raise_on_error and st != L.OK:

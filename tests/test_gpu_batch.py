@@ -122,28 +122,34 @@ def test_batch_rejects_bad_patch():
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("graph,big", [(False, False), (True, False), (False, True), (True, True)])
-def test_batch_persistent_launch_equals_polled(graph, big):
+def test_batch_persistent_launch_equals_polled(graph, big, precision):
     # one cooperative launch per step (and all steps in one hipGraph) runs the same
     # sweep bodies over the same block plan: results and counts are bitwise equal.
-    # The big case spreads each patch over many blocks of up to 16 tiles, so the
-    # grid barrier must make neighbour values visible across XCDs.
+    # In mixed precision that launch runs the whole refinement loop of every patch,
+    # its decisions made on the device.  The big case spreads each patch over many
+    # blocks of up to 16 tiles, so the grid barrier must make neighbour values visible
+    # across XCDs.
+    from paper_1401_1112_amd import FP64, MIXED
+    prec = MIXED if precision == "mixed" else FP64
+    tol = 1e-10 if precision == "mixed" else 1e-12
     if big:
         patches, alpha = patch_batch(4900, 48, n_min=24, n_max=96)
     else:
         patches, alpha = patch_batch(4800, 12, n_min=4, n_max=24)
+    print(f"batch persistent vs polled: {precision}, graph {graph}, {len(patches)} patches", flush=True)
     s = _solver(robin_alpha=alpha)
-    a, _ = s.solve(patches, 3, 1e-12)
-    it_a = [x["iters"] for x in s.stats()]
+    a, _ = s.solve(patches, 3, tol, precision=prec)
+    it_a = [(x["iters"], x["outer_iters"]) for x in s.stats()]
     s.close()
     sp = _solver(robin_alpha=alpha, persistent=True, graph=graph)
-    b, st = sp.solve(patches, 3, 1e-12)
+    b, st = sp.solve(patches, 3, tol, precision=prec)
     stats = sp.stats()
     sp.close()
-    assert {x["launch_mode"] for x in stats} <= {1, 2}
-    if graph:
-        print("launch modes:", {x["launch_mode"] for x in stats})
-    assert [x["iters"] for x in stats] == it_a
+    assert {x["launch_mode"] for x in stats} == ({2} if graph else {1})
+    assert [(x["iters"], x["outer_iters"]) for x in stats] == it_a
+    assert all(x["converged"] == 1 for x in stats)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
 

@@ -223,21 +223,28 @@ def test_patch_batch_full_size_sampled(batch512):
     assert max(r for _, _, r in out2.values()) <= 1e-12
 
 
-def test_patch_batch_full_size_persistent_bitwise(batch512):
-    # every batch launch shape the autotuner may pick gives the polled results bitwise
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_patch_batch_full_size_persistent_bitwise(batch512, precision):
+    # every batch launch shape the autotuner may pick gives the polled results bitwise;
+    # in mixed precision the persistent launch runs each step's whole refinement loop
+    from paper_1401_1112_amd import FP64, MIXED
     from paper_1401_1112_amd.solver import BatchSolver
     patches, alpha = batch512
+    prec = MIXED if precision == "mixed" else FP64
     out = []
     for kw in ({}, {"persistent": True, "graph": True}, {"persistent": True, "persistent_per_cu": 1},
                {"persistent": True, "graph": True, "persistent_per_cu": 2}):
+        print(f"batch 512 {precision} {kw}", flush=True)
         bs = BatchSolver(robin_alpha=alpha, **kw)
         h = bs.upload(patches)
-        bs.run(h, 2, 1e-10)
-        out.append((bs.result(h), [x["iters"] for x in bs.stats()], max(x["launch_mode"] for x in bs.stats())))
+        bs.run(h, 2, 1e-10, prec)
+        st = bs.stats()
+        out.append((bs.result(h), [(x["iters"], x["outer_iters"]) for x in st], {x["launch_mode"] for x in st}))
         bs.close()
-    a, ia, _ = out[0]
+    a, ia, ma = out[0]
+    assert ma == {0}
     for b, ib, mode in out[1:]:
-        assert mode in (1, 2)
+        assert mode in ({1}, {2})
         assert ia == ib
         assert all(np.array_equal(x, y) for x, y in zip(a, b))
 

@@ -1,9 +1,10 @@
 """One coarse step of the subcycled driver captured as a hipGraph of persistent level
-solves and replayed (amrfld_opts.graph with persistent, FP64): every replay against the
-same steps run eagerly (host-polled sweeps, and one persistent launch per solve), bitwise
-with equal iteration counts, with the program's own eager work and synchronisations
-between the replays; a change of dt, of the fields or of the launch shape forces a new
-capture; mixed precision runs eagerly."""
+solves and replayed (amrfld_opts.graph with persistent): every replay against the same
+steps run eagerly (host-polled sweeps, and one persistent launch per solve), bitwise with
+equal iteration counts, with the program's own eager work and synchronisations between
+the replays; a change of dt, of the fields or of the launch shape forces a new capture.
+In mixed precision each captured solve is the whole refinement loop in one persistent
+launch, its decisions made on the device."""
 import numpy as np
 import pytest
 
@@ -102,11 +103,16 @@ def test_graph_launch_shape_change_recaptures():
     assert all(np.array_equal(res[0][0][l], res[1][0][l]) for l in res[0][0])
 
 
-def test_graph_mixed_runs_eagerly():
+@pytest.mark.parametrize("case", ["tiny_lp", "coupled"])
+@pytest.mark.parametrize("mode", [0, 2])
+def test_graph_mixed_replays_equal_eager(case, mode):
     from paper_1401_1112_amd import MIXED
-    p = config_tiny(0, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-10)
-    dts = [p.dt_coarse] * 2
-    a = _run(p, 0, dts, precision=MIXED, persistent=True, graph=True)
-    b = _run(p, 0, dts, precision=MIXED, persistent=True)
-    assert all(2 not in m for _, _, m in a)
-    _same(a, b)
+    p = CASES[case]()
+    dts = [p.dt_coarse] * 3
+    graph = _run(p, mode, dts, precision=MIXED, persistent=True, graph=True)
+    assert all(m == {2} for _, _, m in graph)
+    eager = _run(p, mode, dts, precision=MIXED, persistent=True)
+    assert all(m == {1} for _, _, m in eager)
+    polled = _run(p, mode, dts, precision=MIXED)
+    _same(graph, eager)
+    _same(graph, polled)
