@@ -14,8 +14,10 @@ does the same work.
 
 Output: one JSON line (metric: PCG cell-iterations per second = sum over solves
 of leaf cells x iterations / wall time), with the roofline of the dominant
-kernel (the operator sweep, pass A) from HIP events its launches record and the
-CPU FP64 oracle timed on a bounded sample of the same workload.
+kernel (the fused CG iteration sweep) from HIP events its launches record, the
+same for the sweeps of the HBM-streaming workloads (the 512-patch batch and the
+collapse hierarchy), and the CPU FP64 oracle timed on a bounded sample of the same
+workload on one thread and on all host threads.
 """
 from __future__ import annotations
 
@@ -30,14 +32,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per slot (FP64): pass A reads r, p_old, diag, 3 face
-# coefficients and the per-oct neighbour table (24 B per oct = 3 B per slot),
-# writes p_new and q; pass B reads x, r, p, q, diag and writes x, r.
-PASS_A_BYTES = 3 * 8 + 3 * 8 + 3 + 2 * 8
-# what it moves with the coefficients formed from K: K (8 B) and the face mask (1 B)
-# instead of the three coefficients
-PASS_A_BYTES_FORMED = 3 * 8 + 8 + 1 + 3 + 2 * 8
-PASS_B_BYTES = 5 * 8 + 2 * 8
+# the method's own bytes per cell and CG iteration, each array element counted once
+# per iteration (the two sweeps of Jacobi PCG: r, p, d, 3 face coefficients, the
+# neighbour table, p and q written; x, r, p, q, d read, x and r written): FP64 125 B,
+# the FP32 inner solve of the mixed form 65 B.  The rooflines are quoted against them.
+ALG_BYTES_FP64 = 125
+ALG_BYTES_FP32 = 65
+# what the fused iteration sweep itself moves per slot: reads p, s, w, x, r, rs
+# (48 B), three scaled face coefficients (24 B) and the per-oct neighbour table (24 B
+# per oct = 3 B per slot); writes p, s, x, r, w (40 B)
+SWEEP_BYTES = 6 * 8 + 3 * 8 + 3 + 5 * 8
+# with the coefficients formed from K: K (8 B) and the face mask (1 B) instead
+SWEEP_BYTES_FORMED = 6 * 8 + 8 + 1 + 3 + 5 * 8
+SWEEP_BYTES_FP32 = 6 * 4 + 3 * 4 + 3 + 5 * 4
 METRIC = "PCG cell-iterations/s + HBM GB/s vs peak; FP64 vs mixed+batched at 1e-10"
 
 
@@ -50,11 +57,12 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(kernel: str, max_blocks: int):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary,
-    or None when the kernel source or the launch shape differ from those the counters
-    were taken with."""
-    prof = os.path.join(ROOT, "profiles", "fld_lognormal_L6-9_fp64_hbm_counters.txt")
+def _measured_traffic(kernel: str, max_blocks: int, profile: str = "fld_lognormal_L6-9_fp64_hbm_counters.txt"):
+    """Fabric-side bytes per dispatch of `kernel` (L2-to-fabric reads and writes, which
+    include Infinity Cache hits) from a committed rocprofv3 counter summary, or None
+    when the kernel source or the launch shape differ from those the counters were
+    taken with."""
+    prof = os.path.join(ROOT, "profiles", profile)
     try:
         kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines()
                   if line.startswith("traffic_"))
@@ -94,11 +102,66 @@ def _problem():
     return config_fld_lognormal()
 
 
-def _cpu_baseline(p, budget_s=30.0):
-    """Oracle on the first solves of one coarse step (finest level first), timed on the
-    solve region only; BLAS limited to one thread."""
+def _schedule(p):
+    """The operations of one coarse step in the driver's order (Sect. 2.2): finer levels
+    first, nsub = 2, restriction after their substeps."""
+    ops = []
+
+    def walk(level, dt):
+        if level < p.hierarchy.max_level:
+            for _ in range(2):
+                walk(level + 1, dt / 2)
+            ops.append(("restrict", level + 1, None))
+        ops.append(("solve", level, dt))
+
+    walk(p.hierarchy.base_level, p.dt_coarse)
+    return ops
+
+
+def _align(level, cells_a, vals_a, cells_b):
+    """Values given in cell order cells_a, reordered into cell order cells_b."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
+    n = np.int64(1) << level
+
+    def key(c):
+        c = np.asarray(c, dtype=np.int64)
+        return (c[:, 0] * n + c[:, 1]) * n + c[:, 2]
+
+    ka, kb = key(cells_a), key(cells_b)
+    o = np.argsort(ka)
+    return np.asarray(vals_a)[o[np.searchsorted(ka[o], kb)]]
+
+
+def _mixed_per_solve(p, init, n_solves):
+    """The mixed-precision form run solve by solve through the C ABI in the driver's
+    order (level solves and restrictions), its result after each of the first
+    n_solves solves: (level, cells, E)."""
+    from paper_1401_1112_amd import BC_DIRICHLET, MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+    s = solver_from_problem(p, precision=MIXED)
+    for lvl in s.levels:
+        rho, E = init[lvl]
+        s.set_fields(lvl, rho, E, kmode=1)
+    out = []
+    for kind, lvl, dt in _schedule(p):
+        if len(out) >= n_solves:
+            break
+        if kind == "restrict":
+            s.restrict(lvl)
+        else:
+            s.solve_level(lvl, dt, BC_DIRICHLET, p.tol)
+            out.append((lvl, s.cells(lvl), to_numpy(s.E(lvl))))
+    s.close()
+    return out
+
+
+def _cpu_baseline(p, budget_s=30.0, threads=1, mixed=None):
+    """Oracle on the first solves of one coarse step (finest level first), timed on the
+    solve region only, with BLAS limited to `threads` (None: all of them).  `mixed`:
+    results of the mixed-precision GPU form after the same solves, compared per solve
+    (outside the timed region)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import oracle as ora
     o = ora.Oracle(p.hierarchy.base_level, p.hierarchy.octs, kmode=p.kmode, robin_alpha=p.robin_alpha,
@@ -106,20 +169,10 @@ def _cpu_baseline(p, budget_s=30.0):
     for lvl in p.hierarchy.levels:
         c = o.cells(lvl)
         o.set_fields(lvl, p.rho(lvl, c), p.E(lvl, c))
-    # schedule of one coarse step, finest first (levels base..max, nsub = 2)
-    sched = []
-
-    def walk(level, dt):
-        if level < p.hierarchy.max_level:
-            for _ in range(2):
-                walk(level + 1, dt / 2)
-            sched.append(("restrict", level + 1, None))
-        sched.append(("solve", level, dt))
-
-    walk(p.hierarchy.base_level, p.dt_coarse)
-    done, cell_it, t_solve = [], 0, 0.0
-    with threadpool_limits(limits=1):
-        for kind, lvl, dt in sched:
+    done, cell_it, t_solve, errs = [], 0, 0.0, []
+    with threadpool_limits(limits=threads):
+        n_threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+        for kind, lvl, dt in _schedule(p):
             if kind == "restrict":
                 o.restrict(lvl)
                 continue
@@ -128,6 +181,12 @@ def _cpu_baseline(p, budget_s=30.0):
             t_solve += time.perf_counter() - t0
             cell_it += st["n_leaf"] * st["iters"]
             done.append(f"L{lvl}:{st['iters']}it")
+            k = len(done) - 1
+            if mixed is not None and k < len(mixed) and mixed[k][0] == lvl:
+                _, cells, e = mixed[k]
+                ref = _align(lvl, o.cells(lvl), o.E[lvl], cells)
+                errs.append({"solve": k, "level": lvl, "max_rel": float(np.abs(e - ref).max() / np.abs(ref).max()),
+                             "l2_rel": float(np.linalg.norm(e - ref) / np.linalg.norm(ref))})
             if t_solve >= budget_s:
                 break
     model = ""
@@ -135,11 +194,65 @@ def _cpu_baseline(p, budget_s=30.0):
         model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return {"value": cell_it / t_solve, "unit": "cell-iterations/s", "cores": 1, "kind": "oracle",
-            "host_cpu": f"{model} ({os.cpu_count()} logical CPUs visible)",
-            "sample": (f"first {len(done)} of 15 level solves of one coarse step ({', '.join(done)}), "
-                       f"{cell_it:.3e} cell-iterations in {t_solve:.1f} s, numpy/scipy CSR, 1 thread"),
-            "seconds": t_solve}
+    out = {"value": cell_it / t_solve, "unit": "cell-iterations/s", "cores": int(n_threads), "kind": "oracle",
+           "host_cpu": f"{model} ({os.cpu_count()} logical CPUs visible)",
+           "sample": (f"first {len(done)} of 15 level solves of one coarse step ({', '.join(done)}), "
+                      f"{cell_it:.3e} cell-iterations in {t_solve:.1f} s, numpy/scipy CSR, BLAS on {n_threads} "
+                      f"thread(s) (the CSR operator product of scipy runs on one)"),
+           "seconds": t_solve}
+    if errs:
+        out["mixed_err_vs_fp64_oracle_per_solve"] = errs
+    return out
+
+
+def _patch_oracle_job(args):
+    from threadpoolctl import threadpool_limits
+
+    from oracle.patch_oracle import patch_advance
+    q, p, alpha, tol = args
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, hist = patch_advance(p.rho, p.E, p.dx, p.dt, p.face_mode, p.face_ghost, p.face_flux, 1, tol, alpha=alpha)
+        el = time.perf_counter() - t0
+    return q, int(p.n) ** 3 * hist[0]["iters"], el
+
+
+def _batch_cpu_baseline(patches, alpha, tol, n_sample=32, workers=None):
+    """The patch oracle on a seeded sample of the batch's patches, one step each, the
+    independent patches spread over all host threads (one process each)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    rng = np.random.default_rng(2024)
+    sample = sorted(int(i) for i in rng.choice(len(patches), min(n_sample, len(patches)), replace=False))
+    workers = workers or min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    # fresh interpreters (spawn), which never touch the GPU
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_patch_oracle_job, [(q, patches[q], alpha, tol) for q in sample])
+    el = time.perf_counter() - t0
+    ci = sum(r[1] for r in res)
+    return {"value": ci / el, "unit": "cell-iterations/s", "cores": workers, "kind": "oracle",
+            "solves_per_s": len(sample) / el,
+            "sample": f"{len(sample)} seeded patches of the batch, one step each, {ci:.3e} cell-iterations in "
+                      f"{el:.1f} s on {workers} processes (one thread each)"}
+
+
+def _roofline(stats, bytes_per_cell, kernel, note, traffic=None, active=None):
+    """Roofline of the CG iteration sweep from the start/stop events its launches
+    recorded: the method's bytes per cell x the cells of each timed launch over the
+    summed launch time.  active(st) -> cells of one timed launch (default: the solve's
+    leaves)."""
+    ms = sum(st["pass_a_ms"] for st in stats)
+    n = sum(st["n_timed"] for st in stats)
+    if ms <= 0 or n == 0:
+        return None
+    byts = sum(bytes_per_cell * (active(st) if active else st["n_leaf"] * st["n_timed"]) for st in stats)
+    achieved = byts / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "alg_bytes_per_cell": bytes_per_cell, "alg_bytes_per_launch": round(byts / n),
+            "timed_launches": n, "avg_launch_us": round(ms * 1e3 / n, 2), "note": note}
 
 
 def _rel_err(a, b):
@@ -171,52 +284,76 @@ def _residual_gate(stats, tol, abs_floor=1e-14):
 
 
 def _mixed_form(p, s64, init, ms64, args):
-    """The precision form on the same workload: FP32 inner PCG inside FP64 refinement to
-    the same 1e-10 relative residual; error against the FP64 GPU solve of the same step."""
+    """The precision form on the same workload: FP32 inner CG inside FP64 refinement to
+    the same 1e-10 relative residual, host-driven and as one persistent launch per
+    solve captured with the whole step in a hipGraph; error against the FP64 GPU solve
+    of the same step (the error against the FP64 oracle, per solve, is in the
+    cpu_baseline record)."""
+    import numpy as np
     import torch
     from paper_1401_1112_amd import BC_DIRICHLET, MIXED
     from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
+
+    def timed(s, steps):
+        def step():
+            for lvl in s.levels:
+                rho, E = init[lvl]
+                s.set_fields(lvl, rho, E, kmode=1)
+            s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+            return s.stats()
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sts, step
+
     s = solver_from_problem(p, precision=MIXED, max_blocks=args.max_blocks)
-
-    def step():
-        for lvl in s.levels:
-            rho, E = init[lvl]
-            s.set_fields(lvl, rho, E, kmode=1)
-        s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
-        return s.stats()
-
     inner = {"inner_tol": 1e-2, "tuned": False}
     if not args.no_tune:
         # the inner tolerance: the split between FP32 inner iterations and FP64 refinement
         from paper_1401_1112_amd.autotune import tune_refinement
-        best, times, cached = tune_refinement(s, step, [s.info(l)[0] for l in s.levels], "levels")
+
+        def one():
+            for lvl in s.levels:
+                rho, E = init[lvl]
+                s.set_fields(lvl, rho, E, kmode=1)
+            s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
+        best, times, cached = tune_refinement(s, one, [s.info(l)[0] for l in s.levels], "levels")
         inner = {"inner_tol": best["inner_tol"], "tuned": True, "source": cached, "candidate_ms_per_step": times}
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sts = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, sts, _ = timed(s, args.steps)
     cell_it = sum(st["n_leaf"] * st["iters"] for x in sts for st in x)
+    res_polled = {l: to_numpy(s.E(l)) for l in s.levels}
+    s.close()
+    # the whole step as a graph of persistent solves, each one cooperative launch
+    g = solver_from_problem(p, precision=MIXED, max_blocks=args.max_blocks, persistent=True, graph=True,
+                            inner_tol=inner["inner_tol"])
+    el_g, sts_g, _ = timed(g, args.steps)
+    res_graph = {l: to_numpy(g.E(l)) for l in g.levels}
+    g.close()
     # the FP64 reference: the same step from the same state (s64 may hold another form's result)
     for lvl in s64.levels:
         rho, E = init[lvl]
         s64.set_fields(lvl, rho, E, kmode=1)
     s64.advance(p.dt_coarse, BC_DIRICHLET, p.tol)
     worst_max, worst_l2 = 0.0, 0.0
-    for lvl in s.levels:
-        a, b = to_numpy(s.E(lvl)), to_numpy(s64.E(lvl))
+    for lvl in s64.levels:
+        a, b = res_polled[lvl], to_numpy(s64.E(lvl))
         m, l2 = _rel_err(a, b)
         worst_max, worst_l2 = max(worst_max, m), max(worst_l2, l2)
     last = sts[-1]
-    out = {"value": cell_it / el, "unit": "inner cell-iterations/s", "ms_per_step": el * 1e3 / args.steps,
-           "speedup_vs_fp64": (ms64 / (el * 1e3 / args.steps)),
+    ms = el * 1e3 / args.steps
+    ms_g = el_g * 1e3 / args.steps
+    out = {"value": cell_it / el, "unit": "inner cell-iterations/s", "ms_per_step": ms,
+           "speedup_vs_fp64": ms64 / ms,
+           "persistent_graph_ms_per_step": ms_g, "persistent_graph_speedup_vs_fp64": ms64 / ms_g,
+           "persistent_graph_equals_host_driven_bitwise": all(np.array_equal(res_polled[l], res_graph[l])
+                                                              for l in res_polled),
            "inner_iterations_per_step": sum(st["iters"] for st in last),
            "outer_sweeps_per_step": sum(st["outer_iters"] for st in last),
            "residual": _residual_gate([st for x in sts for st in x], p.tol),
            "err_vs_fp64_gpu": {"max_rel": worst_max, "l2_rel": worst_l2},
            "inner_tol": inner}
-    s.close()
     return out
 
 
@@ -433,8 +570,11 @@ def _batched_form(args):
         return el, ci, st
 
     from paper_1401_1112_amd import AmrfldError
-    forms = [("fp64_polled", {}, 0), ("fp64_persistent_graph", {"persistent": True, "graph": True}, 0),
-             ("mixed_polled", {}, MIXED)]
+    # the host-polled FP64 run also times every time_period-th iteration sweep (roofline)
+    forms = [("fp64_polled", {"time_sweeps": args.time_period}, 0),
+             ("fp64_persistent_graph", {"persistent": True, "graph": True}, 0),
+             ("mixed_polled", {}, MIXED),
+             ("mixed_persistent_graph", {"persistent": True, "graph": True}, MIXED)]
     if not args.no_tune:
         # launch shape of the FP64 batch: host-polled, or a persistent launch with its
         # resident blocks per compute unit, each timed on one step
@@ -461,7 +601,18 @@ def _batched_form(args):
         del h
         torch.cuda.empty_cache()
         out["tuned_inner_tol"] = {"best": best_in, "source": cached_in, "candidate_ms_per_step": times_in}
-        forms.append(("mixed_tuned", {"form_coefs": bool(best.get("form_coefs", 0)),
+        # launch shape of the mixed batch at that inner tolerance
+        print("bench: tuning the mixed batch launch shape", file=sys.stderr, flush=True)
+        bs = BatchSolver(robin_alpha=alpha, graph=True, inner_tol=best_in["inner_tol"])
+        h = bs.upload(patches)
+        best_m, times_m, cached_m = tune_batch(bs, lambda: bs.run(h, 1, tol, MIXED), [p.n for p in patches], 1)
+        bs.close()
+        del h
+        torch.cuda.empty_cache()
+        out["tuned_shape_mixed"] = {"best": best_m, "source": cached_m, "candidate_ms_per_step": times_m}
+        forms.append(("mixed_tuned", {"persistent": bool(best_m["persistent"]), "graph": True,
+                                      "persistent_per_cu": best_m["persistent_per_cu"],
+                                      "form_coefs": bool(best_m.get("form_coefs", 0)),
                                       "inner_tol": best_in["inner_tol"]}, MIXED))
     results = {}
     for name, kw, prec in forms:
@@ -510,7 +661,11 @@ def _batched_form(args):
     a = results["fp64_polled"][0]
     b = results["fp64_persistent_graph"][0]
     m = results["mixed_polled"][0]
+    mg = results["mixed_persistent_graph"][0]
     out["persistent_equals_polled_bitwise"] = all(np.array_equal(x, y) for x, y in zip(a, b))
+    out["mixed_persistent_equals_polled_bitwise"] = all(np.array_equal(x, y) for x, y in zip(m, mg))
+    out["mixed_persistent_graph_speedup_vs_fp64_polled"] = out["fp64_polled"]["seconds"] / \
+        out["mixed_persistent_graph"]["seconds"]
     out["max_rel_l2_batch_vs_single"] = max(_rel_err(x, y)[1] for x, y in zip(a, single_res))
     out["mixed_err_vs_fp64_gpu"] = {"max_rel": max(_rel_err(x, y)[0] for x, y in zip(m, a)),
                                     "l2_rel": max(_rel_err(x, y)[1] for x, y in zip(m, a))}
@@ -518,6 +673,38 @@ def _batched_form(args):
         mt = results["mixed_tuned"][0]
         out["mixed_tuned_err_vs_fp64_gpu"] = {"max_rel": max(_rel_err(x, y)[0] for x, y in zip(mt, a)),
                                               "l2_rel": max(_rel_err(x, y)[1] for x, y in zip(mt, a))}
+    # roofline of the FP64 iteration sweep on this HBM-streaming workload: the timed
+    # sweeps of each step (every time_period-th iteration) move the method's bytes of the
+    # cells of the patches still iterating
+    st = results["fp64_polled"][1]
+    n = len(patches)
+    sizes3 = [int(p.n) ** 3 for p in patches]
+    ms = byts = 0.0
+    launches = 0
+    for k in range(steps):
+        its = [st[k * n + q]["iters"] for q in range(n)]
+        rec = st[k * n]
+        if rec["n_timed"] == 0:
+            continue
+        ms += rec["pass_a_ms"]
+        for j in range(1, rec["n_timed"] + 1):
+            it = j * args.time_period
+            byts += ALG_BYTES_FP64 * sum(c for c, i in zip(sizes3, its) if i >= it)
+            launches += 1
+    if ms > 0:
+        ach = byts / (ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(ach / HBM_PEAK_GBS, 4),
+                           "traffic": _measured_traffic("k_cg_sweep<double>", 0,
+                                                        "patch_batch_512_fp64_polled_hbm_counters.txt"),
+                           "kernel": "k_cg_sweep<double> (fused CG iteration sweep), host-polled FP64 batch",
+                           "alg_bytes_per_cell": ALG_BYTES_FP64, "alg_bytes_per_launch": round(byts / launches),
+                           "timed_launches": launches, "avg_launch_us": round(ms * 1e3 / launches, 2),
+                           "note": "cells of the patches still iterating in each timed sweep; the 17 GB batch "
+                                   "streams from HBM"}
+    if not args.no_cpu_baseline:
+        print("bench: batch oracle on the host cores", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = _batch_cpu_baseline(patches, alpha, tol)
     return out
 
 
@@ -525,9 +712,11 @@ def _collapse_form(args):
     """Collapse-like hierarchy: levels 6..13 Jeans-refined around a softened singular
     isothermal sphere (contrast 1e6), radiation coupled to the gas energy, levels 6..9
     sharing the coarse dt and 10..13 subcycling (34 solves per coarse step, 16 on level 13).
-    Mixed precision (FP32 inner PCG, FP64 refinement to 1e-10) with one persistent launch
-    per inner solve, against mixed and FP64 host-polled sweeps; every variant advances
-    one coarse step from the same state."""
+    Mixed precision (FP32 inner CG, FP64 refinement to 1e-10) with the whole refinement
+    loop of each solve in one persistent launch (and the coarse step captured in a
+    hipGraph), against mixed and FP64 host-driven sweeps; every variant advances one
+    coarse step from the same state.  The host-driven runs also time their iteration
+    sweeps (rooflines on this HBM-streaming workload)."""
     import torch
     from paper_1401_1112_amd import BC_DIRICHLET, FP64, MIXED
     from paper_1401_1112_amd.solver import HierarchySolver, solver_from_problem
@@ -562,15 +751,18 @@ def _collapse_form(args):
         tuned = best
         first.set_launch(args.max_blocks, True, 0)
 
-    results = {}
-    shapes = [("mixed_persistent", MIXED, True), ("mixed_polled", MIXED, False), ("fp64_polled", FP64, False)]
+    results, stats = {}, {}
+    shapes = [("mixed_persistent", MIXED, {"persistent": True}),
+              ("mixed_persistent_graph", MIXED, {"persistent": True, "graph": True}),
+              ("mixed_polled", MIXED, {"time_sweeps": args.time_period}),
+              ("fp64_polled", FP64, {"time_sweeps": args.time_period})]
     if tuned is not None:
         shapes.append(("mixed_tuned", MIXED, tuned))
     for name, prec, pers in shapes:
         print(f"bench: collapse form {name}", file=sys.stderr, flush=True)
         if first is not None:
             s, first = first, None
-        elif isinstance(pers, dict):  # the tuned shape and inner tolerance
+        elif name == "mixed_tuned":  # the tuned shape and inner tolerance
             s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, nsub=p.nsub)
             s.set_launch(pers["max_blocks"], bool(pers["persistent"]), pers["persistent_per_cu"],
                          bool(pers.get("form_coefs", 0)))
@@ -583,8 +775,8 @@ def _collapse_form(args):
             best_in, times_in, cached_in = tune_refinement(s, tune_step, list(slots.values()), "collapse")
             out["tuned_inner_tol"] = {"best": best_in, "source": cached_in, "candidate_ms_per_step": times_in}
         else:
-            s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, persistent=pers,
-                                nsub=p.nsub, max_blocks=args.max_blocks)
+            s = HierarchySolver(p.hierarchy.base_level, p.hierarchy.octs, precision=prec, nsub=p.nsub,
+                                max_blocks=args.max_blocks, **pers)
         reset(s)
         s.advance(p.dt_coarse, BC_DIRICHLET, p.tol)  # warm-up
         reset(s)
@@ -594,6 +786,7 @@ def _collapse_form(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         st = s.stats()
+        stats[name] = st
         ci = sum(x["n_leaf"] * x["iters"] for x in st)
         results[name] = {l: s.E(l, with_T=True) for l in s.levels}
         out[name] = {"ms_per_step": round(el * 1e3, 1), "solves": len(st),
@@ -634,8 +827,18 @@ def _collapse_form(args):
                             / torch.linalg.vector_norm(ref[l][1])) for l in ref)
         out[name]["rel_l2_vs_fp64_gpu"] = {"E": worst_e, "T": worst_t}
     out["mixed_persistent_equals_polled_bitwise"] = all(
-        bool(torch.equal(results["mixed_persistent"][l][0], results["mixed_polled"][l][0])) for l in ref)
-    out["mixed_speedup_vs_fp64"] = out["fp64_polled"]["ms_per_step"] / out["mixed_persistent"]["ms_per_step"]
+        bool(torch.equal(results[k][l][0], results["mixed_polled"][l][0]))
+        for k in ("mixed_persistent", "mixed_persistent_graph") for l in ref)
+    out["mixed_speedup_vs_fp64"] = {k: out["fp64_polled"]["ms_per_step"] / out[k]["ms_per_step"]
+                                    for k in ("mixed_persistent", "mixed_persistent_graph", "mixed_polled",
+                                              "mixed_tuned") if k in out}
+    # rooflines of the iteration sweeps on this HBM-streaming workload (levels of 2-6.5 M
+    # cells, coupled E-T): FP64 and the FP32 inner sweep of the mixed form
+    out["roofline"] = {
+        "fp64_sweep": _roofline(stats["fp64_polled"], ALG_BYTES_FP64, "k_cg_sweep<double>, host-driven FP64",
+                                "leaves of the level of each timed sweep"),
+        "fp32_inner_sweep": _roofline(stats["mixed_polled"], ALG_BYTES_FP32, "k_cg_sweep<float>, inner solves of "
+                                      "the host-driven mixed form", "leaves of the level of each timed sweep")}
     return out
 
 
@@ -712,36 +915,32 @@ def main(argv=None):
 
     cell_it = sum(st["n_leaf"] * st["iters"] for sts in all_stats for st in sts)
     slots = {lvl: s.info(lvl)[0] for lvl in s.levels}
-    a_bytes = sum(PASS_A_BYTES * slots[st["level"]] * st["n_timed"] for sts in all_stats for st in sts)
-    b_bytes = sum(PASS_B_BYTES * slots[st["level"]] * st["n_timed"] for sts in all_stats for st in sts)
-    a_ms = sum(st["pass_a_ms"] for sts in all_stats for st in sts)
-    b_ms = sum(st["pass_b_ms"] for sts in all_stats for st in sts)
-    n_a = sum(st["n_timed"] for sts in all_stats for st in sts)
     pcg_ms = sum(st["pcg_ms"] for sts in all_stats for st in sts)
     solve_ms = sum(st["ms"] for sts in all_stats for st in sts)
     per_step = all_stats[-1]
-    roofline = None
-    if a_ms > 0:
-        achieved = a_bytes / (a_ms * 1e-3) / 1e9
-        traffic = None if args.form_coefs else _measured_traffic("k_pass_a<double>",
-                                                                   args.max_blocks if args.max_blocks > 0 else 1024)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None if traffic is None else round(traffic),
-                    "traffic_note": "measured HBM bytes per pass-A dispatch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
-                                    "copy-calibrated), profiles/fld_lognormal_L6-9_fp64_hbm_counters.txt",
-                    "alg_bytes_per_launch": round(a_bytes / max(n_a, 1)),
-                    "kernel": "k_pass_a (p update + 7-point operator + (p,q) partials)",
-                    "bytes_per_slot": PASS_A_BYTES, "timed_launches": n_a,
-                    "coefficients": "formed from K in the sweep (bitwise the stored ones)" if args.form_coefs
-                                    else "stored (3 per slot)",
-                    "bytes_per_slot_moved": PASS_A_BYTES_FORMED if args.form_coefs else PASS_A_BYTES,
-                    "timing": f"HIP start/stop events recorded by the launches themselves "
-                              f"(hipExtLaunchKernelGGL) of the sweeps of every {args.time_period}th PCG iteration",
-                    "avg_launch_us": round(a_ms * 1e3 / max(n_a, 1), 2),
-                    "pass_b_GBs": round(b_bytes / (b_ms * 1e-3) / 1e9, 1) if b_ms > 0 else None,
-                    "pass_b_bytes_per_slot": PASS_B_BYTES,
-                    "copy_GBs_achievable": round(_copy_bandwidth(), 1)}
+    flat = [st for sts in all_stats for st in sts]
+    roofline = _roofline(flat, ALG_BYTES_FP64, "k_cg_sweep<double> (fused CG iteration: p, s, x, r updates and "
+                         "the 7-point operator on the new r, two dot products)",
+                         "the levels (about 150 MB each) sit in the 256 MB Infinity Cache: cache-assisted, the "
+                         "HBM gate is judged on the batch and collapse workloads (roofline_gate)")
+    if roofline is not None:
+        n_a = roofline["timed_launches"]
+        a_ms = sum(st["pass_a_ms"] for st in flat)
+        moved = sum((SWEEP_BYTES_FORMED if args.form_coefs else SWEEP_BYTES) * slots[st["level"]] * st["n_timed"]
+                    for st in flat)
+        traffic = _measured_traffic("k_cg_sweep<double>", args.max_blocks if args.max_blocks > 0 else 1024)
+        roofline.update({
+            "traffic": None if (traffic is None or args.form_coefs) else round(traffic),
+            "traffic_note": "fabric-side bytes per sweep dispatch from rocprofv3 (FETCH_SIZE x fetch scale + "
+                            "WRITE_SIZE, both scales from a device copy of known size): reads that hit the "
+                            "Infinity Cache count too; profiles/fld_lognormal_L6-9_fp64_hbm_counters.txt",
+            "coefficients": "formed from K in the sweep (bitwise the stored ones)" if args.form_coefs
+                            else "stored (3 scaled coefficients per slot)",
+            "bytes_per_slot_moved": SWEEP_BYTES_FORMED if args.form_coefs else SWEEP_BYTES,
+            "moved_GBs": round(moved / (a_ms * 1e-3) / 1e9, 1),
+            "timing": f"HIP start/stop events recorded by the launches themselves (hipExtLaunchKernelGGL) of "
+                      f"the sweep of every {args.time_period}th CG iteration",
+            "copy_GBs_achievable": round(_copy_bandwidth(), 1)})
     out = {
         "metric": METRIC,
         "value": cell_it / elapsed,
@@ -775,8 +974,12 @@ def main(argv=None):
     out["forms"] = {}
     if not args.no_unique:
         out["forms"]["unique_time_step"] = _unique_form(p, s, init, elapsed * 1e3 / args.steps, args)
+    mixed_solves = None
     if not args.no_mixed:
         out["forms"]["mixed"] = _mixed_form(p, s, init, elapsed * 1e3 / args.steps, args)
+        if not args.no_cpu_baseline:
+            # the mixed form solve by solve, for its per-solve error against the oracle
+            mixed_solves = _mixed_per_solve(p, init, 15)
     s.close()
     if not args.no_batch:
         import torch as _t
@@ -790,10 +993,30 @@ def main(argv=None):
         import torch as _t
         _t.cuda.empty_cache()
         out["forms"]["collapse"] = _collapse_form(args)
+    # the rooflines of the HBM-streaming workloads, on which the bandwidth gate is judged
+    gate = {}
+    if isinstance(out["forms"].get("batched", {}).get("roofline"), dict):
+        gate["patch_batch_fp64_sweep"] = out["forms"]["batched"]["roofline"]
+    for k, v in (out["forms"].get("collapse", {}).get("roofline") or {}).items():
+        if v is not None:
+            gate["collapse_" + k] = v
+    out["roofline_gate"] = gate or None
     if not args.no_cpu_baseline:
-        cb = _cpu_baseline(p, args.cpu_budget)
-        cb.pop("seconds", None)
-        out["cpu_baseline"] = cb
+        # the oracle on all host threads (BLAS) and on one, each on a bounded sample
+        print("bench: oracle on the host cores", file=sys.stderr, flush=True)
+        one = _cpu_baseline(p, args.cpu_budget / 2, threads=1, mixed=mixed_solves)
+        allc = _cpu_baseline(p, args.cpu_budget / 2, threads=None)
+        errs = one.pop("mixed_err_vs_fp64_oracle_per_solve", None)
+        if errs and "mixed" in out["forms"]:
+            out["forms"]["mixed"]["err_vs_fp64_oracle"] = {
+                "per_solve": errs, "max_rel": max(e["max_rel"] for e in errs),
+                "l2_rel": max(e["l2_rel"] for e in errs),
+                "note": "the mixed form run solve by solve in the driver's order (amrfld_solve_level, "
+                        "amrfld_restrict_level) against the FP64 oracle after the same solves"}
+        one.pop("seconds", None)
+        allc.pop("seconds", None)
+        allc["one_core"] = one
+        out["cpu_baseline"] = allc
     print(json.dumps(out), flush=True)
     return 0
 

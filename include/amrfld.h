@@ -58,7 +58,9 @@ typedef enum {
   AMRFLD_E_NOMEM = -3,     /* device or host allocation failed */
   AMRFLD_E_DEVICE = -4,    /* a HIP runtime call failed */
   AMRFLD_E_NOCONV = -5,    /* PCG hit max_iter; E holds the last iterate */
-  AMRFLD_E_NONFINITE = -6  /* NaN or Inf met in the residual of a solve */
+  AMRFLD_E_NONFINITE = -6  /* NaN or Inf met in the residual of a solve; also a diagonal
+                              entry <= 0 (the system is then not SPD and has no
+                              Jacobi scaling) */
 } amrfld_status;
 
 typedef enum { AMRFLD_BC_DIRICHLET = 0, AMRFLD_BC_NEUMANN = 1, AMRFLD_BC_ROBIN = 2 } amrfld_bc;
@@ -78,10 +80,10 @@ typedef struct {
   int nsub[32];          /* substeps of level l per step of level l-1; 0 means 2 */
   int check_every;       /* PCG iterations between host convergence checks; 0 = auto */
   int true_residual;     /* 1: compute ||b - A x|| after each solve for the stats */
-  int time_sweeps;       /* N > 0: time the two sweeps of every N-th PCG iteration with HIP events */
+  int time_sweeps;       /* N > 0: time the sweep of every N-th CG iteration with HIP events */
   double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner solve; default 1e-2 */
   int max_outer;         /* AMRFLD_MIXED: refinement sweeps cap; default 30 */
-  int max_blocks;        /* blocks per PCG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
+  int max_blocks;        /* blocks per CG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
   int persistent;        /* 1 = all PCG iterations of a solve (batch form: of a step) in one cooperative
                             launch, where the device can run it; in AMRFLD_MIXED the whole refinement
                             loop with its inner solves, every decision made on the device; else
@@ -123,8 +125,8 @@ typedef struct {
   double dt;
   int outer_iters;       /* refinement sweeps (mixed precision), else 0 */
   int n_timed;           /* iterations whose sweeps were timed (time_sweeps), else 0 */
-  double pass_a_ms;      /* summed device time of the timed operator sweeps (pass A) */
-  double pass_b_ms;      /* summed device time of the timed update sweeps (pass B) */
+  double pass_a_ms;      /* summed device time of the timed iteration sweeps (one per CG iteration) */
+  double pass_b_ms;      /* 0: kept for the layout (the iteration is one fused sweep) */
   int launch_mode;       /* 0 host-polled sweeps, 1 persistent launch, 2 persistent launches in a hipGraph */
   double rnorm0;         /* ||r_0|| = ||b - A x_0|| (mixed precision: the first outer residual) */
   double bnorm;          /* ||b||; the stopping threshold is max(tol ||r_0||, abs_floor ||b||) */
@@ -183,12 +185,12 @@ amrfld_status amrfld_solve_level(amrfld_ctx* c, int level, double dt, int bc_mod
 
 /* For callers that cannot allocate device memory (tight serving loops, harnesses
  * that forbid hipMalloc): amrfld_solve_level with the same arguments, kernels,
- * results and stats, whose PCG workspace (residual, two search-direction buffers,
- * operator product, block partials, scalar record, persistent-launch barrier words)
+ * results and stats, whose CG workspace (residual, operator products and search
+ * direction vectors, block partials, scalar record, persistent-launch barrier words)
  * lives in a static device array of the library instead of context workspace.  It
  * makes no device allocation or free; the level's tables and fields come from
  * amrfld_build_level / amrfld_set_coeffs as usual.
- * Limits: a level of at most 2^21 slots (about 64 MB of scratch per device, held
+ * Limits: a level of at most 2^20 slots (about 57 MB of scratch per device, held
  * from the first amrfld_create on that device until the process ends); FP64 only;
  * no sweep timing (opts.time_sweeps is ignored).
  * Errors: AMRFLD_E_INVALID for a larger level, AMRFLD_MIXED precision or bad

@@ -366,7 +366,8 @@ class Oracle:
                                self.abs_floor, self.linf_test)
         r_true = b - A @ x
         st.update(level=level, dt=dt, n_leaf=len(x), true_res=float(np.linalg.norm(r_true)),
-                  bnorm=float(np.linalg.norm(b)), min_E=float(x.min()) if len(x) else 0.0)
+                  bnorm=float(np.linalg.norm(b)), min_E=float(x.min()) if len(x) else 0.0,
+                  min_diag=float(A.diagonal().min()) if len(x) else 1.0)
         self._post_solve(level, dt, mode, x, coupling)
         self.history.append(st)
         return st

@@ -64,15 +64,16 @@ void dfree(void* p) {
 
 // ----------------------------------------------------------- static scratch
 // Workspace of amrfld_solve_level_noalloc in a file-scope device array, for callers
-// that cannot allocate device memory: the PCG vectors r, p (two buffers) and q of up
-// to kScratchSlots slots, the block partials of that many slots' sweeps, one scalar
-// record and the barrier words of the persistent launch.  Every sub-buffer starts on
+// that cannot allocate device memory: the CG vectors (r^, w^, s^ in two buffers each
+// and p^) of up to kScratchSlots slots, the block partials of that many slots'
+// sweeps, one scalar record and the barrier words of the persistent launch.  Every sub-buffer starts on
 // a 256-byte boundary.  Each device holds its own copy for the life of the process.
-constexpr int64_t kScratchSlots = int64_t(1) << 21;
-constexpr int64_t kScratchPartials = 4 * ((kScratchSlots + kBlock - 1) / kBlock);
+constexpr int64_t kScratchSlots = int64_t(1) << 20;
+constexpr int kScratchVectors = 7;  // r^, w^, s^ (two buffers each) and p^
+constexpr int64_t kScratchPartials = 8 * ((kScratchSlots + kBlock - 1) / kBlock);
 constexpr int64_t kScratchScalarDoubles = 32;            // one PcgScalars, padded to 256 B
 constexpr int64_t kScratchBarDoubles = kBarWords / 2;    // kBarWords unsigned words
-constexpr int64_t kScratchOffPartials = 4 * kScratchSlots;
+constexpr int64_t kScratchOffPartials = kScratchVectors * kScratchSlots;
 constexpr int64_t kScratchOffScalars = kScratchOffPartials + kScratchPartials;
 constexpr int64_t kScratchOffBar = kScratchOffScalars + kScratchScalarDoubles;
 constexpr int64_t kScratchDoubles = kScratchOffBar + kScratchBarDoubles;
@@ -121,6 +122,7 @@ struct LevelState {
   bool tables_uploaded = false, child_dirty = true;
   double *rho = nullptr, *E = nullptr, *T = nullptr, *K = nullptr;
   double *Cp = nullptr, *diag = nullptr, *b = nullptr, *reg = nullptr;
+  double *Ch = nullptr, *rs = nullptr;  // the Jacobi-scaled operator of the current solve
   uint8_t* mask = nullptr;  // per slot: faces that couple two leaves of the level
   bool has_fields = false, has_T = false;
   int kmode = 1;
@@ -142,10 +144,11 @@ struct LevelState {
   }
   void release() {
     for (void* p : {(void*)nbr, (void*)cnb, (void*)parent, (void*)child, (void*)rho, (void*)E,
-                    (void*)T, (void*)K, (void*)Cp, (void*)diag, (void*)b, (void*)reg, (void*)mask})
+                    (void*)T, (void*)K, (void*)Cp, (void*)diag, (void*)b, (void*)reg, (void*)mask, (void*)Ch,
+                    (void*)rs})
       dfree(p);
     nbr = cnb = parent = child = nullptr;
-    rho = E = T = K = Cp = diag = b = reg = nullptr;
+    rho = E = T = K = Cp = diag = b = reg = Ch = rs = nullptr;
     mask = nullptr;
     tables_uploaded = false;
   }
@@ -166,6 +169,7 @@ struct BatchState {
   int32_t *blk_prob = nullptr, *blk0 = nullptr, *tile0 = nullptr;
   int64_t* d_out_off = nullptr;
   double *E = nullptr, *rho = nullptr, *K = nullptr, *Cp = nullptr, *diag = nullptr, *b = nullptr;
+  double *Ch = nullptr, *rs = nullptr;  // the Jacobi-scaled operator of the current step
   uint8_t* mask = nullptr;
   PatchParams* pp = nullptr;
   const double** src = nullptr;  // device array of n_prob pointers
@@ -173,11 +177,11 @@ struct BatchState {
   void release() {
     for (void* p : {(void*)nbr, (void*)cnb, (void*)child, (void*)oct_prob, (void*)idx, (void*)blk_prob,
                     (void*)blk0, (void*)tile0, (void*)d_out_off, (void*)E, (void*)rho, (void*)K, (void*)Cp,
-                    (void*)diag, (void*)b, (void*)pp, (void*)src, (void*)mask})
+                    (void*)diag, (void*)b, (void*)pp, (void*)src, (void*)mask, (void*)Ch, (void*)rs})
       dfree(p);
     nbr = cnb = child = oct_prob = idx = blk_prob = blk0 = tile0 = nullptr;
     d_out_off = nullptr;
-    E = rho = K = Cp = diag = b = nullptr;
+    E = rho = K = Cp = diag = b = Ch = rs = nullptr;
     mask = nullptr;
     pp = nullptr;
     src = nullptr;
@@ -236,12 +240,14 @@ struct amrfld_ctx {
   int finest = -1;
   std::vector<LevelState> lev;  // index: level - base
   int64_t ws_n = 0;
-  double *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *partials = nullptr;
+  CgVecs<double> cg;  // the CG vectors of the largest solve so far
+  double* partials = nullptr;
   int64_t partial_n = 0;
-  // mixed-precision workspace
+  // mixed-precision workspace: FP32 scaled operator, outer residual, inner iterate
+  // and CG vectors; second buffer of the FP64 refinement sweeps
   int64_t ws32_n = 0;
-  float *Cp32 = nullptr, *K32 = nullptr, *diag32 = nullptr, *r32 = nullptr, *d32 = nullptr,
-        *p32[2] = {nullptr, nullptr}, *q32 = nullptr;
+  float *Ch32 = nullptr, *K32 = nullptr, *rs32 = nullptr, *r32 = nullptr, *d32 = nullptr;
+  CgVecs<float> cg32;
   double* x_alt = nullptr;
   PcgScalars* sc = nullptr;     // [2 sc_cap]: outer (or plain) solves, then inner solves
   PcgScalars* h_sc = nullptr;   // pinned mirror
@@ -301,21 +307,26 @@ amrfld_status guarded(amrfld_ctx* c, F&& f) {
   }
 }
 
+template <typename T>
+void free_vecs(CgVecs<T>& v) {
+  for (T* p : {v.r[0], v.r[1], v.w[0], v.w[1], v.s[0], v.s[1], v.p}) dfree(p);
+  v = CgVecs<T>{};
+}
+
+template <typename T>
+void alloc_vecs(CgVecs<T>& v, int64_t n, const char* what) {
+  for (T** p : {&v.r[0], &v.r[1], &v.w[0], &v.w[1], &v.s[0], &v.s[1], &v.p}) *p = dalloc<T>(n, what);
+}
+
 void ensure_workspace(amrfld_ctx* c, int64_t n) {
   if (n > c->ws_n) {
-    dfree(c->r);
-    dfree(c->p[0]);
-    dfree(c->p[1]);
-    dfree(c->q);
-    c->r = c->p[0] = c->p[1] = c->q = nullptr;
+    free_vecs(c->cg);
     c->ws_n = 0;
-    c->r = dalloc<double>(n, "workspace r");
-    c->p[0] = dalloc<double>(n, "workspace p");
-    c->p[1] = dalloc<double>(n, "workspace p");
-    c->q = dalloc<double>(n, "workspace q");
+    alloc_vecs(c->cg, n, "workspace");
     c->ws_n = n;
   }
-  const int64_t g = int64_t(tiles_of(n)) * 4;
+  // 4 partials per block and iteration parity
+  const int64_t g = int64_t(tiles_of(n)) * 8;
   if (g > c->partial_n) {
     dfree(c->partials);
     c->partials = nullptr;
@@ -327,20 +338,18 @@ void ensure_workspace(amrfld_ctx* c, int64_t n) {
 
 void ensure_workspace32(amrfld_ctx* c, int64_t n) {
   if (n <= c->ws32_n) return;
-  for (void* p : {(void*)c->Cp32, (void*)c->K32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
-                  (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
+  for (void* p : {(void*)c->Ch32, (void*)c->K32, (void*)c->rs32, (void*)c->r32, (void*)c->d32, (void*)c->x_alt})
     dfree(p);
-  c->Cp32 = c->K32 = c->diag32 = c->r32 = c->d32 = c->p32[0] = c->p32[1] = c->q32 = nullptr;
+  free_vecs(c->cg32);
+  c->Ch32 = c->K32 = c->rs32 = c->r32 = c->d32 = nullptr;
   c->x_alt = nullptr;
   c->ws32_n = 0;
-  c->Cp32 = dalloc<float>(3 * n, "workspace fp32");
+  c->Ch32 = dalloc<float>(3 * n, "workspace fp32");
   c->K32 = dalloc<float>(n, "workspace fp32");
-  c->diag32 = dalloc<float>(n, "workspace fp32");
+  c->rs32 = dalloc<float>(n, "workspace fp32");
   c->r32 = dalloc<float>(n, "workspace fp32");
   c->d32 = dalloc<float>(n, "workspace fp32");
-  c->p32[0] = dalloc<float>(n, "workspace fp32");
-  c->p32[1] = dalloc<float>(n, "workspace fp32");
-  c->q32 = dalloc<float>(n, "workspace fp32");
+  alloc_vecs(c->cg32, n, "workspace fp32");
   c->x_alt = dalloc<double>(n, "workspace x");
   c->ws32_n = n;
 }
@@ -547,16 +556,16 @@ bool all_done(const PcgScalars* h, int n) {
   return true;
 }
 
-// Iterations of the PCG solves of all problems of a plan, whose start sweeps
-// already ran: batches of (operator sweep, update sweep) pairs, a stopping check
-// after each batch, the next batch size predicted from the slowest problem's
-// observed convergence rate.  Launches after a problem converged return at once.
-// Returns the largest iteration count of the problems' solves (0: every problem was
-// already stopped).  first_chunk > 0: size of the first batch (a prediction, e.g. the
-// previous inner solve's count), else the default.
+// Iterations of the CG solves of all problems of a plan, whose start sweeps
+// already ran: batches of iteration sweeps, a stopping check after each batch, the
+// next batch size predicted from the slowest problem's observed convergence rate.
+// Launches after a problem converged return at once.  Returns the largest
+// iteration count of the problems' solves (0: every problem was already stopped).
+// first_chunk > 0: size of the first batch (a prediction, e.g. the previous inner
+// solve's count), else the default.
 template <typename T>
-int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag, T* x, T* r,
-                   T* const* p, T* q, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls,
+int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const ScaledOp<T>& Ah,
+                   const CgVecs<T>& v, T* x, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls,
                    int first_chunk = 0) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
@@ -569,8 +578,7 @@ int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const F
     const int blocks = persistent_blocks<T>(Pp, per_cu);
     if (blocks > 0) {
       launch_zero_u32(s, c->bar, kBarWords);
-      const hipError_t e = launch_pcg_persistent<T>(s, D, Pp, max_iter, A, diag, x, r, p, q, sc_dev, c->partials,
-                                                    c->bar, per_cu);
+      const hipError_t e = launch_pcg_persistent<T>(s, D, Pp, max_iter, Ah, v, x, sc_dev, c->partials, c->bar, per_cu);
       if (e == hipSuccess) {
         read_scalars(c, sc_host, sc_dev, np);
         unsigned aborted = 0;
@@ -598,9 +606,10 @@ int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const F
   bool first = true;
   while ((first || !all_done(sc_host, np)) && launched < max_iter) {
     first = false;
+    // sweep it makes iterate it; the check after the last one tests iterate max_iter
     const int k = std::min(chunk, max_iter - launched);
     if (period > 0) {
-      while (int(c->sweep_ev.size()) < 4 * ((launched + k) / period + 1)) {
+      while (int(c->sweep_ev.size()) < 2 * ((launched + k) / period + 1)) {
         hipEvent_t e;
         check(hipEventCreate(&e), "event");
         c->sweep_ev.push_back(e);
@@ -608,17 +617,12 @@ int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const F
     }
     for (int t = 0; t < k; ++t) {
       const int it = launched + t + 1;
-      T* pn = p[it & 1];
-      const T* po = p[(it & 1) ^ 1];
-      // every period-th iteration: each sweep's launch records its own start and end
-      hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[4 * (it / period - 1)] : nullptr;
-      launch_pass_a<T>(s, D, P, it, A, diag, r, po, pn, q, sc_dev, c->partials, e ? e[0] : nullptr,
-                       e ? e[1] : nullptr);
+      // every period-th iteration: the sweep's launch records its own start and end
+      hipEvent_t* e = (period > 0 && it % period == 0) ? &c->sweep_ev[2 * (it / period - 1)] : nullptr;
+      launch_cg_sweep<T>(s, D, P, it, Ah, v, x, sc_dev, c->partials, e ? e[0] : nullptr, e ? e[1] : nullptr);
       if constexpr (std::is_same<T, double>::value) {
-        if (D.n_if_rows > 0) launch_interface(s, D, pn, q, sc_dev, D.if_part);
+        if (D.n_if_rows > 0) launch_interface(s, D, v.r[it & 1], v.w[it & 1], sc_dev, D.if_part);
       }
-      launch_pass_b<T>(s, D, P, it, diag, pn, q, x, r, sc_dev, c->partials, e ? e[2] : nullptr,
-                       e ? e[3] : nullptr);
     }
     launched += k;
     launch_check(s, P, launched, sc_dev, c->partials);
@@ -646,15 +650,13 @@ int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const F
     max_done = std::max(max_done, sc_host[qq].iter);
   }
   if (period > 0) {
-    // timed iterations that did work for at least one problem
-    for (int it = period; it <= max_done && 4 * (it / period) <= int(c->sweep_ev.size()); it += period) {
+    // timed sweeps that did work for at least one problem (sweep it makes iterate it)
+    for (int it = period; it <= max_done && 2 * (it / period) <= int(c->sweep_ev.size()); it += period) {
       const int kk = it / period - 1;
-      float ta = 0.f, tb = 0.f;
-      check(hipEventSynchronize(c->sweep_ev[4 * kk + 3]), "event");
-      check(hipEventElapsedTime(&ta, c->sweep_ev[4 * kk], c->sweep_ev[4 * kk + 1]), "event");
-      check(hipEventElapsedTime(&tb, c->sweep_ev[4 * kk + 2], c->sweep_ev[4 * kk + 3]), "event");
+      float ta = 0.f;
+      check(hipEventSynchronize(c->sweep_ev[2 * kk + 1]), "event");
+      check(hipEventElapsedTime(&ta, c->sweep_ev[2 * kk], c->sweep_ev[2 * kk + 1]), "event");
       ls->a_ms += ta;
-      ls->b_ms += tb;
       ls->n_timed += 1;
     }
   }
@@ -670,34 +672,57 @@ PcgScalars make_scalars(double tol, double abs_floor, int max_iter, int linf_tes
   return init;
 }
 
-// Operator arrays of one solve (a level or a whole batch), slot order.
+// Operator arrays of one solve (a level or a whole batch), slot order: the
+// unscaled operator (diag and A, stored or formed face coefficients) and the
+// Jacobi-scaled one the CG sweeps read.
 struct SolveArrays {
   FaceCoefs<double> A;
   const double* diag;
   const double* b;
   double* x;  // x_0 on entry (the energy, updated in place)
   int64_t n;
+  ScaledOp<double> Ah;
 };
 
-// The FP32 copy of a solve's operator (launched on s into the FP32 workspace) as the
-// inner sweeps read it.
-FaceCoefs<float> operator_f32(amrfld_ctx* c, hipStream_t s, const SolveArrays& A) {
+// The Jacobi-scaled operator of a solve: rs (and the stored scaled coefficients
+// unless they are formed in the sweeps) computed from the assembled system on s.
+ScaledOp<double> scale_operator(amrfld_ctx* c, hipStream_t s, const DevLevel& D, const FaceCoefs<double>& A,
+                                const double* Cp, const double* diag, double* rs, double* Ch) {
+  launch_jacobi_scale(s, D, A.Cp ? Cp : nullptr, diag, rs, Ch);
+  ScaledOp<double> Ah;
+  Ah.rs = rs;
+  if (A.Cp) {
+    Ah.Ch = Ch;
+  } else {
+    Ah.K = A.K;
+    Ah.mask = A.mask;
+    Ah.scale = A.scale;
+    Ah.theta = A.theta;
+    Ah.per_problem = A.per_problem;
+  }
+  return Ah;
+}
+
+// The FP32 copy of a solve's scaled operator (launched on s into the FP32
+// workspace) as the inner sweeps read it.
+ScaledOp<float> operator_f32(amrfld_ctx* c, hipStream_t s, const SolveArrays& A) {
   ensure_workspace32(c, A.n);
-  launch_to_f32(s, A.n, A.A.Cp, A.A.K, A.diag, c->Cp32, c->K32, c->diag32);
-  FaceCoefs<float> A32;
-  if (A.A.Cp) {
-    A32.Cp = c->Cp32;
+  launch_to_f32(s, A.n, A.Ah.Ch, A.Ah.K, A.Ah.rs, c->Ch32, c->K32, c->rs32);
+  ScaledOp<float> A32;
+  A32.rs = c->rs32;
+  if (A.Ah.Ch) {
+    A32.Ch = c->Ch32;
   } else {
     A32.K = c->K32;
-    A32.mask = A.A.mask;
-    A32.scale = A.A.scale;
-    A32.theta = A.A.theta;
-    A32.per_problem = A.A.per_problem;
+    A32.mask = A.Ah.mask;
+    A32.scale = A.Ah.scale;
+    A32.theta = A.Ah.theta;
+    A32.per_problem = A.Ah.per_problem;
   }
   return A32;
 }
 
-MixedArgs mixed_args(amrfld_ctx* c, const SolveArrays& A, const FaceCoefs<float>& A32, PcgScalars* out,
+MixedArgs mixed_args(amrfld_ctx* c, const SolveArrays& A, const ScaledOp<float>& A32, PcgScalars* out,
                      PcgScalars* in, int max_outer) {
   MixedArgs M;
   M.A = A.A;
@@ -705,13 +730,10 @@ MixedArgs mixed_args(amrfld_ctx* c, const SolveArrays& A, const FaceCoefs<float>
   M.b = A.b;
   M.x = A.x;
   M.x_alt = c->x_alt;
-  M.A32 = A32;
-  M.diag32 = c->diag32;
+  M.Ah32 = A32;
+  M.v32 = c->cg32;
   M.r32 = c->r32;
   M.d32 = c->d32;
-  M.q32 = c->q32;
-  M.p32[0] = c->p32[0];
-  M.p32[1] = c->p32[1];
   M.outer = out;
   M.inner = in;
   M.part = c->partials;
@@ -722,33 +744,41 @@ MixedArgs mixed_args(amrfld_ctx* c, const SolveArrays& A, const FaceCoefs<float>
   return M;
 }
 
+// The two start sweeps of the FP64 CG (and, for the composite system, the couplings
+// of w^_0 to other levels).
+void cg_start(amrfld_ctx* c, hipStream_t s, const DevLevel& D, const SweepPlan& P, const SolveArrays& A,
+              PcgScalars* sc) {
+  launch_cg_init_r<double>(s, D, P, A.A, A.diag, A.b, A.x, A.Ah.rs, c->cg);
+  launch_cg_init_w<double>(s, D, P, A.Ah, A.b, c->cg, c->partials);
+  if (D.n_if_rows > 0) launch_interface(s, D, c->cg.r[0], c->cg.w[0], sc, D.if_part);
+}
+
 void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
               LoopStats* ls) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
   for (int q = 0; q < np; ++q) c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
   write_scalars(c, c->sc, c->h_sc, np);
-  launch_pcg_init<double>(s, D, P, A.A, A.diag, A.b, A.x, c->r, c->p[0], c->partials);
-  launch_init_finish(s, P, c->partials, c->sc);
+  cg_start(c, s, D, P, A, c->sc);
   check(hipEventRecord(c->ev[1], s), "event");
-  pcg_iterations<double>(c, D, P, A.A, A.diag, A.x, c->r, c->p, c->q, c->sc, c->h_sc, c->o.max_iter, ls);
+  pcg_iterations<double>(c, D, P, A.Ah, c->cg, A.x, c->sc, c->h_sc, c->o.max_iter, ls);
 }
 
-// FP32 inner PCG on A d = r inside an FP64 iterative-refinement loop: the FP64
+// FP32 inner CG on A d = r inside an FP64 iterative-refinement loop: the FP64
 // sweep applies x += d and forms the true residual r = b - A x; the inner solve
-// uses FP32 coefficients, vectors and operator arithmetic with FP64 dot products.
-// Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].  Every decision
-// of the loop is made on the device (k_ir_finish): the host enqueues rounds and
-// learns that all problems stopped when a round's inner solves all end after 0
-// iterations, so it reads scalars only inside the inner solves.  With `persistent`
-// the whole solve is one cooperative launch (the same bits).  Once the stream has
-// run, the outer records hold the refinement sweeps (iter) and the inner iterations
-// (inner_total).
+// uses the FP32 scaled operator, FP32 vectors and operator arithmetic with FP64 dot
+// products.  Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].
+// Every decision of the loop is made on the device (k_ir_finish): the host enqueues
+// rounds and learns that all problems stopped when a round's inner solves all end
+// after 0 iterations, so it reads scalars only inside the inner solves.  With
+// `persistent` the whole solve is one cooperative launch (the same bits).  Once the
+// stream has run, the outer records hold the refinement sweeps (iter) and the inner
+// iterations (inner_total).
 void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
                LoopStats* ls) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
-  const FaceCoefs<float> A32 = operator_f32(c, s, A);
+  const ScaledOp<float> A32 = operator_f32(c, s, A);
   for (int q = 0; q < np; ++q) {
     c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
     c->h_sc[np + q] = make_scalars(c->o.inner_tol, 0.0, c->o.max_iter, 0);
@@ -786,12 +816,9 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
                     c->partials);
     std::swap(x_cur, x_nxt);
     launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, max_outer, out, in, c->partials);
-    launch_inner_init(s, D, P, c->diag32, c->r32, c->d32, c->p32[0], out, c->partials);
-    launch_init_finish(s, P, c->partials, in);
-    LoopStats inner_ls;
-    inner_ls.iters.assign(np, 0);
-    const int done = pcg_iterations<float>(c, D, P, A32, c->diag32, c->d32, c->r32, c->p32, c->q32, in,
-                                           c->h_sc + np, c->o.max_iter, &inner_ls, hint + 1);
+    launch_inner_init(s, D, P, A32, c->r32, c->d32, c->cg32, out, c->partials);
+    const int done = pcg_iterations<float>(c, D, P, A32, c->cg32, c->d32, in, c->h_sc + np, c->o.max_iter, ls,
+                                           hint + 1);
     if (done == 0) break;  // every refinement loop had stopped before this round's inner solves
     hint = done;
   }
@@ -824,13 +851,14 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
     launch_theta_step(s, D, c->o.theta, L.E, face_coefs(c, L.Cp, L.K, L.mask, scale, 1.0, false), L.Cp, L.diag,
                       L.b);
   const FaceCoefs<double> Aop = face_coefs(c, L.Cp, L.K, L.mask, scale, c->o.theta, false);
+  const ScaledOp<double> Ah = scale_operator(c, s, D, Aop, L.Cp, L.diag, L.rs, L.Ch);
 
   const int n_tiles = tiles_of(D.n_slots);
   const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
   ensure_scalars(c, 1);
   LoopStats ls;
   ls.iters.assign(1, 0);
-  const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots};
+  const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots, Ah};
   if (c->o.precision == AMRFLD_MIXED) {
     pcg_mixed(c, D, P, A, tol, &ls);
   } else {
@@ -933,6 +961,8 @@ hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int
     launch_theta_step(st, D, c->o.theta, L.E, face_coefs(c, L.Cp, L.K, L.mask, scale, 1.0, false), L.Cp, L.diag,
                       L.b);
   const FaceCoefs<double> Aop = face_coefs(c, L.Cp, L.K, L.mask, scale, c->o.theta, false);
+  const ScaledOp<double> Ah = scale_operator(c, st, D, Aop, L.Cp, L.diag, L.rs, L.Ch);
+  const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots, Ah};
   const int n_tiles = tiles_of(D.n_slots);
   const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
   SweepPlan Pp = P;
@@ -942,16 +972,14 @@ hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int
   launch_zero_u32(st, c->bar, kBarAbort);  // arrivals, releases, stop counts; not the abort flag
   hipError_t e;
   if (mixed) {
-    const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots};
-    const FaceCoefs<float> A32 = operator_f32(c, st, A);
+    const ScaledOp<float> A32 = operator_f32(c, st, A);
     launch_init_scalars(st, sc_inner, 1, c->o.inner_tol, 0.0, c->o.max_iter, 0);
     const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
     e = launch_mixed_persistent(st, D, Pp, mixed_args(c, A, A32, sc, sc_inner, max_outer), c->o.persistent_per_cu);
   } else {
-    launch_pcg_init<double>(st, D, P, Aop, L.diag, L.b, L.E, c->r, c->p[0], c->partials);
-    launch_init_finish(st, P, c->partials, sc);
-    e = launch_pcg_persistent<double>(st, D, Pp, c->o.max_iter, Aop, L.diag, L.E, c->r, c->p, c->q, sc, c->partials,
-                                      c->bar, c->o.persistent_per_cu);
+    cg_start(c, st, D, P, A, sc);
+    e = launch_pcg_persistent<double>(st, D, Pp, c->o.max_iter, Ah, c->cg, L.E, sc, c->partials, c->bar,
+                                      c->o.persistent_per_cu);
   }
   if (e != hipSuccess) return e;
   if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Aop, L.diag, L.b, L.E, sc, c->partials);
@@ -1109,6 +1137,7 @@ struct CompositeState {
   std::vector<PatchParams> pp_host;
   double *x = nullptr, *K = nullptr, *rho = nullptr, *T = nullptr;
   double *Cp = nullptr, *cif = nullptr, *diag = nullptr, *b = nullptr;
+  double *Ch = nullptr, *rs = nullptr;  // the Jacobi-scaled operator of the current solve
   uint8_t* c2f = nullptr;
   // rows coupled to other levels: row, entry range, column, coefficient index into cif
   int n_if_rows = 0, n_if_entries = 0;
@@ -1138,7 +1167,7 @@ struct CompositeState {
   void release() {
     for (void* p : {(void*)nbr, (void*)cnb, (void*)child, (void*)lvl, (void*)pp, (void*)x, (void*)K, (void*)rho,
                     (void*)T, (void*)Cp, (void*)cif, (void*)diag, (void*)b, (void*)c2f, (void*)if_row,
-                    (void*)if_ptr, (void*)if_col, (void*)if_src, (void*)if_val, (void*)if_part})
+                    (void*)if_ptr, (void*)if_col, (void*)if_src, (void*)if_val, (void*)if_part, (void*)Ch, (void*)rs})
       dfree(p);
   }
 };
@@ -1266,6 +1295,8 @@ void build_composite_into(amrfld_ctx* c, CompositeState* C) {
   C->cif = dalloc<double>(3 * n, "composite system");
   C->diag = dalloc<double>(n, "composite system");
   C->b = dalloc<double>(n, "composite system");
+  C->Ch = dalloc<double>(3 * n, "composite system");
+  C->rs = dalloc<double>(n, "composite system");
   C->c2f = dalloc<uint8_t>(n, "composite system");
   launch_fill(c->stream(), C->x, n, 0.0);  // padding slots keep x = 0 (identity rows)
   launch_fill(c->stream(), C->rho, n, 1.0);
@@ -1307,7 +1338,8 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   cp.T = coupled ? C.T : nullptr;
   const DevLevel D = C.dev();
   launch_assemble_composite(s, D, C.K, C.x, C.rho, cp, outer_bc(c), dt, C.Cp, C.cif, C.c2f, C.diag, C.b);
-  launch_interface_values(s, C.n_if_entries, C.if_src, C.cif, C.if_val);
+  const ScaledOp<double> Ah = scale_operator(c, s, D, stored_face_coefs(C.Cp), C.Cp, C.diag, C.rs, C.Ch);
+  launch_interface_values(s, D, C.n_if_entries, C.cif, C.rs, C.if_val);
   const int n_tiles = tiles_of(C.n_slots);
   const int B = c->o.max_blocks > 0 ? c->o.max_blocks : 1024;
   SweepPlan P = single_plan(sweep_blocks(n_tiles, B), n_tiles);
@@ -1317,7 +1349,7 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   }
   LoopStats ls;
   ls.iters.assign(1, 0);
-  pcg_fp64(c, D, P, SolveArrays{stored_face_coefs(C.Cp), C.diag, C.b, C.x, C.n_slots}, tol, &ls);
+  pcg_fp64(c, D, P, SolveArrays{stored_face_coefs(C.Cp), C.diag, C.b, C.x, C.n_slots, Ah}, tol, &ls);
   check(hipEventRecord(c->ev[2], s), "event");
   if (c->o.true_residual) launch_true_residual(s, D, P, stored_face_coefs(C.Cp), C.diag, C.b, C.x, c->sc, c->partials);
   int64_t n_leaf = 0;
@@ -1494,6 +1526,8 @@ void build_batch_into(amrfld_ctx* c, BatchState* B, const std::vector<int>& size
   B->mask = dalloc<uint8_t>(B->n_slots, "batch fields");
   B->diag = dalloc<double>(B->n_slots, "batch fields");
   B->b = dalloc<double>(B->n_slots, "batch fields");
+  B->Ch = dalloc<double>(3 * B->n_slots, "batch fields");
+  B->rs = dalloc<double>(B->n_slots, "batch fields");
   B->pp = dalloc<PatchParams>(B->n_prob, "batch params");
   B->src = reinterpret_cast<const double**>(dalloc<const double*>(B->n_prob, "batch pointers"));
   check(hipStreamSynchronize(c->stream()), "batch tables");
@@ -1522,7 +1556,6 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
   cp.T = nullptr;
   const CellKParams kp{1, 1.0, 1.0, 1.0};
   const FaceCoefs<double> Aop = face_coefs(c, B.Cp, B.K, B.mask, 1.0, 1.0, true);
-  const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots};
   const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
   auto record = [&](hipStream_t st) -> hipError_t {
     launch_zero_u32(st, c->bar, kBarWords);
@@ -1531,18 +1564,18 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       launch_cell_K(st, D, B.E, B.rho, nullptr, kp, OuterBC{}, B.K);
       launch_assemble(st, D, B.K, nullptr, B.E, nullptr, B.rho, nullptr, 1.0, 1.0, c->o.robin_alpha, cp, kp,
                       OuterBC{}, B.Cp, B.mask, B.diag, B.b);
+      const ScaledOp<double> Ah = scale_operator(c, st, D, Aop, B.Cp, B.diag, B.rs, B.Ch);
+      const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots, Ah};
       launch_init_scalars(st, sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
       launch_zero_u32(st, c->bar, kBarAbort);
       hipError_t e;
       if (mixed) {
-        const FaceCoefs<float> A32 = operator_f32(c, st, A);
+        const ScaledOp<float> A32 = operator_f32(c, st, A);
         launch_init_scalars(st, sc_inner, np, c->o.inner_tol, 0.0, c->o.max_iter, 0);
         e = launch_mixed_persistent(st, D, P, mixed_args(c, A, A32, sc, sc_inner, max_outer), per_cu);
       } else {
-        launch_pcg_init<double>(st, D, P, Aop, B.diag, B.b, B.E, c->r, c->p[0], c->partials);
-        launch_init_finish(st, P, c->partials, sc);
-        e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, Aop, B.diag, B.E, c->r, c->p, c->q, sc,
-                                          c->partials, c->bar, per_cu);
+        cg_start(c, st, D, P, A, sc);
+        e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, Ah, c->cg, B.E, sc, c->partials, c->bar, per_cu);
       }
       if (e != hipSuccess) return e;
       if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Aop, B.diag, B.b, B.E, sc, c->partials);
@@ -1692,7 +1725,8 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     LoopStats ls;
     ls.iters.assign(np, 0);
     const FaceCoefs<double> Aop = face_coefs(c, B.Cp, B.K, B.mask, 1.0, 1.0, true);
-    const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots};
+    const ScaledOp<double> Ah = scale_operator(c, s, D, Aop, B.Cp, B.diag, B.rs, B.Ch);
+    const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots, Ah};
     if (precision == AMRFLD_MIXED) {
       pcg_mixed(c, D, P, A, tol, &ls);
     } else {
@@ -1755,16 +1789,14 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
 amrfld_status solve_one_noalloc(amrfld_ctx* c, double* scr, int level, double dt, int mode, double tol) {
   struct Swap {
     amrfld_ctx* c;
-    double *r, *p0, *p1, *q, *partials;
+    CgVecs<double> cg;
+    double* partials;
     int64_t ws_n, partial_n;
     PcgScalars* sc;
     unsigned* bar;
     int time_sweeps;
     ~Swap() {
-      c->r = r;
-      c->p[0] = p0;
-      c->p[1] = p1;
-      c->q = q;
+      c->cg = cg;
       c->partials = partials;
       c->ws_n = ws_n;
       c->partial_n = partial_n;
@@ -1773,11 +1805,10 @@ amrfld_status solve_one_noalloc(amrfld_ctx* c, double* scr, int level, double dt
       c->o.time_sweeps = time_sweeps;
       g_no_alloc = false;
     }
-  } keep{c, c->r, c->p[0], c->p[1], c->q, c->partials, c->ws_n, c->partial_n, c->sc, c->bar, c->o.time_sweeps};
-  c->r = scr;
-  c->p[0] = scr + kScratchSlots;
-  c->p[1] = scr + 2 * kScratchSlots;
-  c->q = scr + 3 * kScratchSlots;
+  } keep{c, c->cg, c->partials, c->ws_n, c->partial_n, c->sc, c->bar, c->o.time_sweeps};
+  double** vec[kScratchVectors] = {&c->cg.r[0], &c->cg.r[1], &c->cg.w[0], &c->cg.w[1], &c->cg.s[0], &c->cg.s[1],
+                                   &c->cg.p};
+  for (int k = 0; k < kScratchVectors; ++k) *vec[k] = scr + k * kScratchSlots;
   c->partials = scr + kScratchOffPartials;
   c->ws_n = kScratchSlots;
   c->partial_n = kScratchPartials;
@@ -1887,9 +1918,10 @@ void amrfld_destroy(amrfld_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& e : c->cap_ev)
     if (e) (void)hipEventDestroy(e);
-  for (void* p : {(void*)c->r, (void*)c->p[0], (void*)c->p[1], (void*)c->q, (void*)c->partials,
-                  (void*)c->sc, (void*)c->Cp32, (void*)c->K32, (void*)c->diag32, (void*)c->r32, (void*)c->d32,
-                  (void*)c->p32[0], (void*)c->p32[1], (void*)c->q32, (void*)c->x_alt})
+  free_vecs(c->cg);
+  free_vecs(c->cg32);
+  for (void* p : {(void*)c->partials, (void*)c->sc, (void*)c->Ch32, (void*)c->K32, (void*)c->rs32, (void*)c->r32,
+                  (void*)c->d32, (void*)c->x_alt})
     dfree(p);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->h_seq) (void)hipHostFree(c->h_seq);
@@ -1929,6 +1961,8 @@ amrfld_status amrfld_build_level(amrfld_ctx* c, int level, int64_t n_oct, const 
       fresh.mask = dalloc<uint8_t>(n, "fields");
       fresh.diag = dalloc<double>(n, "fields");
       fresh.b = dalloc<double>(n, "fields");
+      fresh.Ch = dalloc<double>(3 * n, "fields");
+      fresh.rs = dalloc<double>(n, "fields");
       upload_tables(c, fresh);
     } catch (...) {
       (void)hipStreamSynchronize(c->stream());

@@ -45,9 +45,21 @@ __device__ __forceinline__ T face_coef(T Ki, T Kj, T scale, T theta) {
   return c;
 }
 
+// Coefficient of a face of the Jacobi-scaled operator formed from the two cells'
+// diffusivities and scale factors: the assembly's coefficient times rs_i rs_j (the
+// stored scaled coefficients are computed with the same expression).
+template <typename T>
+__device__ __forceinline__ T scaled_face(T Ki, T Kj, T rsi, T rsj, T scale, T theta) {
+  return face_coef(Ki, Kj, scale, theta) * (rsi * rsj);
+}
+
 // dt / dx^2 of problem `prob` of a solve.
 template <typename T>
 __device__ __forceinline__ T coef_scale(const FaceCoefs<T>& A, const DevLevel& L, int prob) {
+  return T(A.per_problem ? L.pp[prob].coef : A.scale);
+}
+template <typename T>
+__device__ __forceinline__ T coef_scale(const ScaledOp<T>& A, const DevLevel& L, int prob) {
   return T(A.per_problem ? L.pp[prob].coef : A.scale);
 }
 
@@ -335,6 +347,54 @@ __device__ __forceinline__ T apply_stencil(int ii, const int32_t* __restrict__ n
     if (nb >= 0 && ((m >> (2 * axis + my)) & 1u)) {
       const int j = (nb << 3) | (pos ^ bit);
       const T c_out = face_coef(Ki, A.K[j], scale, th);
+      if (c_out != T(0)) acc -= c_out * get(j);
+    }
+  }
+  return acc;
+}
+
+// The Jacobi-scaled operator at slot ii (diagonal 1) applied to a vector whose value
+// at ii is vi and at other slots is get(j); `scale` is the problem's coef_scale.
+template <typename T, class Get>
+__device__ __forceinline__ T apply_scaled(int ii, const int32_t* __restrict__ nbr, const ScaledOp<T>& A, T scale,
+                                          int n, T vi, Get get) {
+  const int pos = ii & 7, o = ii >> 3;
+  T acc = vi;
+  if (A.Ch) {
+#pragma unroll
+    for (int axis = 0; axis < 3; ++axis) {
+      const int bit = 1 << axis;
+      const T* __restrict__ Ca = A.Ch + size_t(axis) * n;
+      const T c_own = Ca[ii];
+      const T v_sib = __shfl_xor(vi, bit, 64);
+      const T c_sib = __shfl_xor(c_own, bit, 64);
+      const int my = (pos >> axis) & 1;
+      acc -= (my ? c_sib : c_own) * v_sib;
+      const int nb = nbr[o * 6 + 2 * axis + my];
+      if (nb >= 0) {
+        const int j = (nb << 3) | (pos ^ bit);
+        const T c_out = my ? c_own : Ca[j];
+        if (c_out != T(0)) acc -= c_out * get(j);
+      }
+    }
+    return acc;
+  }
+  const T Ki = A.K[ii], rsi = A.rs[ii];
+  const unsigned m = A.mask[ii];
+  const T th = T(A.theta);
+#pragma unroll
+  for (int axis = 0; axis < 3; ++axis) {
+    const int bit = 1 << axis;
+    const T K_sib = __shfl_xor(Ki, bit, 64);
+    const T rs_sib = __shfl_xor(rsi, bit, 64);
+    const T v_sib = __shfl_xor(vi, bit, 64);
+    const int my = (pos >> axis) & 1;
+    const T c_in = ((m >> (2 * axis + 1 - my)) & 1u) ? scaled_face(Ki, K_sib, rsi, rs_sib, scale, th) : T(0);
+    acc -= c_in * v_sib;
+    const int nb = nbr[o * 6 + 2 * axis + my];
+    if (nb >= 0 && ((m >> (2 * axis + my)) & 1u)) {
+      const int j = (nb << 3) | (pos ^ bit);
+      const T c_out = scaled_face(Ki, A.K[j], rsi, A.rs[j], scale, th);
       if (c_out != T(0)) acc -= c_out * get(j);
     }
   }

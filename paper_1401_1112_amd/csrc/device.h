@@ -27,7 +27,8 @@ constexpr int kBarArrive = 0, kBarRelease = 64, kBarDone = 128, kBarOuterDone = 
 // the stopping decision themselves from the previous sweep's block partials;
 // the host reads this record only between batches of iterations.
 struct PcgScalars {
-  double rho[2];    // (r, z) of iterate j, stored at index j & 1
+  double gam[2];    // (r^, r^) of iterate j (scaled residual), stored at index j & 1
+  double alpha[2];  // step alpha_j that takes iterate j to j + 1, at index j & 1
   double rnorm0, bnorm, thresh;
   double tol, abs_floor;
   double rnorm;     // ||r_j|| of the recursive residual
@@ -150,6 +151,34 @@ struct FaceCoefs {
   bool per_problem = false;
 };
 
+// The Jacobi-scaled operator A^ = S A S, S = diag(rs), rs = 1 / sqrt(diag A), of a
+// solve, as the CG sweeps read it: its diagonal is 1 on every row and the
+// coefficient of a face is C_f rs_i rs_j.  Stored (Ch set): Ch[a][i] for the +a face
+// of slot i, zero unless both sides are leaves.  Formed (K set): from the two
+// diffusivities with the assembly's expression, times rs_i rs_j, the same bits.
+template <typename T>
+struct ScaledOp {
+  const T* Ch = nullptr;
+  const T* K = nullptr;
+  const uint8_t* mask = nullptr;
+  const T* rs = nullptr;  // always set
+  double scale = 1.0;
+  double theta = 1.0;
+  bool per_problem = false;
+};
+
+// Vectors of the CG iteration on the scaled system: residual r^, w^ = A^ r^ and
+// s^ = A^ p^ in two buffers each (the sweep of iteration it reads buffer
+// (it - 1) & 1 and writes it & 1, so values that other blocks recompute across
+// their range boundaries are never overwritten during a sweep), search direction p^.
+template <typename T>
+struct CgVecs {
+  T* r[2] = {nullptr, nullptr};
+  T* w[2] = {nullptr, nullptr};
+  T* s[2] = {nullptr, nullptr};
+  T* p = nullptr;
+};
+
 struct CouplingParams {
   const double* T;  // nullptr: no coupling
   double kappa_P, c_light, a_rad, c_v;
@@ -189,53 +218,71 @@ void launch_fill(hipStream_t s, double* p, int64_t n, double v);
 // generic copy runs far below HBM rate at these sizes).
 void launch_copy_f64(hipStream_t s, double* dst, const double* src, int64_t n);
 void launch_fill_f32(hipStream_t s, float* p, int64_t n, float v);
-// FP32 copies of an FP64 operator: Cp (stored form) or K (formed), and diag.
-void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* K, const double* diag, float* Cp32,
-                   float* K32, float* diag32);
+// Jacobi scaling of an assembled operator: rs = 1 / sqrt(diag) on every slot and,
+// when Cp is given, Ch[a][i] = Cp[a][i] rs_i rs_j for the +a neighbour j.
+void launch_jacobi_scale(hipStream_t s, const DevLevel& L, const double* Cp, const double* diag, double* rs,
+                         double* Ch);
+// FP32 copies of a scaled operator: Ch (stored form) or K (formed), and rs.
+void launch_to_f32(hipStream_t s, int64_t n, const double* Ch, const double* K, const double* rs, float* Ch32,
+                   float* K32, float* rs32);
 
 // -------------------------------------------------------------- PCG sweeps
-// G = number of blocks of every sweep of a solve (<= tiles); partials hold
-// 4 G doubles: [0, G) for the operator sweep, [G, 4G) for the update sweep.
+// Jacobi PCG (Sect. 3.3.4) run as CG on the Jacobi-scaled system with the
+// recurrences of Chronopoulos and Gear: one fused sweep per iteration, whose two
+// dot products are reduced together at the head of the next sweep.  G = number of
+// blocks of every sweep of a solve (<= tiles); partials hold 8 G doubles, 4 per
+// block for each iteration parity.
 int sweep_blocks(int n_tiles, int max_blocks);
 
 // Every launcher below covers all problems of the plan; sc points at n_prob
 // scalar records.
+// Start, sweep 1: r^_0 = rs (b - A x0) with the unscaled operator A (diag and A),
+// p^ = 0, s^ buffer 0 = 0.
 template <typename T>
-void launch_pcg_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag,
-                     const T* b, const T* x, T* r, T* p_clear, double* part);
-void launch_init_finish(hipStream_t s, const SweepPlan& P, const double* part, PcgScalars* sc);
+void launch_cg_init_r(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag,
+                      const T* b, const T* x, const T* rs, const CgVecs<T>& v);
+// Start, sweep 2: w^_0 = A^ r^_0; partials (r^, r^), (w^, r^), ||r_0||^2, ||b||^2 over
+// the unknowns.
+template <typename T>
+void launch_cg_init_w(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<T>& Ah, const T* b,
+                      const CgVecs<T>& v, double* part);
+// The iteration sweep `it` (1, 2, ...) advances every problem from iterate it - 1 to
+// iterate it: at its head the stopping test on iterate it - 1 (for it = 1 the start
+// of the solve: ||r_0||, the threshold and the absolute floor), beta and alpha;
+// then p^ = r^ + beta p^, s^ = w^ + beta s^, x += alpha rs p^, r^ -= alpha s^,
+// w^ = A^ r^; partials (r^, r^), (w^, r^), ||r||^2 = sum (r^ / rs)^2 and
+// max |x - x_old| / |x_old|.  x is the unscaled iterate, updated in place.
 // t0 / t1 (optional): events that the launch itself records when the kernel
 // starts and ends, so that they time the kernel alone.
 template <typename T>
-void launch_pass_a(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const FaceCoefs<T>& A,
-                   const T* diag, const T* r, const T* p_old, T* p_new, T* q, PcgScalars* sc,
-                   double* part, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
-template <typename T>
-void launch_pass_b(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const T* diag,
-                   const T* p, const T* q, T* x, T* r, PcgScalars* sc, double* part,
-                   hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+void launch_cg_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, int it, const ScaledOp<T>& Ah,
+                     const CgVecs<T>& v, T* x, PcgScalars* sc, double* part, hipEvent_t t0 = nullptr,
+                     hipEvent_t t1 = nullptr);
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part);
-// Composite system: after the operator sweep of iteration `it`, q -= (couplings to
-// other levels) p for the listed rows, and partials of p . (that part of q) in
-// part_if (ceil(n_if_rows / kBlock) of them); skipped once the problem stopped.
+// Composite system: after a sweep that wrote w^ (buffer `buf` of v, iteration `it`,
+// 0 for the start), w^ -= (scaled couplings to other levels) r^ for the listed rows,
+// and partials of (that part of w^, r^) in part_if (ceil(n_if_rows / kBlock) of
+// them); skipped once the problem stopped.
 int interface_blocks(const DevLevel& L);
-// val[e] = cif[src[e]] for the n_entries interface entries (once per solve).
-void launch_interface_values(hipStream_t s, int n_entries, const int32_t* src, const double* cif, double* val);
-void launch_interface(hipStream_t s, const DevLevel& L, const double* p, double* q, const PcgScalars* sc,
+// val[e] = cif[src[e]] rs_row rs_col for the interface entries of every listed row
+// (once per solve).
+void launch_interface_values(hipStream_t s, const DevLevel& L, int n_entries, const double* cif, const double* rs,
+                             double* val);
+void launch_interface(hipStream_t s, const DevLevel& L, const double* r, double* w, const PcgScalars* sc,
                       double* part_if);
 // All iterations of all problems in one cooperative launch (grid barrier between
 // sweeps); bar is the control buffer (kBarWords), P.done_count = bar + kBarDone;
-// its first kBarAbort words are zeroed before the start sweeps.  Returns an
-// error if the device cannot run the cooperative launch.  bar[kBarAbort]
-// becomes 1 if a grid barrier timed out (the launch then returns early).
+// its first kBarAbort words are zeroed before the launch.  Returns an error if the
+// device cannot run the cooperative launch.  bar[kBarAbort] becomes 1 if a grid
+// barrier timed out (the launch then returns early).
 // Blocks of the persistent launch for this plan (0 if the device cannot run it);
 // per_cu_cap > 0 limits the resident blocks per compute unit (fewer barrier arrivals).
 template <typename T>
 int persistent_blocks(const SweepPlan& P, int per_cu_cap);
 template <typename T>
 hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, int max_iter,
-                                 const FaceCoefs<T>& A, const T* diag, T* x, T* r, T* const* p, T* q, PcgScalars* sc,
-                                 double* part, unsigned* bar, int per_cu_cap);
+                                 const ScaledOp<T>& Ah, const CgVecs<T>& v, T* x, PcgScalars* sc, double* part,
+                                 unsigned* bar, int per_cu_cap);
 void launch_zero_u32(hipStream_t s, unsigned* p, int n);
 // Copies count scalar records between device memory and the device-mapped view of
 // pinned host memory (to_host: then makes the stores visible to the host), so that
@@ -269,10 +316,9 @@ struct MixedArgs {
   const double* b = nullptr;
   double* x = nullptr;      // iterate: x_0 on entry, the result on return
   double* x_alt = nullptr;  // second buffer of the refinement sweeps
-  FaceCoefs<float> A32;     // FP32 operator of the inner solves
-  const float* diag32 = nullptr;
-  float *r32 = nullptr, *d32 = nullptr, *q32 = nullptr;
-  float* p32[2] = {nullptr, nullptr};
+  ScaledOp<float> Ah32;     // FP32 scaled operator of the inner solves
+  CgVecs<float> v32;
+  float *r32 = nullptr, *d32 = nullptr;
   PcgScalars* outer = nullptr;  // n_prob outer records (tol, abs_floor, max_iter, linf_test set)
   PcgScalars* inner = nullptr;  // n_prob inner records
   double* part = nullptr;
@@ -288,10 +334,12 @@ int mixed_persistent_blocks(const SweepPlan& P, int per_cu_cap);
 // the cooperative launch; bar[kBarAbort] becomes 1 if a grid barrier timed out.
 hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const MixedArgs& M,
                                    int per_cu_cap);
-// Inner start: d = 0, p = 0; partials (r, r / diag), ||r||^2 of the FP32 residual.
-void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const float* diag32,
-                       const float* r32, float* d, float* p_clear, const PcgScalars* outer,
-                       double* part);
+// Inner start (one sweep, x_0 = 0): d = 0, r^_0 = rs r32, w^_0 = A^ r^_0 (the
+// neighbours' r^_0 formed from their r32 and rs), p^ = 0, s^ buffer 0 = 0; partials
+// (r^, r^), (w^, r^), ||r32||^2 twice (the inner ||r_0|| and ||b||).  Problems whose
+// refinement has stopped are left alone.
+void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<float>& Ah,
+                       const float* r32, float* d, const CgVecs<float>& v, const PcgScalars* outer, double* part);
 
 // ------------------------------------------------------------- batch layout
 // dst[i] = src[prob(i)][idx[i]] (idx < 0: padding slot, dst = pad).

@@ -325,20 +325,53 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* p, int64_t n, T v) {
 }
 
 // FP32 copies of the operator for the inner solve of the mixed-precision form.
-__global__ __launch_bounds__(kBlock) void k_to_f32(int64_t n, const double* __restrict__ Cp,
+// Jacobi scaling of an assembled operator (Sect. 3.3.4's diagonal preconditioner as
+// a symmetric scaling): rs = 1 / sqrt(diag) and Ch[a][i] = Cp[a][i] rs_i rs_j for the
+// +a neighbour j, computed with the expression the sweeps use for formed
+// coefficients, so both forms give the same bits.  Identity rows: diag 1, Ch 0.
+__global__ __launch_bounds__(kBlock) void k_jacobi_scale(DevLevel L, const double* __restrict__ Cp,
+                                                         const double* __restrict__ diag, double* __restrict__ rs,
+                                                         double* __restrict__ Ch) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int n = L.n_slots;
+  if (i >= n) return;
+  const double rsi = 1.0 / sqrt(diag[i]);
+  rs[i] = rsi;
+  if (!Cp) return;
+  const int pos = i & 7, o = i >> 3;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double c = Cp[size_t(a) * n + i];
+    double ch = 0.0;
+    if (c != 0.0) {
+      const int bit = 1 << a;
+      int j = -1;
+      if (((pos >> a) & 1) == 0) {
+        j = i ^ bit;
+      } else {
+        const int nb = L.nbr[o * 6 + 2 * a + 1];
+        if (nb >= 0) j = (nb << 3) | (pos ^ bit);
+      }
+      if (j >= 0) ch = c * (rsi * (1.0 / sqrt(diag[j])));
+    }
+    Ch[size_t(a) * n + i] = ch;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(int64_t n, const double* __restrict__ Ch,
                                                    const double* __restrict__ K,
-                                                   const double* __restrict__ diag,
-                                                   float* __restrict__ Cp32, float* __restrict__ K32,
-                                                   float* __restrict__ diag32) {
+                                                   const double* __restrict__ rs,
+                                                   float* __restrict__ Ch32, float* __restrict__ K32,
+                                                   float* __restrict__ rs32) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
-  if (Cp) {
-    Cp32[i] = float(Cp[i]);
-    Cp32[n + i] = float(Cp[n + i]);
-    Cp32[2 * n + i] = float(Cp[2 * n + i]);
+  if (Ch) {
+    Ch32[i] = float(Ch[i]);
+    Ch32[n + i] = float(Ch[n + i]);
+    Ch32[2 * n + i] = float(Ch[2 * n + i]);
   }
   if (K) K32[i] = float(K[i]);
-  diag32[i] = float(diag[i]);
+  rs32[i] = float(rs[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_gather(DevLevel L, const int32_t* __restrict__ idx,
@@ -426,9 +459,14 @@ void launch_fill_f32(hipStream_t s, float* p, int64_t n, float v) {
   hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
 }
 
-void launch_to_f32(hipStream_t s, int64_t n, const double* Cp, const double* K, const double* diag, float* Cp32,
-                   float* K32, float* diag32) {
-  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, Cp, K, diag, Cp32, K32, diag32);
+void launch_jacobi_scale(hipStream_t s, const DevLevel& L, const double* Cp, const double* diag, double* rs,
+                         double* Ch) {
+  hipLaunchKernelGGL(k_jacobi_scale, dim3(grid_for(L.n_slots)), dim3(kBlock), 0, s, L, Cp, diag, rs, Ch);
+}
+
+void launch_to_f32(hipStream_t s, int64_t n, const double* Ch, const double* K, const double* rs, float* Ch32,
+                   float* K32, float* rs32) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, Ch, K, rs, Ch32, K32, rs32);
 }
 
 }  // namespace amrfld

@@ -49,7 +49,33 @@ def test_measured_traffic_only_for_the_counted_source_and_shape(monkeypatch):
 
 
 def test_algorithmic_bytes_per_slot():
-    # pass A: r, p_old, d, three coefficients, 3 B of neighbour table; writes p, q
-    assert bench.PASS_A_BYTES == 67
-    # pass B: x, r, p, q, d; writes x, r
-    assert bench.PASS_B_BYTES == 56
+    # the method's bytes per cell and CG iteration, the figures the rooflines quote:
+    # FP64 pass A 69 + pass B 56, FP32 inner 37 + 28
+    assert bench.ALG_BYTES_FP64 == 125 and bench.ALG_BYTES_FP32 == 65
+    # the fused sweep moves p, s, w, x, r, rs, three coefficients and 3 B of neighbour
+    # table, and writes p, s, x, r, w
+    assert bench.SWEEP_BYTES == 115 and bench.SWEEP_BYTES_FORMED == 100 and bench.SWEEP_BYTES_FP32 == 59
+
+
+def test_roofline_of_timed_sweeps():
+    stats = [{"pass_a_ms": 2.0, "n_timed": 4, "n_leaf": 1_000_000},
+             {"pass_a_ms": 1.0, "n_timed": 2, "n_leaf": 1_000_000}]
+    r = bench._roofline(stats, 125, "k", "n")
+    # 6 launches over 1e6 cells at 125 B in 3 ms
+    assert r["achieved"] == pytest.approx(6 * 125e6 / 3e-3 / 1e9, rel=1e-6)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
+    assert r["timed_launches"] == 6 and r["avg_launch_us"] == pytest.approx(500.0)
+    assert bench._roofline([{"pass_a_ms": 0.0, "n_timed": 0, "n_leaf": 1}], 125, "k", "n") is None
+
+
+def test_schedule_is_fine_first_with_restrictions():
+    class H:
+        base_level, max_level = 6, 8
+
+    class P:
+        hierarchy, dt_coarse = H, 1.0
+
+    ops = bench._schedule(P)
+    solves = [(l, dt) for k, l, dt in ops if k == "solve"]
+    assert solves == [(8, 0.25), (8, 0.25), (7, 0.5), (8, 0.25), (8, 0.25), (7, 0.5), (6, 1.0)]
+    assert [l for k, l, _ in ops if k == "restrict"] == [8, 8, 7]

@@ -16,12 +16,15 @@ MODES = {"dirichlet": 0, "neumann": 1, "robin": 2}
 
 
 def _run_levels(p, mode, steps, **kw):
+    # a Neumann interface can drive energies negative in the first step (Sect. 3.3.5);
+    # the next step's system is then not positive definite and may end non-finite: both
+    # forms must still take the same path, so statuses are compared too (and NaN = NaN)
     from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
     s = solver_from_problem(p, **kw)
     its = []
     for _ in range(steps):
-        s.advance(p.dt_coarse, mode, p.tol)
-        its.append([x["iters"] for x in s.stats()])
+        st = s.advance(p.dt_coarse, mode, p.tol, raise_on_error=False)
+        its.append((st, [x["iters"] for x in s.stats()]))
     out = {l: to_numpy(s.E(l)) for l in p.hierarchy.levels}
     s.close()
     return out, its
@@ -35,7 +38,7 @@ def test_formed_equals_stored_levels(seed, mode, kmode):
     a, ia = _run_levels(p, MODES[mode], 2, form_coefs=True)
     b, ib = _run_levels(p, MODES[mode], 2)
     assert ia == ib
-    assert all(np.array_equal(a[l], b[l]) for l in a)
+    assert all(np.array_equal(a[l], b[l], equal_nan=True) for l in a)
 
 
 @pytest.mark.parametrize("variant", ["theta", "power_outer", "persistent"])

@@ -20,22 +20,30 @@ def _run(p, mode, dts, reset_each=False, **kw):
     for dt in dts:
         if reset_each:
             sample_problem_fields(s, p)
-        s.advance(dt, mode, p.tol)
+        # Neumann / Robin steps can end with negative energies (Sect. 3.3.5) and the next
+        # step's system then may end non-finite: every form must take the same path
+        status = s.advance(dt, mode, p.tol, raise_on_error=False)
         st = s.stats()
         out.append(({l: (to_numpy(s.E(l)), None if p.T is None else to_numpy(s.E(l, with_T=True)[1]))
                      for l in p.hierarchy.levels},
-                    [(x["level"], x["iters"]) for x in st], {x["launch_mode"] for x in st}))
+                    [status] + [(x["level"], x["iters"]) for x in st], {x["launch_mode"] for x in st}))
     s.close()
     return out
 
 
 def _same(a, b):
     for (fa, ia, _), (fb, ib, _) in zip(a, b):
+        if ia[0] != 0 or ib[0] != 0:
+            # a failed step (non-finite after negative energies): the same status; an eager
+            # step stops at the failing solve while a replay runs all of them, so nothing
+            # after it is compared
+            assert ia[0] == ib[0]
+            return
         assert ia == ib
         for l in fa:
-            assert np.array_equal(fa[l][0], fb[l][0])
+            assert np.array_equal(fa[l][0], fb[l][0], equal_nan=True)
             if fa[l][1] is not None:
-                assert np.array_equal(fa[l][1], fb[l][1])
+                assert np.array_equal(fa[l][1], fb[l][1], equal_nan=True)
 
 
 CASES = {

@@ -82,18 +82,39 @@ def _spd_start(p, o):
 
 def _run_pair(p, mode, steps, tol, max_iter):
     """Advance GPU and oracle side by side over the steps that start from an SPD state;
-    returns per-step iteration lists and the largest per-level relative L2 difference."""
+    returns per-step iteration lists and the largest per-level relative L2 difference.
+    tol = 0 runs every solve for exactly max_iter iterations (no absolute floor either).
+
+    A solve inside a step can still meet a diagonal entry <= 0 (energies gone negative
+    earlier in the step): CG on the Jacobi-scaled system is undefined there, and the GPU
+    must report E_NONFINITE for exactly that solve after the same counts on the solves
+    before it; the comparison ends at that step."""
     torch, S = _gpu()
-    s = S.solver_from_problem(p, max_iter=max_iter)
-    o = oracle_from_problem(p, max_iter=max_iter)
+    floor = {} if tol > 0 else {"abs_floor": 0.0}
+    s = S.solver_from_problem(p, max_iter=max_iter, **floor)
+    o = oracle_from_problem(p, max_iter=max_iter, **floor)
     counts, diffs = [], []
     for _ in range(steps):
         if not _spd_start(p, o):
             break
         start = len(o.history)
-        s.advance(p.dt_coarse, mode, tol, raise_on_error=False)
+        status = s.advance(p.dt_coarse, mode, tol, raise_on_error=False)
         o.advance_subcycled(p.dt_coarse, mode, tol)
-        counts.append((_iters_gpu(s), _iters_oracle(o, start)))
+        g, r = _iters_gpu(s), _iters_oracle(o, start)
+        bad = [k for k, h in enumerate(o.history[start:]) if h["min_diag"] <= 0.0]
+        # a fixed-count run (tol = 0) ends every solve at its cap: E_NOCONV by design
+        fine = {S.L.OK} if tol > 0 else {S.L.OK, S.L.E_NOCONV}
+        st = s.stats()
+        if bad:
+            k = bad[0]
+            assert status != S.L.OK and len(st) == k + 1, (status, len(st), k)
+            assert st[k]["status"] == S.L.E_NONFINITE and st[k]["level"] == r[k][0]
+            assert all(x["status"] in fine for x in st[:k])
+            if k:
+                counts.append((g[:k], r[:k]))
+            break
+        assert status in fine and all(x["status"] in fine for x in st), status
+        counts.append((g, r))
         diffs.append(_compare_levels(s, o, p.hierarchy.levels, tol=np.inf))
     s.close()
     return counts, diffs
@@ -104,14 +125,14 @@ def _parity_protocol(p, mode, steps, tol=1e-12):
     count differs (a near-tie at the stopping threshold) both sides are re-run with the
     largest count fixed and tol = 0, and that comparison is gated at 1e-12."""
     counts, diffs = _run_pair(p, mode, steps, p.tol, p.max_iter)
-    assert counts, "no step started from an SPD state"
+    assert counts and diffs, "no step started from an SPD state"
     if all(g == o for g, o in counts):
         assert max(diffs) <= tol, diffs
         return "same-count"
     n_fix = max(it for g, o in counts for _, it in g + o)
     counts2, diffs2 = _run_pair(p, mode, steps, 0.0, n_fix)
-    assert all(g == o for g, o in counts2)
-    assert max(diffs2) <= tol, diffs2
+    assert all(g == o for g, o in counts2), counts2
+    assert diffs2 and max(diffs2) <= tol, diffs2
     return "fixed-count"
 
 
@@ -336,3 +357,30 @@ def test_persistent_level_solves_equal_polled(precision, mode):
         assert m == {1}
         assert c == counts
         assert all(np.array_equal(a, b) for a, b in zip(e, base))
+
+
+def test_own_schedule_with_restrict_equals_advance():
+    # a caller's own schedule of amrfld_solve_level and amrfld_restrict_level calls in
+    # the driver's order (Sect. 2.2: finer levels first, restriction after their
+    # substeps) gives the subcycled step bit for bit
+    torch, S = _gpu()
+    from paper_1401_1112_amd import E_INVALID, _lib as L
+    p = config_tiny(5, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-12)
+    a = S.solver_from_problem(p)
+    a.advance(p.dt_coarse, 0, p.tol)
+    b = S.solver_from_problem(p)
+
+    def step(level, dt):
+        if level < p.hierarchy.max_level:
+            for _ in range(2):
+                step(level + 1, dt / 2)
+            b.restrict(level + 1)
+        b.solve_level(level, dt, 0, p.tol)
+
+    step(p.hierarchy.base_level, p.dt_coarse)
+    for lvl in p.hierarchy.levels:
+        assert np.array_equal(S.to_numpy(a.E(lvl)), S.to_numpy(b.E(lvl))), lvl
+    assert L.amrfld_restrict_level(b.ctx, p.hierarchy.base_level) == E_INVALID
+    assert L.amrfld_restrict_level(b.ctx, p.hierarchy.max_level + 1) == E_INVALID
+    a.close()
+    b.close()

@@ -78,17 +78,26 @@ def test_unique_parity_coupled_collapse():
     _parity(config_collapse(base_level=3, max_level=7, jeans=2.5, contrast=1e4, field_n=64, shared_dt_levels=2), 1)
 
 
-def test_unique_on_one_level_is_the_level_solve_bitwise():
+@pytest.mark.parametrize("level", [4, 5])
+def test_unique_on_one_level_is_the_level_solve(level):
+    # the composite system of one level is that level's system with every row times
+    # the cell volume V = 2^(-3 level); its Jacobi scaling 1 / sqrt(V d) equals
+    # V^(-1/2) / sqrt(d) exactly when V^(1/2) is a power of two (even levels), so the
+    # two solves agree bit for bit there and to rounding on odd levels
     from paper_1401_1112_amd import BC_DIRICHLET
     from paper_1401_1112_amd.solver import solver_from_problem, to_numpy
-    p = config_uniform(5, kmode="lp", seed=4)
+    p = config_uniform(level, kmode="lp", seed=4)
     a = solver_from_problem(p)
     b = solver_from_problem(p)
     a.advance_unique(p.dt_coarse, 1e-12)
     b.advance(p.dt_coarse, BC_DIRICHLET, 1e-12)
     assert [x["iters"] for x in a.stats()] == [x["iters"] for x in b.stats()]
     assert a.stats()[0]["level"] == -1
-    assert np.array_equal(to_numpy(a.E(5)), to_numpy(b.E(5)))
+    ea, eb = to_numpy(a.E(level)), to_numpy(b.E(level))
+    if level % 2 == 0:
+        assert np.array_equal(ea, eb)
+    else:
+        assert np.linalg.norm(ea - eb) <= 1e-14 * np.linalg.norm(eb)
     a.close()
     b.close()
 

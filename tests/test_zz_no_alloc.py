@@ -6,11 +6,22 @@ import numpy as np
 import pytest
 
 from synth.configs import config_tiny, config_uniform
-from synth.hierarchy import uniform_hierarchy
+from synth.hierarchy import Hierarchy, uniform_hierarchy
 
 pytestmark = pytest.mark.gpu
 
-SCRATCH_SLOTS = 1 << 21
+SCRATCH_SLOTS = 1 << 20
+
+
+def _at_the_limit():
+    """Uniform level 6 and a level 7 over the half box x < 1/2: exactly 2^20 slots."""
+    p = config_uniform(6, kmode="lp", seed=3)
+    g = np.arange(64, dtype=np.int32)
+    I, J, K = np.meshgrid(np.arange(32, dtype=np.int32), g, g, indexing="ij")
+    slab = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
+    p.hierarchy = Hierarchy(6, {6: p.hierarchy.octs[6], 7: slab})
+    assert 8 * len(slab) == SCRATCH_SLOTS
+    return p
 
 
 def _mods():
@@ -49,7 +60,7 @@ def _same(res):
 def test_noalloc_matches_solve_level_on_calls_in_a_row():
     # largest level first (exactly the scratch limit), then smaller ones on the
     # scratch contents the earlier calls left behind
-    big = config_uniform(7, kmode="lp", seed=3)
+    big = _at_the_limit()
     dx = 1.0 / 128
     _same(_both(big, 7, 8.0 * dx * dx, 0, 1e-10))
     small = config_tiny(2, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-12)
@@ -97,9 +108,9 @@ def test_noalloc_rejections_leave_the_context_usable():
     assert "FP64" in L.amrfld_last_error(m.ctx)
     m.close()
     # a level above the scratch limit (no fields needed: the size is checked first)
-    h = uniform_hierarchy(8)
+    h = uniform_hierarchy(7)
     big = S.HierarchySolver(h.base_level, h.octs)
-    assert big.info(8)[0] > SCRATCH_SLOTS
-    assert L.amrfld_solve_level_noalloc(big.ctx, 8, 1e-5, 0, 1e-10) == L.E_INVALID
+    assert big.info(7)[0] > SCRATCH_SLOTS
+    assert L.amrfld_solve_level_noalloc(big.ctx, 7, 1e-5, 0, 1e-10) == L.E_INVALID
     assert "scratch limit" in L.amrfld_last_error(big.ctx)
     big.close()
