@@ -325,12 +325,15 @@ def _mixed_form(p, s64, init, ms64, args):
     cell_it = sum(st["n_leaf"] * st["iters"] for x in sts for st in x)
     res_polled = {l: to_numpy(s.E(l)) for l in s.levels}
     s.close()
-    # the whole step as a graph of persistent solves, each one cooperative launch
-    g = solver_from_problem(p, precision=MIXED, max_blocks=args.max_blocks, persistent=True, graph=True,
-                            inner_tol=inner["inner_tol"])
-    el_g, sts_g, _ = timed(g, args.steps)
-    res_graph = {l: to_numpy(g.E(l)) for l in g.levels}
-    g.close()
+    ms_g, res_graph = None, None
+    if not args.no_persistent:
+        # the whole step as a graph of persistent solves, each one cooperative launch
+        g = solver_from_problem(p, precision=MIXED, max_blocks=args.max_blocks, persistent=True, graph=True,
+                                inner_tol=inner["inner_tol"])
+        el_g, sts_g, _ = timed(g, args.steps)
+        res_graph = {l: to_numpy(g.E(l)) for l in g.levels}
+        g.close()
+        ms_g = el_g * 1e3 / args.steps
     # the FP64 reference: the same step from the same state (s64 may hold another form's result)
     for lvl in s64.levels:
         rho, E = init[lvl]
@@ -343,12 +346,12 @@ def _mixed_form(p, s64, init, ms64, args):
         worst_max, worst_l2 = max(worst_max, m), max(worst_l2, l2)
     last = sts[-1]
     ms = el * 1e3 / args.steps
-    ms_g = el_g * 1e3 / args.steps
     out = {"value": cell_it / el, "unit": "inner cell-iterations/s", "ms_per_step": ms,
            "speedup_vs_fp64": ms64 / ms,
-           "persistent_graph_ms_per_step": ms_g, "persistent_graph_speedup_vs_fp64": ms64 / ms_g,
-           "persistent_graph_equals_host_driven_bitwise": all(np.array_equal(res_polled[l], res_graph[l])
-                                                              for l in res_polled),
+           "persistent_graph_ms_per_step": ms_g,
+           "persistent_graph_speedup_vs_fp64": ms64 / ms_g if ms_g else None,
+           "persistent_graph_equals_host_driven_bitwise":
+               all(np.array_equal(res_polled[l], res_graph[l]) for l in res_polled) if res_graph else None,
            "inner_iterations_per_step": sum(st["iters"] for st in last),
            "outer_sweeps_per_step": sum(st["outer_iters"] for st in last),
            "residual": _residual_gate([st for x in sts for st in x], p.tol),
@@ -858,6 +861,8 @@ def main(argv=None):
     ap.add_argument("--no-equilibrium", action="store_true",
                     help="skip the nonlinear equilibrium test of the paper")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched form")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the persistent (cooperative) launches of the mixed level form (profiling runs)")
     ap.add_argument("--batch-patches", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=16)
     ap.add_argument("--no-collapse", action="store_true",

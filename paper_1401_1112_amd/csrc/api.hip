@@ -725,8 +725,7 @@ ScaledOp<float> operator_f32(amrfld_ctx* c, hipStream_t s, const SolveArrays& A)
 MixedArgs mixed_args(amrfld_ctx* c, const SolveArrays& A, const ScaledOp<float>& A32, PcgScalars* out,
                      PcgScalars* in, int max_outer) {
   MixedArgs M;
-  M.A = A.A;
-  M.diag = A.diag;
+  M.Ah = A.Ah;
   M.b = A.b;
   M.x = A.x;
   M.x_alt = c->x_alt;
@@ -767,7 +766,8 @@ void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveA
 // FP32 inner CG on A d = r inside an FP64 iterative-refinement loop: the FP64
 // sweep applies x += d and forms the true residual r = b - A x; the inner solve
 // uses the FP32 scaled operator, FP32 vectors and operator arithmetic with FP64 dot
-// products.  Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].
+// products, and after each refinement sweep continues its search direction from the
+// replaced residual instead of starting afresh.  Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].
 // Every decision of the loop is made on the device (k_ir_finish): the host enqueues
 // rounds and learns that all problems stopped when a round's inner solves all end
 // after 0 iterations, so it reads scalars only inside the inner solves.  With
@@ -812,11 +812,11 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
   double* x_nxt = c->x_alt;
   int hint = 0;
   for (int outer = 0; outer <= max_outer; ++outer) {
-    launch_ir_sweep(s, D, P, A.A, A.diag, A.b, x_cur, outer == 0 ? nullptr : c->d32, x_nxt, c->r32, out,
-                    c->partials);
+    launch_ir_sweep(s, D, P, A.Ah, A.b, x_cur, outer == 0 ? nullptr : c->d32, c->cg32.p, A32.rs, x_nxt, c->r32,
+                    out, in, c->partials);
     std::swap(x_cur, x_nxt);
     launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, max_outer, out, in, c->partials);
-    launch_inner_init(s, D, P, A32, c->r32, c->d32, c->cg32, out, c->partials);
+    launch_inner_init(s, D, P, A32, c->r32, c->d32, c->cg32, out, in, c->partials);
     const int done = pcg_iterations<float>(c, D, P, A32, c->cg32, c->d32, in, c->h_sc + np, c->o.max_iter, ls,
                                            hint + 1);
     if (done == 0) break;  // every refinement loop had stopped before this round's inner solves

@@ -43,6 +43,11 @@ struct PcgScalars {
   int linf_test;
   int counted;      // this problem's stop has been added to the plan's done counter
   int inner_total;  // mixed precision, outer record: inner iterations of the refinement so far
+  // mixed precision, inner record: 0 = the inner CG starts afresh (p = 0); 1 or 2 =
+  // it continues its search direction after a residual replacement, with s^ of the
+  // last iteration in buffer cont - 1 (gam[1], alpha[1] hold that iteration's scalars)
+  int cont;
+  int pad_;
 };
 
 // Parameters of one independent patch of a batch: a box of cells of size dx
@@ -300,19 +305,21 @@ void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, con
 
 // ------------------------------------------- mixed precision (FP32 inner solve)
 // Outer sweep: x_new = x_old + d (d in FP32, may be null), r = b - A x_new in
-// FP64, r32 = (float) r; partials ||r||^2, ||b||^2, max |d| / |x_old|; then the
-// finisher applies the outer stopping test, the caps of max_outer sweeps and of the
-// outer record's max_iter inner iterations, and prepares the inner scalars (an
-// inner solve of a stopped problem is off from the start).
-void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,
-                     const double* diag, const double* b, const double* x_old, const float* d,
-                     double* x_new, float* r32, const PcgScalars* outer, double* part);
+// FP64 (applied as S^-1 A^ (S^-1 x_new) with the FP64 scaled operator Ah),
+// r32 = (float) r; partials ||r||^2, ||b||^2 and the largest relative change of the
+// last inner iteration (alpha of the inner record times rs32 p32, against the
+// iterate before it); then the finisher applies the outer stopping test, the caps of
+// max_outer sweeps and of the outer record's max_iter inner iterations, and prepares
+// the inner scalars (an inner solve of a stopped problem is off from the start).
+void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<double>& Ah,
+                     const double* b, const double* x_old, const float* d, const float* p32,
+                     const float* rs32, double* x_new, float* r32, const PcgScalars* outer,
+                     const PcgScalars* inner, double* part);
 void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int max_outer,
                       PcgScalars* outer, PcgScalars* inner, const double* part);
 // Arrays and parameters of the whole mixed-precision solve in one persistent launch.
 struct MixedArgs {
-  FaceCoefs<double> A;  // FP64 operator of the refinement sweeps
-  const double* diag = nullptr;
+  ScaledOp<double> Ah;  // FP64 scaled operator of the refinement sweeps
   const double* b = nullptr;
   double* x = nullptr;      // iterate: x_0 on entry, the result on return
   double* x_alt = nullptr;  // second buffer of the refinement sweeps
@@ -334,12 +341,14 @@ int mixed_persistent_blocks(const SweepPlan& P, int per_cu_cap);
 // the cooperative launch; bar[kBarAbort] becomes 1 if a grid barrier timed out.
 hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const MixedArgs& M,
                                    int per_cu_cap);
-// Inner start (one sweep, x_0 = 0): d = 0, r^_0 = rs r32, w^_0 = A^ r^_0 (the
-// neighbours' r^_0 formed from their r32 and rs), p^ = 0, s^ buffer 0 = 0; partials
+// Inner start (one sweep): d = 0, r^ = rs r32, w^ = A^ r^ (the neighbours' r^
+// formed from their r32 and rs); for a fresh start (inner cont = 0) p^ = 0 and s^
+// buffer 0 = 0, for a continued one s^ is moved into buffer 0 and p^ kept; partials
 // (r^, r^), (w^, r^), ||r32||^2 twice (the inner ||r_0|| and ||b||).  Problems whose
 // refinement has stopped are left alone.
 void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<float>& Ah,
-                       const float* r32, float* d, const CgVecs<float>& v, const PcgScalars* outer, double* part);
+                       const float* r32, float* d, const CgVecs<float>& v, const PcgScalars* outer,
+                       const PcgScalars* inner, double* part);
 
 // ------------------------------------------------------------- batch layout
 // dst[i] = src[prob(i)][idx[i]] (idx < 0: padding slot, dst = pad).

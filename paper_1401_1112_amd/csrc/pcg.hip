@@ -43,7 +43,6 @@ namespace {
 using dev::apply_scaled;
 using dev::apply_stencil;
 using dev::block_plan;
-using dev::block_read_flag;
 using dev::block_reduce;
 using dev::BlockPlan;
 using dev::grid_barrier;
@@ -168,52 +167,55 @@ __device__ __forceinline__ void body_cg_init_w(int vb, DevLevel L, SweepPlan P, 
   write_partials<4>(acc, mx, part_of(part, P, 0), lds, vb);
 }
 
-// Inner start of the mixed form (x_0 = 0): d = 0, r^_0 = rs r32, w^_0 = A^ r^_0,
-// p^ = 0, s^_{-1} = 0; partials (r^, r^), (w^, r^), ||r32||^2 twice.
-__device__ __forceinline__ void body_inner_init(int vb, DevLevel L, SweepPlan P, const ScaledOp<float>& Ah,
-                                                const float* __restrict__ r32, float* __restrict__ d,
-                                                CgVecs<float> v, const PcgScalars* outer, double* part) {
-  __shared__ double lds[kLds];
-  const int n = L.n_slots;
-  const BlockPlan bp = block_plan(P, vb);
-  if (outer[bp.prob].done) return;  // set by an earlier kernel (or before a grid barrier)
-  const float scale = dev::coef_scale(Ah, L, bp.prob);
-  const float* __restrict__ rs = Ah.rs;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int t = bp.t0; t < bp.t1; ++t) {
-    const int i = t * kBlock + int(threadIdx.x);
-    const bool valid = i < n;
-    const int ii = valid ? i : n - 1;
-    const float ri = rs[ii] * r32[ii];
-    const float wi = apply_scaled<float>(ii, L.nbr, Ah, scale, n, ri, [&](int j) { return rs[j] * r32[j]; });
-    if (valid) {
-      v.r[0][i] = ri;
-      v.w[0][i] = wi;
-      v.p[i] = 0.0f;
-      v.s[0][i] = 0.0f;
-      d[i] = 0.0f;
-      acc[0] += double(ri) * double(ri);
-      acc[1] += double(wi) * double(ri);
-      const double rr = double(r32[i]) * double(r32[i]);
-      acc[2] += rr;
-      acc[3] += rr;
-    }
-  }
-  const bool mx[4] = {false, false, false, false};
-  write_partials<4>(acc, mx, part_of(part, P, 0), lds, vb);
-}
+// Operand values at slots outside a block's range, from the values loaded there
+// (the block computes the same values for its own range into LDS, in the same
+// arithmetic, so both agree bitwise).
+// The new scaled residual of an iteration sweep from the previous r^, w^ and s^
+// (read buffers, which no block writes during the sweep).
+template <typename T>
+struct HaloIterate {
+  const T* __restrict__ r;
+  const T* __restrict__ w;
+  const T* __restrict__ s;
+  T ta, tb;
+  struct V {
+    T r, w, s;
+  };
+  __device__ __forceinline__ V load(int j) const { return V{r[j], w[j], s[j]}; }
+  __device__ __forceinline__ T value(const V& g) const { return fma(-ta, fma(tb, g.s, g.w), g.r); }
+};
+// The scaled FP32 residual of an inner start, rs r32.
+struct HaloScaledResidual {
+  const float* __restrict__ r32;
+  const float* __restrict__ rs;
+  struct V {
+    float r, q;
+  };
+  __device__ __forceinline__ V load(int j) const { return V{r32[j], rs[j]}; }
+  __device__ __forceinline__ float value(const V& g) const { return g.q * g.r; }
+};
+// The scaled FP64 iterate of a refinement sweep, (x + d) / rs (d may be null).
+struct HaloScaledIterate {
+  const double* __restrict__ x;
+  const float* __restrict__ d;
+  const double* __restrict__ rs;
+  struct V {
+    double x, q;
+    float d;
+  };
+  __device__ __forceinline__ V load(int j) const { return V{x[j], rs[j], d ? d[j] : 0.0f}; }
+  __device__ __forceinline__ double value(const V& g) const { return (g.x + double(g.d)) / g.q; }
+};
 
-// Phase 2 of the iteration sweep: w^ = A^ r^ over the block's range, with in-oct
-// neighbours by cross-lane shuffle, out-of-oct neighbours inside the range from LDS
-// and the rest recomputed from their previous r^, w^ and s^ (read buffers, which no
-// block writes during the sweep).  Lanes that need no gather read the range's first
-// slot (one line, in cache) instead of their own, whose lines the first phase read
-// long enough ago to have left L2.  dl accumulates (w^, r^).
-template <typename T, int U2, bool kFormed>
-__device__ __forceinline__ void iteration_operator(const DevLevel& L, const ScaledOp<T>& Ah, T scale, T ta, T tb,
-                                                   int s0, int s1, int t0, int t1, const T* rl,
-                                                   const T* __restrict__ r_o, const T* __restrict__ w_o,
-                                                   const T* __restrict__ s_o, T* __restrict__ w_n, double& dl) {
+// Phase 2 of a staged sweep: out(i, (A^ v)_i, v_i) for every slot of the block's
+// range, where the block has staged v over its range in LDS (rl).  In-oct neighbours
+// come by cross-lane shuffle, out-of-oct neighbours inside the range from LDS, the
+// rest from halo.  Lanes that need no gather read the range's first slot (one line,
+// in cache) instead of their own, whose lines the first phase read long enough ago
+// to have left L2.
+template <typename T, int U2, bool kFormed, class Halo, class Out>
+__device__ __forceinline__ void staged_operator(const DevLevel& L, const ScaledOp<T>& Ah, T scale, int s0, int s1,
+                                                int t0, int t1, const T* rl, const Halo& halo, Out out) {
   const int n = L.n_slots;
   const T th = T(Ah.theta);
   for (int tb0 = t0; tb0 < t1; tb0 += U2) {
@@ -242,10 +244,11 @@ __device__ __forceinline__ void iteration_operator(const DevLevel& L, const Scal
       for (int a = 0; a < 3; ++a) nbv[u][a] = L.nbr[o * 6 + 2 * a + ((pos >> a) & 1)];
     }
     // gathers: the out-of-oct coefficient (stored: of a -face, at the neighbour;
-    // formed: the neighbour's K and rs) and the recompute inputs of neighbours outside
+    // formed: the neighbour's K and rs) and the halo inputs of neighbours outside
     // the range
     int jv[U2][3];
-    T cj[U2][3], kj[U2][3], rj[U2][3], wj[U2][3], sj[U2][3];
+    T cj[U2][3], kj[U2][3];
+    typename Halo::V hv[U2][3];
 #pragma unroll
     for (int u = 0; u < U2; ++u) {
       const int pos = ii[u] & 7;
@@ -265,21 +268,19 @@ __device__ __forceinline__ void iteration_operator(const DevLevel& L, const Scal
           cj[u][a] = Ah.K[j];
           kj[u][a] = Ah.rs[j];
         }
-        rj[u][a] = r_o[jo];
-        wj[u][a] = w_o[jo];
-        sj[u][a] = s_o[jo];
+        hv[u][a] = halo.load(jo);
       }
     }
 #pragma unroll
     for (int u = 0; u < U2; ++u) {
       const int pos = ii[u] & 7;
-      const T ri = valid[u] ? rl[ii[u] - s0] : T(0);
-      T acc = ri;
+      const T vi = valid[u] ? rl[ii[u] - s0] : T(0);
+      T acc = vi;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int bit = 1 << a;
         const int my = (pos >> a) & 1;
-        const T r_sib = __shfl_xor(ri, bit, 64);
+        const T v_sib = __shfl_xor(vi, bit, 64);
         T c_in;
         if constexpr (!kFormed) {
           const T c_sib = __shfl_xor(own[u][a], bit, 64);
@@ -289,27 +290,82 @@ __device__ __forceinline__ void iteration_operator(const DevLevel& L, const Scal
           const T rs_sib = __shfl_xor(rsi[u], bit, 64);
           c_in = ((mk[u] >> (2 * a + 1 - my)) & 1u) ? scaled_face(own[u][0], K_sib, rsi[u], rs_sib, scale, th) : T(0);
         }
-        acc -= c_in * r_sib;
+        acc -= c_in * v_sib;
         const int j = jv[u][a];
         if (j >= 0) {
           T c_out;
           if constexpr (!kFormed) c_out = my ? own[u][a] : cj[u][a];
           else c_out = scaled_face(own[u][0], cj[u][a], rsi[u], kj[u][a], scale, th);
-          T rn;
-          if (j >= s0 && j < s1) {
-            rn = rl[j - s0];
-          } else {
-            rn = fma(-ta, fma(tb, sj[u][a], wj[u][a]), rj[u][a]);
-          }
-          acc -= c_out * rn;
+          const T vn = (j >= s0 && j < s1) ? rl[j - s0] : halo.value(hv[u][a]);
+          acc -= c_out * vn;
         }
       }
-      if (valid[u]) {
-        w_n[ii[u]] = acc;
-        dl += double(acc) * double(ri);
-      }
+      if (valid[u]) out(ii[u], acc, vi);
     }
   }
+}
+
+template <typename T, int U2, class Halo, class Out>
+__device__ __forceinline__ void staged_operator(const DevLevel& L, const ScaledOp<T>& Ah, T scale, int s0, int s1,
+                                                int t0, int t1, const T* rl, const Halo& halo, Out out) {
+  if (Ah.Ch) staged_operator<T, U2, false>(L, Ah, scale, s0, s1, t0, t1, rl, halo, out);
+  else staged_operator<T, U2, true>(L, Ah, scale, s0, s1, t0, t1, rl, halo, out);
+}
+
+// Slots per thread of the streaming phase and tiles per trip of the operator phase
+// of the sweeps (twice these in FP32 measured slower).
+template <typename T>
+constexpr int kStreamUnroll = 4;
+template <typename T>
+constexpr int kOperatorUnroll = 2;
+
+// Inner start of the mixed form: d = 0 (the inner solve's iterate, a correction of
+// the FP64 x), r^ = rs r32 (the FP64 residual, rounded and scaled), w^ = A^ r^;
+// partials (r^, r^), (w^, r^), ||r32||^2 twice.  A fresh start (inner cont = 0)
+// clears p^ and s^; a continued one (the residual replaced after a refinement
+// sweep, the search direction kept) moves s^ of the last iteration into buffer 0.
+__device__ __forceinline__ void body_inner_init(int vb, DevLevel L, SweepPlan P, const ScaledOp<float>& Ah,
+                                                const float* __restrict__ r32, float* __restrict__ d,
+                                                CgVecs<float> v, const PcgScalars* outer,
+                                                const PcgScalars* inner, double* part) {
+  __shared__ double lds[kLds];
+  extern __shared__ unsigned char dyn_lds[];
+  float* rl = reinterpret_cast<float*>(dyn_lds);
+  const int n = L.n_slots;
+  const BlockPlan bp = block_plan(P, vb);
+  if (outer[bp.prob].done) return;  // set by an earlier kernel (or before a grid barrier)
+  const int cont = inner[bp.prob].cont;
+  const int s0 = bp.t0 * kBlock, s1 = min(bp.t1 * kBlock, n);
+  const float* __restrict__ rs = Ah.rs;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = s0 + int(threadIdx.x); i < s1; i += kBlock) {
+    const float ri = rs[i] * r32[i];
+    rl[i - s0] = ri;
+    v.r[0][i] = ri;
+    d[i] = 0.0f;
+    if (cont == 0) {
+      v.p[i] = 0.0f;
+      v.s[0][i] = 0.0f;
+    } else if (cont == 2) {
+      v.s[0][i] = v.s[1][i];
+    }
+    acc[0] += double(ri) * double(ri);
+    const double rr = double(r32[i]) * double(r32[i]);
+    acc[2] += rr;
+    acc[3] += rr;
+  }
+  __syncthreads();
+  const float scale = dev::coef_scale(Ah, L, bp.prob);
+  float* __restrict__ w = v.w[0];
+  double dl = 0.0;
+  staged_operator<float, kOperatorUnroll<float>>(L, Ah, scale, s0, s1, bp.t0, bp.t1, rl,
+                                                 HaloScaledResidual{r32, rs}, [&](int i, float wi, float ri) {
+                                                   w[i] = wi;
+                                                   dl += double(wi) * double(ri);
+                                                 });
+  acc[1] = dl;
+  const bool mx[4] = {false, false, false, false};
+  write_partials<4>(acc, mx, part_of(part, P, 0), lds, vb);
 }
 
 // The iteration sweep of iteration `it`: it advances every problem of the plan from
@@ -317,7 +373,8 @@ __device__ __forceinline__ void iteration_operator(const DevLevel& L, const Scal
 // stopping test on iterate it - 1 and the recurrences
 //   beta_j = gamma_j / gamma_{j-1},  alpha_j = gamma_j / (delta_j - beta_j gamma_j / alpha_{j-1})
 // (j = it - 1; for it = 1 the start's partials give ||r_0||, the threshold, the
-// absolute floor and alpha_0 = gamma_0 / delta_0, beta_0 = 0).  Then two phases over
+// absolute floor and alpha_0 = gamma_0 / delta_0, beta_0 = 0, unless the record
+// continues an inner solve, whose previous scalars sit at index 1).  Then two phases over
 // the block's contiguous slot range: (1) p^ = r^ + beta p^, s^ = w^ + beta s^,
 // x += alpha rs p^, r^ -= alpha s^, the new r^ also into LDS; (2) w^ = A^ r^.
 template <typename T>
@@ -328,11 +385,6 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
   T* rl = reinterpret_cast<T*>(dyn_lds);
   const BlockPlan bp = block_plan(P, vb);
   PcgScalars* sc = scs + bp.prob;
-  // the problem's first block may set `done` during this sweep
-  if (block_read_flag(&sc->done)) {
-    if (vb == bp.b0 && threadIdx.x == 0) mark_done(sc, P);
-    return;
-  }
   const int j = it - 1;
   const int n = L.n_slots;
   const int t0 = bp.t0, t1 = bp.t1;
@@ -349,7 +401,7 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
   // phase 1 loads: U1 slots per thread and trip, the first batch issued before the
   // head reduction (it does not depend on alpha or beta) and each next batch before
   // the current one is used
-  constexpr int U1 = 4;
+  constexpr int U1 = kStreamUnroll<T>;
   T pv[U1], sv[U1], wv[U1], xv[U1], rv[U1], qv[U1];
   auto load1 = [&](int base) {
 #pragma unroll
@@ -367,7 +419,14 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
   load1(min(base, s1 - 1));
   double red[4];
   const bool mxh[4] = {false, false, false, it > 1};
-  reduce_partials_all<4>(part_of(part, P, j) + 4 * bp.b0, bp.Gp, mxh, red, lds);
+  // the stop flag comes with the partials, block-uniformly: the problem's first block
+  // may set it during this sweep
+  bool stopped;
+  reduce_partials_all<4>(part_of(part, P, j) + 4 * bp.b0, bp.Gp, mxh, red, lds, &sc->done, &stopped);
+  if (stopped) {
+    if (vb == bp.b0 && threadIdx.x == 0) mark_done(sc, P);
+    return;
+  }
   if (P.extra_part) {  // composite system: the (w^, r^) part of the couplings to other levels
     double pe[1];
     const bool mx1[1] = {false};
@@ -376,7 +435,7 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
   }
   const bool lead = vb == bp.b0 && threadIdx.x == 0;
   double alpha, beta;
-  if (it == 1) {
+  if (it == 1 && !sc->cont) {
     const double r0 = sqrt(red[2]), bn = sqrt(red[3]);
     const double floor_b = sc->abs_floor * bn;
     const bool fin = isfinite(red[0]) && isfinite(red[1]) && isfinite(r0) && isfinite(bn);
@@ -399,6 +458,7 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
     }
     if (!fin || at_floor) return;
   } else {
+    // (it = 1 of a continued inner solve: the previous iteration's scalars at index 1)
     const StopTest st = stop_test(sc, red, j);
     if (lead) record_stop(sc, st, j, P);
     if (st.stop) return;
@@ -450,10 +510,14 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
   }
   __syncthreads();
   const T scale = dev::coef_scale(Ah, L, bp.prob);
-  if (Ah.Ch)
-    iteration_operator<T, 2, false>(L, Ah, scale, ta, tb, s0, s1, t0, t1, rl, r_o, w_o, s_o, v.w[nb], acc[1]);
-  else
-    iteration_operator<T, 2, true>(L, Ah, scale, ta, tb, s0, s1, t0, t1, rl, r_o, w_o, s_o, v.w[nb], acc[1]);
+  T* __restrict__ w_n = v.w[nb];
+  double dl = 0.0;
+  staged_operator<T, kOperatorUnroll<T>>(L, Ah, scale, s0, s1, t0, t1, rl, HaloIterate<T>{r_o, w_o, s_o, ta, tb},
+                                         [&](int i, T wi, T ri) {
+                                           w_n[i] = wi;
+                                           dl += double(wi) * double(ri);
+                                         });
+  acc[1] = dl;
   const bool mx[4] = {false, false, false, true};
   write_partials<4>(acc, mx, part_of(part, P, it), lds, vb);
 }
@@ -537,38 +601,51 @@ __device__ __forceinline__ void body_finish(int prob, SweepPlan P, int kind, con
   }
 }
 
-__device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, const FaceCoefs<double>& A,
-                                                     const double* __restrict__ diag,
-                                                     const double* __restrict__ b,
-                                                     const double* __restrict__ x_old,
-                                                     const float* __restrict__ d, double* __restrict__ x_new,
-                                                     float* __restrict__ r32, const PcgScalars* outer,
-                                                     double* part) {
+// Refinement sweep of the mixed form: x_new = x_old + d (d null on the first), the
+// FP64 residual r = b - A x_new with A applied as S^-1 A^ S^-1 (the FP64 scaled
+// operator: x^ = x_new / rs staged in LDS, r = b - (A^ x^) / rs), r32 = (float) r;
+// partials ||r||^2, ||b||^2 (over the unknowns) and the largest relative change of
+// the last inner iteration, |dx| / |x_new - dx| with dx = rs32 (alpha p^) as that
+// iteration formed it (alpha of the inner record).
+__device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, const ScaledOp<double>& Ah,
+                                              const double* __restrict__ b, const double* __restrict__ x_old,
+                                              const float* __restrict__ d, const float* __restrict__ p32,
+                                              const float* __restrict__ rs32, double* __restrict__ x_new,
+                                              float* __restrict__ r32, const PcgScalars* outer,
+                                              const PcgScalars* inner, double* part) {
   __shared__ double lds[kLds];
+  extern __shared__ unsigned char dyn_lds[];
+  double* rl = reinterpret_cast<double*>(dyn_lds);
   const int n = L.n_slots;
   const BlockPlan bp = block_plan(P, vb);
+  const int s0 = bp.t0 * kBlock, s1 = min(bp.t1 * kBlock, n);
   if (outer[bp.prob].done) {  // converged problem: carry its iterate into the new buffer
-    for (int i = bp.t0 * kBlock + int(threadIdx.x); i < min(bp.t1 * kBlock, n); i += kBlock) x_new[i] = x_old[i];
+    for (int i = s0 + int(threadIdx.x); i < s1; i += kBlock) x_new[i] = x_old[i];
     return;
   }
-  auto xv = [&](int j) -> double { return d ? x_old[j] + double(d[j]) : x_old[j]; };
-  const double scale = dev::coef_scale(A, L, bp.prob);
+  // the last inner iteration (none on the first sweep or after an empty inner solve)
+  const int jl = d ? inner[bp.prob].iter : 0;
+  const float a_last = jl >= 1 ? float(inner[bp.prob].alpha[(jl - 1) & 1]) : 0.0f;
+  const double* __restrict__ rs = Ah.rs;
   double v[3] = {0.0, 0.0, 0.0};
-  for (int t = bp.t0; t < bp.t1; ++t) {
-    const int i = t * kBlock + int(threadIdx.x);
-    const bool valid = i < n;
-    const int ii = valid ? i : n - 1;
-    const double xi = xv(ii);
-    const double ax = apply_stencil<double>(ii, L.nbr, A, scale, n, diag[ii], xi, xv);
-    if (valid) {
-      const double ri = b[i] - ax;
-      x_new[i] = xi;
-      r32[i] = float(ri);
-      v[0] += ri * ri;
-      if (L.child[i] == -1) v[1] += b[i] * b[i];  // ||b|| over the unknowns only
-      if (d) v[2] = fmax(v[2], rel_change(x_old[i], double(d[i])));
+  for (int i = s0 + int(threadIdx.x); i < s1; i += kBlock) {
+    const double xn = d ? x_old[i] + double(d[i]) : x_old[i];
+    x_new[i] = xn;
+    rl[i - s0] = xn / rs[i];
+    if (jl >= 1) {
+      const double dx = double(rs32[i] * (a_last * p32[i]));
+      v[2] = fmax(v[2], rel_change(xn - dx, dx));
     }
   }
+  __syncthreads();
+  const double scale = dev::coef_scale(Ah, L, bp.prob);
+  staged_operator<double, kOperatorUnroll<double>>(L, Ah, scale, s0, s1, bp.t0, bp.t1, rl,
+                                                   HaloScaledIterate{x_old, d, rs}, [&](int i, double ax, double) {
+                                                     const double ri = b[i] - ax / rs[i];
+                                                     r32[i] = float(ri);
+                                                     v[0] += ri * ri;
+                                                     if (L.child[i] == -1) v[1] += b[i] * b[i];
+                                                   });
   const bool mx[3] = {false, false, true};
   write_partials<3>(v, mx, part + P.G, lds, vb);
 }
@@ -576,11 +653,15 @@ __device__ __forceinline__ void body_ir_sweep(int vb, DevLevel L, SweepPlan P, c
 // One block per problem: the outer stopping test, then the inner scalars.  A
 // problem done in an earlier sweep keeps its state and its inner solve is off.
 // Every decision of the refinement loop is made here, on the device: the FP64
-// stopping test (Sect. 3.3.4 on the true residual), the cap of max_outer refinement
-// sweeps and the cap of the outer record's max_iter inner iterations in all (both
-// end the loop unconverged).  The inner solve that just ended is added to the
-// outer record's count first.  outer_done (or nullptr) counts the problems whose
-// loop has ended, for the persistent launch.
+// stopping test (Sect. 3.3.4 on the true residual, the relative change being that
+// of the last inner iteration), the cap of max_outer refinement sweeps and the cap
+// of the outer record's max_iter inner iterations in all (both end the loop
+// unconverged).  The inner solve that just ended is added to the outer record's
+// count first.  After the first sweep the inner CG is continued, not restarted: its
+// residual is replaced by the new FP64 one and its search direction kept (residual
+// replacement), and it runs until its residual has fallen by inner_tol from there.
+// outer_done (or nullptr) counts the problems whose loop has ended, for the
+// persistent launch.
 __device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first, double inner_tol, int max_outer,
                                                PcgScalars* outs, PcgScalars* ins, const double* part,
                                                unsigned* outer_done) {
@@ -634,6 +715,20 @@ __device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first,
   in->done = out->done;
   in->converged = 0;
   in->nonfinite = 0;
+  if (first) {
+    in->cont = 0;
+  } else {
+    // the scalars of the last iteration j - 1 (j = iter) to index 1, where the
+    // continued solve's first sweep (j = 0 of its own count) reads them
+    const int jl = in->iter;
+    if (jl >= 1 && ((jl - 1) & 1) == 0) {
+      in->gam[1] = in->gam[0];
+      in->alpha[1] = in->alpha[0];
+    }
+    in->cont = 1 + (jl & 1);
+    in->rnorm0 = rn;
+    in->thresh = inner_tol * rn;
+  }
   in->iter = 0;
   in->counted = 0;
 }
@@ -695,20 +790,21 @@ __global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, 
   body_post_solve(int(blockIdx.x), L, P, E, rho, cp, dt, T_out, part);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, FaceCoefs<double> A,
-                                                     const double* __restrict__ diag,
+__global__ __launch_bounds__(kBlock) void k_ir_sweep(DevLevel L, SweepPlan P, ScaledOp<double> Ah,
                                                      const double* __restrict__ b,
                                                      const double* __restrict__ x_old,
-                                                     const float* __restrict__ d, double* __restrict__ x_new,
+                                                     const float* __restrict__ d, const float* __restrict__ p32,
+                                                     const float* __restrict__ rs32, double* __restrict__ x_new,
                                                      float* __restrict__ r32, const PcgScalars* outer,
-                                                     double* part) {
-  body_ir_sweep(int(blockIdx.x), L, P, A, diag, b, x_old, d, x_new, r32, outer, part);
+                                                     const PcgScalars* inner, double* part) {
+  body_ir_sweep(int(blockIdx.x), L, P, Ah, b, x_old, d, p32, rs32, x_new, r32, outer, inner, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_inner_init(DevLevel L, SweepPlan P, ScaledOp<float> Ah,
                                                        const float* __restrict__ r32, float* __restrict__ d,
-                                                       CgVecs<float> v, const PcgScalars* outer, double* part) {
-  body_inner_init(int(blockIdx.x), L, P, Ah, r32, d, v, outer, part);
+                                                       CgVecs<float> v, const PcgScalars* outer,
+                                                       const PcgScalars* inner, double* part) {
+  body_inner_init(int(blockIdx.x), L, P, Ah, r32, d, v, outer, inner, part);
 }
 
 __global__ __launch_bounds__(kBlock) void k_check(SweepPlan P, int it_last, PcgScalars* scs, const double* part) {
@@ -780,8 +876,8 @@ __global__ __launch_bounds__(kBlock) void k_mixed_persistent(DevLevel L, SweepPl
   };
   for (int outer = 0; outer <= M.max_outer; ++outer) {
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
-      body_ir_sweep(vb, L, P, M.A, M.diag, M.b, x_cur, outer == 0 ? nullptr : M.d32, x_nxt, M.r32, M.outer,
-                    M.part);
+      body_ir_sweep(vb, L, P, M.Ah, M.b, x_cur, outer == 0 ? nullptr : M.d32, M.v32.p, M.Ah32.rs, x_nxt, M.r32,
+                    M.outer, M.inner, M.part);
     if (!sync()) return;
     double* t = x_cur;
     x_cur = x_nxt;
@@ -795,7 +891,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed_persistent(DevLevel L, SweepPl
     if (!sync()) return;
     if (read_count(outer_done) >= unsigned(P.n_prob)) break;
     for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
-      body_inner_init(vb, L, P, M.Ah32, M.r32, M.d32, M.v32, M.outer, M.part);
+      body_inner_init(vb, L, P, M.Ah32, M.r32, M.d32, M.v32, M.outer, M.inner, M.part);
     if (!sync()) return;
     for (int it = 1; it <= M.inner_cap + 1; ++it) {
       for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
@@ -901,11 +997,12 @@ void launch_post_solve(hipStream_t s, const DevLevel& L, const SweepPlan& P, con
   hipLaunchKernelGGL(k_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, 1, part, sc);
 }
 
-void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A, const double* diag,
-                     const double* b, const double* x_old, const float* d, double* x_new, float* r32,
-                     const PcgScalars* outer, double* part) {
-  hipLaunchKernelGGL(k_ir_sweep, dim3(P.G), dim3(kBlock), 0, s, L, P, A, diag, b, x_old, d, x_new, r32, outer,
-                     part);
+void launch_ir_sweep(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<double>& Ah,
+                     const double* b, const double* x_old, const float* d, const float* p32, const float* rs32,
+                     double* x_new, float* r32, const PcgScalars* outer, const PcgScalars* inner, double* part) {
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(double);
+  hipLaunchKernelGGL(k_ir_sweep, dim3(P.G), dim3(kBlock), lds, s, L, P, Ah, b, x_old, d, p32, rs32, x_new, r32,
+                     outer, inner, part);
 }
 
 void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner_tol, int max_outer,
@@ -915,8 +1012,10 @@ void launch_ir_finish(hipStream_t s, const SweepPlan& P, int first, double inner
 }
 
 void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<float>& Ah,
-                       const float* r32, float* d, const CgVecs<float>& v, const PcgScalars* outer, double* part) {
-  hipLaunchKernelGGL(k_inner_init, dim3(P.G), dim3(kBlock), 0, s, L, P, Ah, r32, d, v, outer, part);
+                       const float* r32, float* d, const CgVecs<float>& v, const PcgScalars* outer,
+                       const PcgScalars* inner, double* part) {
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(float);
+  hipLaunchKernelGGL(k_inner_init, dim3(P.G), dim3(kBlock), lds, s, L, P, Ah, r32, d, v, outer, inner, part);
 }
 
 void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, double abs_floor, int max_iter,
@@ -980,7 +1079,7 @@ hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPl
 
 int mixed_persistent_blocks(const SweepPlan& P, int per_cu_cap) {
   const int res = resident_blocks(reinterpret_cast<const void*>(&k_mixed_persistent),
-                                  size_t(P.tpb_max) * kBlock * sizeof(float), per_cu_cap);
+                                  size_t(P.tpb_max) * kBlock * sizeof(double), per_cu_cap);
   return res > 0 ? std::min(P.G, res) : 0;
 }
 
@@ -988,7 +1087,8 @@ hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const Sweep
                                    int per_cu_cap) {
   const int grid = mixed_persistent_blocks(P, per_cu_cap);
   if (grid <= 0) return hipErrorNotSupported;
-  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(float);
+  // the refinement sweeps stage FP64 values, the inner sweeps FP32 ones
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(double);
   DevLevel Lv = L;
   SweepPlan Pv = P;
   MixedArgs Mv = M;

@@ -7,7 +7,8 @@ calibrate the per-dispatch HBM byte counters of the solver kernels.
 ``python -m paper_1401_1112_amd.profiling batch --patches 512 --steps 2 --mode polled``
 runs the batched workload alone (for kernel traces of the batch form);
 ``... collapse --mode polled --precision mixed`` likewise the collapse-like hierarchy, and
-``... unique --steps 1`` the unique-time-step composite solves of the lognormal hierarchy.
+``... unique --steps 1`` the unique-time-step composite solves of the lognormal hierarchy,
+and ``... levels --precision mixed --steps 2`` its adaptive coarse steps alone.
 
 ``python -m paper_1401_1112_amd.profiling summarize DIR`` prints a per-kernel
 summary (count, average duration, and the averages of any counters) from the
@@ -95,6 +96,45 @@ def run_collapse(steps: int, mode: str, precision: str, form_coefs: bool = False
     st = s.stats()
     print(f"collapse {precision} {mode}{' formed' if form_coefs else ''}: {el * 1e3:.1f} ms per coarse step, {len(st)} solves, "
           f"{sum(x['iters'] for x in st)} PCG iterations, {sum(x['outer_iters'] for x in st)} refinement sweeps",
+          flush=True)
+    s.close()
+
+
+def run_levels(steps: int, mode: str, precision: str, max_blocks: int, form_coefs: bool = False) -> None:
+    """The lognormal hierarchy (levels 6..9, 4.0 M cells, 15 level solves per coarse
+    step) in FP64 or mixed precision: one warm-up and `steps` timed coarse steps from
+    the same state, host-polled or one persistent launch per solve."""
+    import time
+
+    import torch
+
+    from synth.configs import config_fld_lognormal
+
+    from . import _lib as L
+    from .solver import solver_from_problem
+    p = config_fld_lognormal()
+    prec = L.MIXED if precision == "mixed" else L.FP64
+    s = solver_from_problem(p, precision=prec, persistent=(mode == "persistent"), form_coefs=form_coefs,
+                            max_blocks=max_blocks)
+    fields = {lv: tuple(t.clone() for t in s._fields[lv][:2]) for lv in s.levels}
+
+    def step():
+        for lv in s.levels:
+            rho, E = fields[lv]
+            s.set_fields(lv, rho, E, kmode=1)
+        s.advance(p.dt_coarse, L.BC_DIRICHLET, p.tol)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    st = s.stats()
+    print(f"levels {precision} {mode}{' formed' if form_coefs else ''}: {el * 1e3:.2f} ms per coarse step, "
+          f"{len(st)} solves, {sum(x['iters'] for x in st)} CG iterations, "
+          f"{sum(x['outer_iters'] for x in st)} refinement sweeps, {st[0]['sweep_blocks']} sweep blocks",
           flush=True)
     s.close()
 
@@ -193,11 +233,19 @@ def main(argv=None):
     cl.add_argument("--mode", choices=("polled", "persistent"), default="polled")
     cl.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     cl.add_argument("--form-coefs", action="store_true")
+    lv = sub.add_parser("levels")
+    lv.add_argument("--steps", type=int, default=2)
+    lv.add_argument("--mode", choices=("polled", "persistent"), default="polled")
+    lv.add_argument("--precision", choices=("mixed", "fp64"), default="fp64")
+    lv.add_argument("--max-blocks", type=int, default=512)
+    lv.add_argument("--form-coefs", action="store_true")
     u = sub.add_parser("unique")
     u.add_argument("--steps", type=int, default=1)
     a = ap.parse_args(argv)
     if a.cmd == "unique":
         run_unique(a.steps)
+    elif a.cmd == "levels":
+        run_levels(a.steps, a.mode, a.precision, a.max_blocks, a.form_coefs)
     elif a.cmd == "collapse":
         run_collapse(a.steps, a.mode, a.precision, a.form_coefs)
     elif a.cmd == "copy":
