@@ -309,7 +309,7 @@ def _mixed_form(p, s64, init, ms64, args):
         return time.perf_counter() - t0, sts, step
 
     s = solver_from_problem(p, precision=MIXED, max_blocks=args.max_blocks)
-    inner = {"inner_tol": 1e-2, "tuned": False}
+    inner = {"inner_tol": 3e-3, "tuned": False}
     if not args.no_tune:
         # the inner tolerance: the split between FP32 inner iterations and FP64 refinement
         from paper_1401_1112_amd.autotune import tune_refinement
@@ -848,8 +848,8 @@ def _collapse_form(args):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--time-period", type=int, default=16,
                     help="bracket the two sweeps of every N-th PCG iteration with HIP events (0: off)")

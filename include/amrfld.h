@@ -64,6 +64,12 @@ typedef enum {
 } amrfld_status;
 
 typedef enum { AMRFLD_BC_DIRICHLET = 0, AMRFLD_BC_NEUMANN = 1, AMRFLD_BC_ROBIN = 2 } amrfld_bc;
+/* AMRFLD_MIXED (not in the paper): FP32 operator, vectors and operator arithmetic with
+ * FP64 dot products, inside an FP64 refinement loop that forms the true residual
+ * b - A x and applies the solution update in FP64 and decides the stop with the
+ * rule of Sect. 3.3.4 on that residual.  Between two refinement sweeps the FP32 CG
+ * reduces its residual by inner_tol; after each sweep it continues from the new
+ * residual with its search direction kept (residual replacement). */
 typedef enum { AMRFLD_FP64 = 0, AMRFLD_MIXED = 1 } amrfld_precision;
 typedef enum { AMRFLD_K_CONST = 0, AMRFLD_K_LP = 1, AMRFLD_K_MINERBO = 2, AMRFLD_K_POWER = 3 } amrfld_kmode;
 
@@ -81,7 +87,8 @@ typedef struct {
   int check_every;       /* PCG iterations between host convergence checks; 0 = auto */
   int true_residual;     /* 1: compute ||b - A x|| after each solve for the stats */
   int time_sweeps;       /* N > 0: time the sweep of every N-th CG iteration with HIP events */
-  double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner solve; default 1e-2 */
+  double inner_tol;      /* AMRFLD_MIXED: residual reduction of each FP32 inner CG segment between two
+                            FP64 refinement sweeps; default 3e-3 */
   int max_outer;         /* AMRFLD_MIXED: refinement sweeps cap; default 30 */
   int max_blocks;        /* blocks per CG sweep (0 = 1024); each block sweeps a range of 256-slot tiles */
   int persistent;        /* 1 = all PCG iterations of a solve (batch form: of a step) in one cooperative

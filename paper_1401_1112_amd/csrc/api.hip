@@ -1837,7 +1837,7 @@ void amrfld_default_opts(amrfld_opts* o) {
   o->c_v = 1.0;
   o->check_every = 0;
   o->true_residual = 1;
-  o->inner_tol = 1e-2;
+  o->inner_tol = 3e-3;
   o->max_outer = 30;
   o->max_blocks = 0;
   o->stream = nullptr;

@@ -330,7 +330,7 @@ struct MixedArgs {
   PcgScalars* inner = nullptr;  // n_prob inner records
   double* part = nullptr;
   unsigned* bar = nullptr;      // control buffer; its first kBarAbort words zeroed before the launch
-  double inner_tol = 1e-2;
+  double inner_tol = 3e-3;
   int max_outer = 30;
   int inner_cap = 10000;        // bound of the inner loop (the records' max_iter never exceeds it)
   unsigned spin_limit = 1u << 26;

@@ -35,35 +35,39 @@ def run_copy(mib: int, reps: int) -> None:
     print(f"copied {mib} MiB x {reps}", flush=True)
 
 
-def run_batch(patches: int, steps: int, mode: str, per_cu: int, form_coefs: bool = False) -> None:
+def run_batch(patches: int, steps: int, mode: str, per_cu: int, form_coefs: bool = False,
+              precision: str = "fp64") -> None:
     """The batched workload (seeded patches, n in [8, 128]) for one warm-up step and
-    `steps` timed steps, host-polled or as persistent launches (optionally in a graph)."""
+    `steps` timed steps, host-polled or as persistent launches (optionally in a graph),
+    in FP64 or mixed precision."""
     import time
 
     import torch
 
     from synth.configs import patch_batch
 
+    from . import _lib as L
     from .solver import BatchSolver
+    prec = L.MIXED if precision == "mixed" else L.FP64
     ps, alpha = patch_batch(4000, patches)
     kw = {} if mode == "polled" else {"persistent": True, "graph": mode == "graph", "persistent_per_cu": per_cu}
     kw["form_coefs"] = form_coefs
     bs = BatchSolver(robin_alpha=alpha, **kw)
     h = bs.upload(ps)
-    bs.run(h, 1, 1e-10)
+    bs.run(h, 1, 1e-10, prec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bs.run(h, steps, 1e-10)
+    bs.run(h, steps, 1e-10, prec)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     st = bs.stats()
     ci = sum(x["n_leaf"] * x["iters"] for x in st)
-    print(f"batch {mode}{' formed' if form_coefs else ''}: {patches} patches, {steps} steps in {el:.3f} s, {ci / el:.3e} cell-iterations/s, "
+    print(f"batch {precision} {mode}{' formed' if form_coefs else ''}: {patches} patches, {steps} steps in {el:.3f} s, {ci / el:.3e} cell-iterations/s, "
           f"{st[0]['sweep_blocks']} sweep blocks, {st[0]['launch_blocks']} launch blocks", flush=True)
     bs.close()
 
 
-def run_collapse(steps: int, mode: str, precision: str, form_coefs: bool = False) -> None:
+def run_collapse(steps: int, mode: str, precision: str, form_coefs: bool = False, max_blocks: int = 0) -> None:
     """The collapse-like hierarchy (levels 6..13, ~41 M cells, coupled E-T): one warm-up
     and `steps` timed coarse steps from the same state, host-polled or one persistent
     launch per solve."""
@@ -77,7 +81,8 @@ def run_collapse(steps: int, mode: str, precision: str, form_coefs: bool = False
     from .solver import solver_from_problem
     p = config_collapse()
     prec = L.MIXED if precision == "mixed" else L.FP64
-    s = solver_from_problem(p, precision=prec, persistent=(mode == "persistent"), form_coefs=form_coefs)
+    s = solver_from_problem(p, precision=prec, persistent=(mode == "persistent"), form_coefs=form_coefs,
+                            max_blocks=max_blocks)
     fields = {lv: tuple(t.clone() for t in s._fields[lv]) for lv in s.levels}
 
     def step():
@@ -228,11 +233,13 @@ def main(argv=None):
     b.add_argument("--mode", choices=("polled", "persistent", "graph"), default="polled")
     b.add_argument("--per-cu", type=int, default=0)
     b.add_argument("--form-coefs", action="store_true")
+    b.add_argument("--precision", choices=("mixed", "fp64"), default="fp64")
     cl = sub.add_parser("collapse")
     cl.add_argument("--steps", type=int, default=1)
     cl.add_argument("--mode", choices=("polled", "persistent"), default="polled")
     cl.add_argument("--precision", choices=("mixed", "fp64"), default="mixed")
     cl.add_argument("--form-coefs", action="store_true")
+    cl.add_argument("--max-blocks", type=int, default=512)
     lv = sub.add_parser("levels")
     lv.add_argument("--steps", type=int, default=2)
     lv.add_argument("--mode", choices=("polled", "persistent"), default="polled")
@@ -247,11 +254,11 @@ def main(argv=None):
     elif a.cmd == "levels":
         run_levels(a.steps, a.mode, a.precision, a.max_blocks, a.form_coefs)
     elif a.cmd == "collapse":
-        run_collapse(a.steps, a.mode, a.precision, a.form_coefs)
+        run_collapse(a.steps, a.mode, a.precision, a.form_coefs, a.max_blocks)
     elif a.cmd == "copy":
         run_copy(a.mib, a.reps)
     elif a.cmd == "batch":
-        run_batch(a.patches, a.steps, a.mode, a.per_cu, a.form_coefs)
+        run_batch(a.patches, a.steps, a.mode, a.per_cu, a.form_coefs, a.precision)
     else:
         print(summarize(a.dir))
     return 0

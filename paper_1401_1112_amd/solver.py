@@ -11,7 +11,7 @@ from . import _lib as L
 class HierarchySolver:
     def __init__(self, base_level, octs, *, robin_alpha=0.5, max_iter=10000, precision=L.FP64,
                  linf_test=True, abs_floor=1e-14, a_rad=1.0, c_v=1.0, nsub=None, check_every=0,
-                 true_residual=True, time_sweeps=0, inner_tol=1e-2, max_outer=30, max_blocks=0,
+                 true_residual=True, time_sweeps=0, inner_tol=3e-3, max_outer=30, max_blocks=0,
                  persistent=False, persistent_per_cu=0, theta=1.0, K_exp=0.0, outer=None, form_coefs=False,
                  graph=False, device="cuda:0", stream=None):
         L.load()
@@ -169,7 +169,7 @@ class BatchSolver:
     """Independent patches advanced together (amrfld_solve_batch)."""
 
     def __init__(self, *, robin_alpha=0.5, max_iter=10000, linf_test=True, abs_floor=1e-14,
-                 inner_tol=1e-2, max_outer=30, max_blocks=0, time_sweeps=0, true_residual=True,
+                 inner_tol=3e-3, max_outer=30, max_blocks=0, time_sweeps=0, true_residual=True,
                  check_every=0, persistent=False, graph=False, persistent_per_cu=0, form_coefs=False,
                  device="cuda:0", stream=None):
         L.load()

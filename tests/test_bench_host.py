@@ -43,14 +43,14 @@ def test_measured_traffic_only_for_the_counted_source_and_shape(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: kv["traffic_source_sha256_prefix"])
     assert bench._measured_traffic(kernel, blocks) == pytest.approx(float(kv["traffic_kib_per_dispatch"]) * 1024)
     assert bench._measured_traffic(kernel, blocks * 2) is None
-    assert bench._measured_traffic("k_pass_b<double>", blocks) is None
+    assert bench._measured_traffic("k_other<double>", blocks) is None
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 16)
     assert bench._measured_traffic(kernel, blocks) is None
 
 
 def test_algorithmic_bytes_per_slot():
     # the method's bytes per cell and CG iteration, the figures the rooflines quote:
-    # FP64 pass A 69 + pass B 56, FP32 inner 37 + 28
+    # FP64: the operator sweep of Jacobi PCG 69 + its update sweep 56; FP32 inner 37 + 28
     assert bench.ALG_BYTES_FP64 == 125 and bench.ALG_BYTES_FP32 == 65
     # the fused sweep moves p, s, w, x, r, rs, three coefficients and 3 B of neighbour
     # table, and writes p, s, x, r, w
