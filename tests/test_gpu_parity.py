@@ -307,6 +307,27 @@ def test_mixed_precision_refinement_reaches_fp64_tolerance(seed, mode):
     s.close()
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mixed_precision_inner_iterations_track_fp64_cg(seed):
+    # After a refinement sweep the FP32 CG continues its search direction from the
+    # replaced residual: its iterations over a step stay within a few per cent of FP64
+    # CG's (restarting it from zero after every refinement costs about a third more).
+    torch, S = _gpu()
+    from paper_1401_1112_amd import FP64, MIXED
+    p = config_tiny(seed, base_level=3, max_level=5, p_refine=0.5, kmode="lp", tol=1e-10)
+    its = {}
+    for name, prec in (("fp64", FP64), ("mixed", MIXED)):
+        s = S.solver_from_problem(p, precision=prec)
+        s.advance(p.dt_coarse, MODES["dirichlet"], p.tol)
+        st = s.stats()
+        assert all(x["converged"] == 1 for x in st)
+        its[name] = (sum(x["iters"] for x in st), len(st))
+        s.close()
+    (n64, k), (nmx, _) = its["fp64"], its["mixed"]
+    print(f"seed {seed}: FP64 CG {n64} iterations, mixed inner {nmx} over {k} solves")
+    assert nmx <= 1.15 * n64 + 2 * k, its
+
+
 def test_mixed_precision_uniform_closed_form():
     torch, S = _gpu()
     from paper_1401_1112_amd import MIXED
