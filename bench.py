@@ -839,7 +839,9 @@ def _collapse_form(args):
     # cells, coupled E-T): FP64 and the FP32 inner sweep of the mixed form
     out["roofline"] = {
         "fp64_sweep": _roofline(stats["fp64_polled"], ALG_BYTES_FP64, "k_cg_sweep<double>, host-driven FP64",
-                                "leaves of the level of each timed sweep"),
+                                "leaves of the level of each timed sweep",
+                                traffic=_measured_traffic("k_cg_sweep<double>", args.max_blocks,
+                                                          "collapse_L6-13_fp64_polled_hbm_counters.txt")),
         "fp32_inner_sweep": _roofline(stats["mixed_polled"], ALG_BYTES_FP32, "k_cg_sweep<float>, inner solves of "
                                       "the host-driven mixed form", "leaves of the level of each timed sweep")}
     return out
