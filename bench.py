@@ -573,8 +573,8 @@ def _batched_form(args):
         return el, ci, st
 
     from paper_1401_1112_amd import AmrfldError
-    # the host-polled FP64 run also times every time_period-th iteration sweep (roofline)
-    forms = [("fp64_polled", {"time_sweeps": args.time_period}, 0),
+    # the host-polled FP64 run also times every form_time_period-th iteration sweep (roofline)
+    forms = [("fp64_polled", {"time_sweeps": args.form_time_period}, 0),
              ("fp64_persistent_graph", {"persistent": True, "graph": True}, 0),
              ("mixed_polled", {}, MIXED),
              ("mixed_persistent_graph", {"persistent": True, "graph": True}, MIXED)]
@@ -677,7 +677,7 @@ def _batched_form(args):
         out["mixed_tuned_err_vs_fp64_gpu"] = {"max_rel": max(_rel_err(x, y)[0] for x, y in zip(mt, a)),
                                               "l2_rel": max(_rel_err(x, y)[1] for x, y in zip(mt, a))}
     # roofline of the FP64 iteration sweep on this HBM-streaming workload: the timed
-    # sweeps of each step (every time_period-th iteration) move the method's bytes of the
+    # sweeps of each step (every form_time_period-th iteration) move the method's bytes of the
     # cells of the patches still iterating
     st = results["fp64_polled"][1]
     n = len(patches)
@@ -691,7 +691,7 @@ def _batched_form(args):
             continue
         ms += rec["pass_a_ms"]
         for j in range(1, rec["n_timed"] + 1):
-            it = j * args.time_period
+            it = j * args.form_time_period
             byts += ALG_BYTES_FP64 * sum(c for c, i in zip(sizes3, its) if i >= it)
             launches += 1
     if ms > 0:
@@ -757,8 +757,8 @@ def _collapse_form(args):
     results, stats = {}, {}
     shapes = [("mixed_persistent", MIXED, {"persistent": True}),
               ("mixed_persistent_graph", MIXED, {"persistent": True, "graph": True}),
-              ("mixed_polled", MIXED, {"time_sweeps": args.time_period}),
-              ("fp64_polled", FP64, {"time_sweeps": args.time_period})]
+              ("mixed_polled", MIXED, {"time_sweeps": args.form_time_period}),
+              ("fp64_polled", FP64, {"time_sweeps": args.form_time_period})]
     if tuned is not None:
         shapes.append(("mixed_tuned", MIXED, tuned))
     for name, prec, pers in shapes:
@@ -853,8 +853,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--time-period", type=int, default=16,
-                    help="bracket the two sweeps of every N-th PCG iteration with HIP events (0: off)")
+    ap.add_argument("--time-period", type=int, default=32,
+                    help="bracket the sweep of every N-th CG iteration of the headline step with HIP events "
+                         "(0: off; the per-sweep event handling is host work inside the timed region)")
+    ap.add_argument("--form-time-period", type=int, default=16,
+                    help="the same for the batch and collapse forms, whose solves are shorter")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--max-blocks", type=int, default=0, help="blocks per PCG sweep (0: library default)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision form")
@@ -913,12 +916,18 @@ def main(argv=None):
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
+    import gc
+    gc.collect()
+    gc.disable()  # no collector pauses inside the timed region
     t0 = time.perf_counter()
-    all_stats = []
+    all_stats, marks = [], []
     for _ in range(args.steps):
-        all_stats.append(one_step())
+        all_stats.append(one_step())  # returns after the step's last solve has finished
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    gc.enable()
+    step_ms = sorted((b - a) * 1e3 for a, b in zip([t0] + marks[:-1], marks))
 
     cell_it = sum(st["n_leaf"] * st["iters"] for sts in all_stats for st in sts)
     slots = {lvl: s.info(lvl)[0] for lvl in s.levels}
@@ -973,6 +982,8 @@ def main(argv=None):
         "pcg_only_cell_it_per_s": cell_it / (pcg_ms * 1e-3) if pcg_ms > 0 else None,
         "residual": _residual_gate([st for sts in all_stats for st in sts], p.tol),
         "device_solve_ms_per_step": solve_ms / args.steps,
+        "step_ms": {"min": round(step_ms[0], 2), "median": round(step_ms[len(step_ms) // 2], 2),
+                    "max": round(step_ms[-1], 2)},
         "generation_s": round(t_gen, 1),
         "launch": launch,
         "roofline": roofline,

@@ -124,6 +124,7 @@ struct LevelState {
   double *Cp = nullptr, *diag = nullptr, *b = nullptr, *reg = nullptr;
   double *Ch = nullptr, *rs = nullptr;  // the Jacobi-scaled operator of the current solve
   uint8_t* mask = nullptr;  // per slot: faces that couple two leaves of the level
+  int last_iters = 0;       // CG iterations of the level's last FP64 solve (first batch of the next)
   bool has_fields = false, has_T = false;
   int kmode = 1;
   double K_const = 1.0, kappa_R = 1.0, kappa_P = 1.0, c_light = 1.0, K_exp = 0.0;
@@ -545,11 +546,6 @@ void read_scalars(amrfld_ctx* c, PcgScalars* host, const PcgScalars* dev, int co
   }
 }
 
-void write_scalars(amrfld_ctx* c, PcgScalars* dev, const PcgScalars* host, int count) {
-  if (PcgScalars* m = mapped(c, host, count)) launch_copy_scalars(c->stream(), m, dev, count, false);
-  else check(hipMemcpyAsync(dev, host, count * sizeof(PcgScalars), hipMemcpyHostToDevice, c->stream()), "scalars");
-}
-
 bool all_done(const PcgScalars* h, int n) {
   for (int q = 0; q < n; ++q)
     if (!h[q].done) return false;
@@ -752,15 +748,19 @@ void cg_start(amrfld_ctx* c, hipStream_t s, const DevLevel& D, const SweepPlan& 
   if (D.n_if_rows > 0) launch_interface(s, D, c->cg.r[0], c->cg.w[0], sc, D.if_part);
 }
 
+// hint: the iteration count of a previous solve of the same system shape (0: none);
+// the first batch of sweeps covers it with a small margin, so that a solve that
+// converges as fast as that one needs a single check.
 void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
-              LoopStats* ls) {
+              LoopStats* ls, int hint = 0) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
   for (int q = 0; q < np; ++q) c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
-  write_scalars(c, c->sc, c->h_sc, np);
+  launch_init_scalars(s, c->sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
   cg_start(c, s, D, P, A, c->sc);
   check(hipEventRecord(c->ev[1], s), "event");
-  pcg_iterations<double>(c, D, P, A.Ah, c->cg, A.x, c->sc, c->h_sc, c->o.max_iter, ls);
+  pcg_iterations<double>(c, D, P, A.Ah, c->cg, A.x, c->sc, c->h_sc, c->o.max_iter, ls,
+                         hint > 0 ? hint + std::max(2, hint / 16) : 0);
 }
 
 // FP32 inner CG on A d = r inside an FP64 iterative-refinement loop: the FP64
@@ -783,7 +783,8 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
     c->h_sc[q] = make_scalars(tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
     c->h_sc[np + q] = make_scalars(c->o.inner_tol, 0.0, c->o.max_iter, 0);
   }
-  write_scalars(c, c->sc, c->h_sc, 2 * np);
+  launch_init_scalars(s, c->sc, np, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
+  launch_init_scalars(s, c->sc + np, np, c->o.inner_tol, 0.0, c->o.max_iter, 0);
   check(hipEventRecord(c->ev[1], s), "event");
   PcgScalars* out = c->sc;
   PcgScalars* in = c->sc + np;
@@ -862,7 +863,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   if (c->o.precision == AMRFLD_MIXED) {
     pcg_mixed(c, D, P, A, tol, &ls);
   } else {
-    pcg_fp64(c, D, P, A, tol, &ls);
+    pcg_fp64(c, D, P, A, tol, &ls, L.last_iters);
   }
   check(hipEventRecord(c->ev[2], s), "event");
   if (c->o.true_residual && c->o.precision != AMRFLD_MIXED)
@@ -878,6 +879,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   check(hipGetLastError(), "kernels");
 
   const PcgScalars& h = *c->h_sc;
+  if (c->o.precision != AMRFLD_MIXED) L.last_iters = h.iter;
   amrfld_stats st{};
   st.level = level;
   st.iters = h.iter;
@@ -1714,6 +1716,7 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
   c->o.precision = precision;
   amrfld_status worst = AMRFLD_OK;
   std::string worst_msg;
+  int hint = 0;  // the previous step's longest FP64 solve (first batch of sweeps of the next)
   for (int step = 0; step < n_steps; ++step) {
     check(hipEventRecord(c->ev[0], s), "event");
     const CellKParams kp{1, 1.0, 1.0, 1.0};
@@ -1730,7 +1733,8 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     if (precision == AMRFLD_MIXED) {
       pcg_mixed(c, D, P, A, tol, &ls);
     } else {
-      pcg_fp64(c, D, P, A, tol, &ls);
+      pcg_fp64(c, D, P, A, tol, &ls, hint);
+      hint = *std::max_element(ls.iters.begin(), ls.iters.end());
     }
     check(hipEventRecord(c->ev[2], s), "event");
     if (c->o.true_residual && precision != AMRFLD_MIXED)
