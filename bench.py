@@ -76,6 +76,21 @@ def _measured_traffic(kernel: str, max_blocks: int, profile: str = "fld_lognorma
     return float(kv["traffic_kib_per_dispatch"]) * 1024.0
 
 
+class _gc_paused:
+    """No garbage-collector pauses inside a timed region (Python objects are made per
+    step there)."""
+
+    def __enter__(self):
+        import gc
+        gc.collect()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        import gc
+        gc.enable()
+        return False
+
+
 def _copy_bandwidth(mib=1024, reps=5):
     """Achievable HBM bandwidth: a plain device-to-device copy of `mib` MiB (read + write
     bytes over the event-timed duration, best of `reps`)."""
@@ -303,10 +318,12 @@ def _mixed_form(p, s64, init, ms64, args):
             return s.stats()
         step()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts = [step() for _ in range(steps)]
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0, sts, step
+        with _gc_paused():
+            t0 = time.perf_counter()
+            sts = [step() for _ in range(steps)]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        return el, sts, step
 
     s = solver_from_problem(p, precision=MIXED, max_blocks=args.max_blocks)
     inner = {"inner_tol": 3e-3, "tuned": False}
@@ -380,14 +397,15 @@ def _unique_form(p, s, init, ms_ats, args):
     s.advance_unique(p.dt_coarse, p.tol)  # warm-up (composite tables and workspace)
     steps = max(1, min(args.steps, 3))
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sts = []
-    for _ in range(steps):
-        reset()
-        s.advance_unique(p.dt_coarse, p.tol)
-        sts.append(s.stats())
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / steps
+    with _gc_paused():
+        t0 = time.perf_counter()
+        sts = []
+        for _ in range(steps):
+            reset()
+            s.advance_unique(p.dt_coarse, p.tol)
+            sts.append(s.stats())
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
     st = sts[-1]
     dtu = {l: to_numpy(s.E(l)) for l in s.levels}
     diff = max(_rel_err(dtu[l], ats[l])[1] for l in s.levels)
@@ -916,17 +934,14 @@ def main(argv=None):
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    import gc
-    gc.collect()
-    gc.disable()  # no collector pauses inside the timed region
-    t0 = time.perf_counter()
-    all_stats, marks = [], []
-    for _ in range(args.steps):
-        all_stats.append(one_step())  # returns after the step's last solve has finished
-        marks.append(time.perf_counter())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    gc.enable()
+    with _gc_paused():
+        t0 = time.perf_counter()
+        all_stats, marks = [], []
+        for _ in range(args.steps):
+            all_stats.append(one_step())  # returns after the step's last solve has finished
+            marks.append(time.perf_counter())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     step_ms = sorted((b - a) * 1e3 for a, b in zip([t0] + marks[:-1], marks))
 
     cell_it = sum(st["n_leaf"] * st["iters"] for sts in all_stats for st in sts)
