@@ -258,7 +258,7 @@ def _roofline(stats, bytes_per_cell, kernel, note, traffic=None, active=None):
     recorded: the method's bytes per cell x the cells of each timed launch over the
     summed launch time.  active(st) -> cells of one timed launch (default: the solve's
     leaves)."""
-    ms = sum(st["pass_a_ms"] for st in stats)
+    ms = sum(st["sweep_ms"] for st in stats)
     n = sum(st["n_timed"] for st in stats)
     if ms <= 0 or n == 0:
         return None
@@ -707,7 +707,7 @@ def _batched_form(args):
         rec = st[k * n]
         if rec["n_timed"] == 0:
             continue
-        ms += rec["pass_a_ms"]
+        ms += rec["sweep_ms"]
         for j in range(1, rec["n_timed"] + 1):
             it = j * args.form_time_period
             byts += ALG_BYTES_FP64 * sum(c for c, i in zip(sizes3, its) if i >= it)
@@ -956,7 +956,7 @@ def main(argv=None):
                          "HBM gate is judged on the batch and collapse workloads (roofline_gate)")
     if roofline is not None:
         n_a = roofline["timed_launches"]
-        a_ms = sum(st["pass_a_ms"] for st in flat)
+        a_ms = sum(st["sweep_ms"] for st in flat)
         moved = sum((SWEEP_BYTES_FORMED if args.form_coefs else SWEEP_BYTES) * slots[st["level"]] * st["n_timed"]
                     for st in flat)
         traffic = _measured_traffic("k_cg_sweep<double>", args.max_blocks if args.max_blocks > 0 else 1024)

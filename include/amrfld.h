@@ -132,8 +132,8 @@ typedef struct {
   double dt;
   int outer_iters;       /* refinement sweeps (mixed precision), else 0 */
   int n_timed;           /* iterations whose sweeps were timed (time_sweeps), else 0 */
-  double pass_a_ms;      /* summed device time of the timed iteration sweeps (one per CG iteration) */
-  double pass_b_ms;      /* 0: kept for the layout (the iteration is one fused sweep) */
+  double sweep_ms;       /* summed device time of the timed iteration sweeps (one per CG iteration) */
+  double spare_ms;       /* 0: kept for the layout (the iteration is one fused sweep) */
   int launch_mode;       /* 0 host-polled sweeps, 1 persistent launch, 2 persistent launches in a hipGraph */
   double rnorm0;         /* ||r_0|| = ||b - A x_0|| (mixed precision: the first outer residual) */
   double bnorm;          /* ||b||; the stopping threshold is max(tol ||r_0||, abs_floor ||b||) */

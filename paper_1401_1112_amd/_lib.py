@@ -45,7 +45,7 @@ class amrfld_stats(ctypes.Structure):
         ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
         ("linf_change", ctypes.c_double), ("min_E", ctypes.c_double), ("ms", ctypes.c_double),
         ("pcg_ms", ctypes.c_double), ("dt", ctypes.c_double), ("outer_iters", ctypes.c_int),
-        ("n_timed", ctypes.c_int), ("pass_a_ms", ctypes.c_double), ("pass_b_ms", ctypes.c_double),
+        ("n_timed", ctypes.c_int), ("sweep_ms", ctypes.c_double), ("spare_ms", ctypes.c_double),
         ("launch_mode", ctypes.c_int), ("rnorm0", ctypes.c_double), ("bnorm", ctypes.c_double),
         ("sweep_blocks", ctypes.c_int), ("launch_blocks", ctypes.c_int),
     ]

@@ -477,7 +477,7 @@ amrfld_status check_level_ready(amrfld_ctx* c, int level) {
 struct LoopStats {
   std::vector<int> iters;  // per problem: PCG iterations (inner iterations in mixed precision)
   int n_timed = 0;
-  double a_ms = 0.0, b_ms = 0.0;
+  double sweep_ms = 0.0;
   bool persistent = false;  // iterations ran in persistent launches
   int launch_blocks = 0;    // blocks of those launches
 };
@@ -652,7 +652,7 @@ int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const S
       float ta = 0.f;
       check(hipEventSynchronize(c->sweep_ev[2 * kk + 1]), "event");
       check(hipEventElapsedTime(&ta, c->sweep_ev[2 * kk], c->sweep_ev[2 * kk + 1]), "event");
-      ls->a_ms += ta;
+      ls->sweep_ms += ta;
       ls->n_timed += 1;
     }
   }
@@ -908,8 +908,8 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   st.ms = ms;
   st.pcg_ms = pms;
   st.n_timed = ls.n_timed;
-  st.pass_a_ms = ls.a_ms;
-  st.pass_b_ms = ls.b_ms;
+  st.sweep_ms = ls.sweep_ms;
+  st.spare_ms = 0.0;
   amrfld_status status = AMRFLD_OK;
   if (h.nonfinite) status = AMRFLD_E_NONFINITE;
   else if (!h.converged) status = AMRFLD_E_NOCONV;
@@ -1393,8 +1393,8 @@ amrfld_status solve_composite(amrfld_ctx* c, double dt, double tol) {
   st.ms = ms;
   st.pcg_ms = pms;
   st.n_timed = ls.n_timed;
-  st.pass_a_ms = ls.a_ms;
-  st.pass_b_ms = ls.b_ms;
+  st.sweep_ms = ls.sweep_ms;
+  st.spare_ms = 0.0;
   st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
   c->stats.push_back(st);
   if (st.status == AMRFLD_E_NONFINITE) return fail(c, AMRFLD_E_NONFINITE, "non-finite value in the composite residual");
@@ -1764,8 +1764,8 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
       st.ms = ms;
       st.pcg_ms = pms;
       st.n_timed = ls.n_timed;
-      st.pass_a_ms = ls.a_ms;
-      st.pass_b_ms = ls.b_ms;
+      st.sweep_ms = ls.sweep_ms;
+      st.spare_ms = 0.0;
       st.rnorm0 = h.rnorm0;
       st.bnorm = h.bnorm;
       st.sweep_blocks = P.G;

@@ -101,13 +101,13 @@ struct SweepPlan {
   int n_prob = 1;
   int G = 1;                          // total blocks
   int n_tiles = 0;                    // used when the arrays are null (one problem)
-  int tpb_max = 1;                    // largest tile count of one block (sizes the LDS of the operator sweep)
+  int tpb_max = 1;                    // largest tile count of one block (sizes the LDS of the staged sweeps)
   const int32_t* blk_prob = nullptr;  // [G] or nullptr
   const int32_t* blk0 = nullptr;      // [n_prob + 1] or nullptr
   const int32_t* tile0 = nullptr;     // [n_prob + 1] or nullptr
   unsigned* done_count = nullptr;     // counts problems that stopped (read by the persistent sweep)
-  // one problem only: more (p, q) partials that the update sweep adds after the
-  // operator sweep's (the couplings of the composite system to other levels)
+  // one problem only: more (w^, r^) partials that the iteration sweep's head adds to
+  // its own (the couplings of the composite system to other levels)
   const double* extra_part = nullptr;
   int n_extra = 0;
 };

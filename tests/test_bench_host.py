@@ -58,14 +58,14 @@ def test_algorithmic_bytes_per_slot():
 
 
 def test_roofline_of_timed_sweeps():
-    stats = [{"pass_a_ms": 2.0, "n_timed": 4, "n_leaf": 1_000_000},
-             {"pass_a_ms": 1.0, "n_timed": 2, "n_leaf": 1_000_000}]
+    stats = [{"sweep_ms": 2.0, "n_timed": 4, "n_leaf": 1_000_000},
+             {"sweep_ms": 1.0, "n_timed": 2, "n_leaf": 1_000_000}]
     r = bench._roofline(stats, 125, "k", "n")
     # 6 launches over 1e6 cells at 125 B in 3 ms
     assert r["achieved"] == pytest.approx(6 * 125e6 / 3e-3 / 1e9, rel=1e-6)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
     assert r["timed_launches"] == 6 and r["avg_launch_us"] == pytest.approx(500.0)
-    assert bench._roofline([{"pass_a_ms": 0.0, "n_timed": 0, "n_leaf": 1}], 125, "k", "n") is None
+    assert bench._roofline([{"sweep_ms": 0.0, "n_timed": 0, "n_leaf": 1}], 125, "k", "n") is None
 
 
 def test_schedule_is_fine_first_with_restrictions():
