@@ -91,40 +91,60 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_ma
   __syncthreads();
 }
 
+// A flag that another block may set while this block runs, read once for the
+// whole block.  Waves that each read it at a different moment could see
+// different values and take different paths around the block barriers that
+// follow; in a persistent launch (waves that return go on to the next virtual
+// block) that would pair unrelated barriers.
+__device__ __forceinline__ bool block_read_flag(const int* f) {
+  __shared__ int v;
+  if (threadIdx.x == 0) v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const bool r = v != 0;
+  __syncthreads();
+  return r;
+}
+
 // Sum (or max) of the NV-wide partials of the G blocks of the previous sweep,
 // in a fixed order, made available to every thread of the block.  Every block
 // computes the same bits, so the scalars derived from it agree everywhere.  Up to
 // kPartialRounds * kBlock blocks, every thread issues all its loads at once (one
-// memory latency instead of one per round); the order of the sums is the same.
-// With `flag`, the int it points to is read in the same round trip and returned
-// block-uniformly in *flag_out (nonzero: set): another block may set the flag while
-// this one runs, and waves that each read it at a different moment could see
-// different values and take different paths around the block barriers that follow
-// (in a persistent launch, pairing unrelated barriers).
+// memory latency instead of one per round), and the loads can be issued early
+// (load_partials) and summed later (reduce_loaded); the order of the sums is the
+// same in every case.
 constexpr int kPartialRounds = 4;
 template <int NV>
-__device__ __forceinline__ void reduce_partials_all(const double* __restrict__ part, int G,
-                                                    const bool (&is_max)[NV], double (&out)[NV],
-                                                    double* lds, const int* flag = nullptr,
-                                                    bool* flag_out = nullptr) {
-  int fl = 0;
-  if (flag && threadIdx.x == 0) fl = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  double v[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = is_max[k] ? -DBL_MAX : 0.0;
+struct LoadedPartials {
+  double t[kPartialRounds][NV];
+};
+
+template <int NV>
+__device__ __forceinline__ LoadedPartials<NV> load_partials(const double* __restrict__ part, int G,
+                                                            const bool (&is_max)[NV]) {
+  LoadedPartials<NV> lp;
   if (G <= kPartialRounds * kBlock) {
-    double t[kPartialRounds][NV];
 #pragma unroll
     for (int r = 0; r < kPartialRounds; ++r) {
       const int g = int(threadIdx.x) + r * kBlock;
 #pragma unroll
-      for (int k = 0; k < NV; ++k) t[r][k] = g < G ? part[g * NV + k] : (is_max[k] ? -DBL_MAX : 0.0);
+      for (int k = 0; k < NV; ++k) lp.t[r][k] = g < G ? part[g * NV + k] : (is_max[k] ? -DBL_MAX : 0.0);
     }
+  }
+  return lp;
+}
+
+template <int NV>
+__device__ __forceinline__ void reduce_loaded(const LoadedPartials<NV>& lp, const double* __restrict__ part, int G,
+                                              const bool (&is_max)[NV], double (&out)[NV], double* lds) {
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = is_max[k] ? -DBL_MAX : 0.0;
+  if (G <= kPartialRounds * kBlock) {
 #pragma unroll
     for (int r = 0; r < kPartialRounds; ++r) {
       if (int(threadIdx.x) + r * kBlock < G) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = is_max[k] ? fmax(v[k], t[r][k]) : v[k] + t[r][k];
+        for (int k = 0; k < NV; ++k) v[k] = is_max[k] ? fmax(v[k], lp.t[r][k]) : v[k] + lp.t[r][k];
       }
     }
   } else {
@@ -137,17 +157,21 @@ __device__ __forceinline__ void reduce_partials_all(const double* __restrict__ p
     }
   }
   block_reduce<NV>(v, is_max, lds);
-  __shared__ int fl_s;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) lds[k] = v[k];
-    fl_s = fl;
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) out[k] = lds[k];
-  if (flag_out) *flag_out = fl_s != 0;
   __syncthreads();
+}
+
+template <int NV>
+__device__ __forceinline__ void reduce_partials_all(const double* __restrict__ part, int G,
+                                                    const bool (&is_max)[NV], double (&out)[NV],
+                                                    double* lds) {
+  reduce_loaded<NV>(load_partials<NV>(part, G, is_max), part, G, is_max, out, lds);
 }
 
 // This block's problem, its blocks [b0, b0 + Gp) and its contiguous range of

@@ -43,6 +43,7 @@ namespace {
 using dev::apply_scaled;
 using dev::apply_stencil;
 using dev::block_plan;
+using dev::block_read_flag;
 using dev::block_reduce;
 using dev::BlockPlan;
 using dev::grid_barrier;
@@ -386,6 +387,16 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
   const BlockPlan bp = block_plan(P, vb);
   PcgScalars* sc = scs + bp.prob;
   const int j = it - 1;
+  // the previous sweep's partials are loaded together with the stop flag (the
+  // problem's first block may set it during this sweep); a stopped problem's sweep
+  // returns before it loads anything else
+  const bool mxh[4] = {false, false, false, it > 1};
+  const double* part_prev = part_of(part, P, j) + 4 * bp.b0;
+  const dev::LoadedPartials<4> lp = dev::load_partials<4>(part_prev, bp.Gp, mxh);
+  if (block_read_flag(&sc->done)) {
+    if (vb == bp.b0 && threadIdx.x == 0) mark_done(sc, P);
+    return;
+  }
   const int n = L.n_slots;
   const int t0 = bp.t0, t1 = bp.t1;
   const int s0 = t0 * kBlock;
@@ -418,15 +429,7 @@ __device__ __forceinline__ void body_cg_sweep(int vb, DevLevel L, SweepPlan P, i
   int base = s0 + int(threadIdx.x);
   load1(min(base, s1 - 1));
   double red[4];
-  const bool mxh[4] = {false, false, false, it > 1};
-  // the stop flag comes with the partials, block-uniformly: the problem's first block
-  // may set it during this sweep
-  bool stopped;
-  reduce_partials_all<4>(part_of(part, P, j) + 4 * bp.b0, bp.Gp, mxh, red, lds, &sc->done, &stopped);
-  if (stopped) {
-    if (vb == bp.b0 && threadIdx.x == 0) mark_done(sc, P);
-    return;
-  }
+  dev::reduce_loaded<4>(lp, part_prev, bp.Gp, mxh, red, lds);
   if (P.extra_part) {  // composite system: the (w^, r^) part of the couplings to other levels
     double pe[1];
     const bool mx1[1] = {false};
