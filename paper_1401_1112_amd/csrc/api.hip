@@ -743,8 +743,12 @@ MixedArgs mixed_args(amrfld_ctx* c, const SolveArrays& A, const ScaledOp<float>&
 // of w^_0 to other levels).
 void cg_start(amrfld_ctx* c, hipStream_t s, const DevLevel& D, const SweepPlan& P, const SolveArrays& A,
               PcgScalars* sc) {
-  launch_cg_init_r<double>(s, D, P, A.A, A.diag, A.b, A.x, A.Ah.rs, c->cg);
-  launch_cg_init_w<double>(s, D, P, A.Ah, A.b, c->cg, c->partials);
+  if (D.cif && D.n_if_rows > 0) {  // a composite system with couplings to other levels
+    launch_cg_init_r<double>(s, D, P, A.A, A.diag, A.b, A.x, A.Ah.rs, c->cg);
+    launch_cg_init_w<double>(s, D, P, A.Ah, A.b, c->cg, c->partials);
+  } else {
+    launch_cg_start<double>(s, D, P, A.Ah, A.b, A.x, c->cg, c->partials);
+  }
   if (D.n_if_rows > 0) launch_interface(s, D, c->cg.r[0], c->cg.w[0], sc, D.if_part);
 }
 

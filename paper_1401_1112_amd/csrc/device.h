@@ -241,8 +241,15 @@ int sweep_blocks(int n_tiles, int max_blocks);
 
 // Every launcher below covers all problems of the plan; sc points at n_prob
 // scalar records.
-// Start, sweep 1: r^_0 = rs (b - A x0) with the unscaled operator A (diag and A),
-// p^ = 0, s^ buffer 0 = 0.
+// The two start sweeps of a solve without couplings to other levels, staged in LDS
+// like the iteration sweep: r^_0 = rs b - A^ (x0 / rs), p^ = 0, s^ buffer 0 = 0, then
+// w^_0 = A^ r^_0 and the partials the first iteration sweep reduces.
+template <typename T>
+void launch_cg_start(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<T>& Ah, const T* b,
+                     const T* x, const CgVecs<T>& v, double* part);
+// The start sweeps of the composite system (couplings to other levels included).
+// Sweep 1: r^_0 = rs (b - A x0) with the unscaled operator A (diag and A), p^ = 0, s^
+// buffer 0 = 0.
 template <typename T>
 void launch_cg_init_r(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag,
                       const T* b, const T* x, const T* rs, const CgVecs<T>& v);

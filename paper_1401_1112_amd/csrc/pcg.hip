@@ -185,6 +185,16 @@ struct HaloIterate {
   __device__ __forceinline__ V load(int j) const { return V{r[j], w[j], s[j]}; }
   __device__ __forceinline__ T value(const V& g) const { return fma(-ta, fma(tb, g.s, g.w), g.r); }
 };
+// Values of an array written by an earlier kernel.
+template <typename T>
+struct HaloPlain {
+  const T* __restrict__ v;
+  struct V {
+    T v;
+  };
+  __device__ __forceinline__ V load(int j) const { return V{v[j]}; }
+  __device__ __forceinline__ T value(const V& g) const { return g.v; }
+};
 // The scaled FP32 residual of an inner start, rs r32.
 struct HaloScaledResidual {
   const float* __restrict__ r32;
@@ -206,6 +216,18 @@ struct HaloScaledIterate {
   };
   __device__ __forceinline__ V load(int j) const { return V{x[j], rs[j], d ? d[j] : 0.0f}; }
   __device__ __forceinline__ double value(const V& g) const { return (g.x + double(g.d)) / g.q; }
+};
+
+// The scaled iterate x / rs of a start sweep.
+template <typename T>
+struct HaloScaledIterateT {
+  const T* __restrict__ x;
+  const T* __restrict__ rs;
+  struct V {
+    T x, q;
+  };
+  __device__ __forceinline__ V load(int j) const { return V{x[j], rs[j]}; }
+  __device__ __forceinline__ T value(const V& g) const { return g.x / g.q; }
 };
 
 // Phase 2 of a staged sweep: out(i, (A^ v)_i, v_i) for every slot of the block's
@@ -319,6 +341,64 @@ template <typename T>
 constexpr int kStreamUnroll = 4;
 template <typename T>
 constexpr int kOperatorUnroll = 2;
+
+// Start, sweep 1, staged: r^_0 = rs b - A^ x^_0 with x^_0 = x0 / rs in LDS (the same
+// residual as rs (b - A x0), A applied as S^-1 A^ S^-1), p^ = 0, s^_{-1} = 0.
+template <typename T>
+__device__ __forceinline__ void body_cg_start_r(int vb, DevLevel L, SweepPlan P, const ScaledOp<T>& Ah,
+                                                const T* __restrict__ b, const T* __restrict__ x, CgVecs<T> v) {
+  extern __shared__ unsigned char dyn_lds[];
+  T* rl = reinterpret_cast<T*>(dyn_lds);
+  const int n = L.n_slots;
+  const BlockPlan bp = block_plan(P, vb);
+  const int s0 = bp.t0 * kBlock, s1 = min(bp.t1 * kBlock, n);
+  const T* __restrict__ rs = Ah.rs;
+  for (int i = s0 + int(threadIdx.x); i < s1; i += kBlock) rl[i - s0] = x[i] / rs[i];
+  __syncthreads();
+  const T scale = dev::coef_scale(Ah, L, bp.prob);
+  staged_operator<T, kOperatorUnroll<T>>(L, Ah, scale, s0, s1, bp.t0, bp.t1, rl, HaloScaledIterateT<T>{x, rs},
+                                         [&](int i, T ax, T) {
+                                           v.r[0][i] = rs[i] * b[i] - ax;
+                                           v.p[i] = T(0);
+                                           v.s[0][i] = T(0);
+                                         });
+}
+
+// Start, sweep 2, staged: w^_0 = A^ r^_0 with r^_0 staged in LDS; partials (r^, r^),
+// (w^, r^), ||r_0||^2 and ||b||^2 (over the unknowns only: identity rows hold b = E,
+// which is no part of the system).
+template <typename T>
+__device__ __forceinline__ void body_cg_start_w(int vb, DevLevel L, SweepPlan P, const ScaledOp<T>& Ah,
+                                                const T* __restrict__ b, CgVecs<T> v, double* part) {
+  __shared__ double lds[kLds];
+  extern __shared__ unsigned char dyn_lds[];
+  T* rl = reinterpret_cast<T*>(dyn_lds);
+  const int n = L.n_slots;
+  const BlockPlan bp = block_plan(P, vb);
+  const int s0 = bp.t0 * kBlock, s1 = min(bp.t1 * kBlock, n);
+  const T* __restrict__ r = v.r[0];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = s0 + int(threadIdx.x); i < s1; i += kBlock) {
+    const T ri = r[i];
+    rl[i - s0] = ri;
+    acc[0] += double(ri) * double(ri);
+    const double ru = double(ri) / double(Ah.rs[i]);
+    acc[2] += ru * ru;
+    if (L.child[i] == -1) acc[3] += double(b[i]) * double(b[i]);
+  }
+  __syncthreads();
+  const T scale = dev::coef_scale(Ah, L, bp.prob);
+  T* __restrict__ w = v.w[0];
+  double dl = 0.0;
+  staged_operator<T, kOperatorUnroll<T>>(L, Ah, scale, s0, s1, bp.t0, bp.t1, rl, HaloPlain<T>{r},
+                                         [&](int i, T wi, T ri) {
+                                           w[i] = wi;
+                                           dl += double(wi) * double(ri);
+                                         });
+  acc[1] = dl;
+  const bool mx[4] = {false, false, false, false};
+  write_partials<4>(acc, mx, part_of(part, P, 0), lds, vb);
+}
 
 // Inner start of the mixed form: d = 0 (the inner solve's iterate, a correction of
 // the FP64 x), r^ = rs r32 (the FP64 residual, rounded and scaled), w^ = A^ r^;
@@ -738,6 +818,19 @@ __device__ __forceinline__ void body_ir_finish(int prob, SweepPlan P, int first,
 
 // ------------------------------------------------------------ kernels
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_start_r(DevLevel L, SweepPlan P, ScaledOp<T> Ah,
+                                                       const T* __restrict__ b, const T* __restrict__ x,
+                                                       CgVecs<T> v) {
+  body_cg_start_r<T>(int(blockIdx.x), L, P, Ah, b, x, v);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_start_w(DevLevel L, SweepPlan P, ScaledOp<T> Ah,
+                                                       const T* __restrict__ b, CgVecs<T> v, double* part) {
+  body_cg_start_w<T>(int(blockIdx.x), L, P, Ah, b, v, part);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_init_r(DevLevel L, SweepPlan P, FaceCoefs<T> A,
                                                       const T* __restrict__ diag, const T* __restrict__ b,
                                                       const T* __restrict__ x, const T* __restrict__ rs,
@@ -949,6 +1042,14 @@ __global__ __launch_bounds__(kBlock) void k_interface_values(DevLevel L, const d
 
 // ------------------------------------------------------------ launchers
 template <typename T>
+void launch_cg_start(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<T>& Ah, const T* b,
+                     const T* x, const CgVecs<T>& v, double* part) {
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(T);
+  hipLaunchKernelGGL(k_cg_start_r<T>, dim3(P.G), dim3(kBlock), lds, s, L, P, Ah, b, x, v);
+  hipLaunchKernelGGL(k_cg_start_w<T>, dim3(P.G), dim3(kBlock), lds, s, L, P, Ah, b, v, part);
+}
+
+template <typename T>
 void launch_cg_init_r(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<T>& A, const T* diag,
                       const T* b, const T* x, const T* rs, const CgVecs<T>& v) {
   hipLaunchKernelGGL(k_cg_init_r<T>, dim3(P.G), dim3(kBlock), 0, s, L, P, A, diag, b, x, rs, v);
@@ -1106,6 +1207,8 @@ template hipError_t launch_pcg_persistent<double>(hipStream_t, const DevLevel&, 
 template hipError_t launch_pcg_persistent<float>(hipStream_t, const DevLevel&, const SweepPlan&, int,
                                                  const ScaledOp<float>&, const CgVecs<float>&, float*, PcgScalars*,
                                                  double*, unsigned*, int);
+template void launch_cg_start<double>(hipStream_t, const DevLevel&, const SweepPlan&, const ScaledOp<double>&,
+                                      const double*, const double*, const CgVecs<double>&, double*);
 template void launch_cg_init_r<double>(hipStream_t, const DevLevel&, const SweepPlan&, const FaceCoefs<double>&,
                                        const double*, const double*, const double*, const double*,
                                        const CgVecs<double>&);
