@@ -871,7 +871,7 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   }
   check(hipEventRecord(c->ev[2], s), "event");
   if (c->o.true_residual && c->o.precision != AMRFLD_MIXED)
-    launch_true_residual(s, D, P, Aop, L.diag, L.b, L.E, c->sc, c->partials);
+    launch_true_residual(s, D, P, Ah, L.b, L.E, c->sc, c->partials);
   launch_post_solve(s, D, P, L.E, L.rho, cp, dt, L.T, c->sc, c->partials);
   if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN)) {
     double* reg = ensure_reg(c, *Lc);
@@ -988,7 +988,7 @@ hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int
                                       c->o.persistent_per_cu);
   }
   if (e != hipSuccess) return e;
-  if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Aop, L.diag, L.b, L.E, sc, c->partials);
+  if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Ah, L.b, L.E, sc, c->partials);
   launch_post_solve(st, D, P, L.E, L.rho, cp, dt, L.T, sc, c->partials);
   if (Lc && (mode == AMRFLD_BC_NEUMANN || mode == AMRFLD_BC_ROBIN))
     launch_flux_register(st, D, L.K, Lc->K, L.E, Lc->E, dt, Lc->reg, int(Lc->t.n_slots()));
@@ -1584,7 +1584,7 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
         e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, Ah, c->cg, B.E, sc, c->partials, c->bar, per_cu);
       }
       if (e != hipSuccess) return e;
-      if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Aop, B.diag, B.b, B.E, sc, c->partials);
+      if (c->o.true_residual && !mixed) launch_true_residual(st, D, P, Ah, B.b, B.E, sc, c->partials);
       launch_post_solve(st, D, P, B.E, B.rho, cp, 0.0, nullptr, sc, c->partials);
     }
     return hipGetLastError();
@@ -1742,7 +1742,7 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     }
     check(hipEventRecord(c->ev[2], s), "event");
     if (c->o.true_residual && precision != AMRFLD_MIXED)
-      launch_true_residual(s, D, P, Aop, B.diag, B.b, B.E, c->sc, c->partials);
+      launch_true_residual(s, D, P, Ah, B.b, B.E, c->sc, c->partials);
     launch_post_solve(s, D, P, B.E, B.rho, cp, 0.0, nullptr, c->sc, c->partials);
     check(hipEventRecord(c->ev[3], s), "event");
     read_scalars(c, c->h_sc, c->sc, np);

@@ -303,6 +303,10 @@ void launch_zero_u32(hipStream_t s, unsigned* p, int n);
 void launch_copy_scalars(hipStream_t s, const PcgScalars* src, PcgScalars* dst, int count, bool to_host);
 void launch_init_scalars(hipStream_t s, PcgScalars* sc, int n, double tol, double abs_floor, int max_iter,
                          int linf_test);
+// The same with the scaled operator, staged in LDS, for solves without couplings to
+// other levels.
+void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<double>& Ah,
+                          const double* b, const double* x, PcgScalars* sc, double* part);
 void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,
                           const double* diag, const double* b, const double* x, PcgScalars* sc,
                           double* part);

@@ -400,6 +400,32 @@ __device__ __forceinline__ void body_cg_start_w(int vb, DevLevel L, SweepPlan P,
   write_partials<4>(acc, mx, part_of(part, P, 0), lds, vb);
 }
 
+// The FP64 true residual norm of a solve without couplings to other levels, staged:
+// x^ = x / rs in LDS, r = b - (A^ x^) / rs; one partial ||r||^2 per block.
+__device__ __forceinline__ void body_true_residual_staged(int vb, DevLevel L, SweepPlan P,
+                                                          const ScaledOp<double>& Ah,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ x, double* part) {
+  __shared__ double lds[kLds];
+  extern __shared__ unsigned char dyn_lds[];
+  double* rl = reinterpret_cast<double*>(dyn_lds);
+  const int n = L.n_slots;
+  const BlockPlan bp = block_plan(P, vb);
+  const int s0 = bp.t0 * kBlock, s1 = min(bp.t1 * kBlock, n);
+  const double* __restrict__ rs = Ah.rs;
+  for (int i = s0 + int(threadIdx.x); i < s1; i += kBlock) rl[i - s0] = x[i] / rs[i];
+  __syncthreads();
+  const double scale = dev::coef_scale(Ah, L, bp.prob);
+  double v[1] = {0.0};
+  staged_operator<double, kOperatorUnroll<double>>(L, Ah, scale, s0, s1, bp.t0, bp.t1, rl,
+                                                   HaloScaledIterateT<double>{x, rs}, [&](int i, double ax, double) {
+                                                     const double ri = b[i] - ax / rs[i];
+                                                     v[0] += ri * ri;
+                                                   });
+  const bool mx[1] = {false};
+  write_partials<1>(v, mx, part, lds, vb);
+}
+
 // Inner start of the mixed form: d = 0 (the inner solve's iterate, a correction of
 // the FP64 x), r^ = rs r32 (the FP64 residual, rounded and scaled), w^ = A^ r^;
 // partials (r^, r^), (w^, r^), ||r32||^2 twice.  A fresh start (inner cont = 0)
@@ -880,6 +906,12 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(DevLevel L, SweepPlan 
   body_true_residual(int(blockIdx.x), L, P, A, diag, b, x, part);
 }
 
+__global__ __launch_bounds__(kBlock) void k_true_residual_staged(DevLevel L, SweepPlan P, ScaledOp<double> Ah,
+                                                                 const double* __restrict__ b,
+                                                                 const double* __restrict__ x, double* part) {
+  body_true_residual_staged(int(blockIdx.x), L, P, Ah, b, x, part);
+}
+
 __global__ __launch_bounds__(kBlock) void k_post_solve(DevLevel L, SweepPlan P, const double* __restrict__ E,
                                                        const double* __restrict__ rho, CouplingParams cp,
                                                        double dt, double* __restrict__ T_out, double* part) {
@@ -1087,6 +1119,13 @@ void launch_interface(hipStream_t s, const DevLevel& L, const double* r, double*
 
 void launch_check(hipStream_t s, const SweepPlan& P, int it_last, PcgScalars* sc, const double* part) {
   hipLaunchKernelGGL(k_check, dim3(P.n_prob), dim3(kBlock), 0, s, P, it_last, sc, part);
+}
+
+void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<double>& Ah,
+                          const double* b, const double* x, PcgScalars* sc, double* part) {
+  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(double);
+  hipLaunchKernelGGL(k_true_residual_staged, dim3(P.G), dim3(kBlock), lds, s, L, P, Ah, b, x, part);
+  hipLaunchKernelGGL(k_finish, dim3(P.n_prob), dim3(kBlock), 0, s, P, 0, part, sc);
 }
 
 void launch_true_residual(hipStream_t s, const DevLevel& L, const SweepPlan& P, const FaceCoefs<double>& A,
