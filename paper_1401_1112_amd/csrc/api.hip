@@ -767,6 +767,11 @@ void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveA
                          hint > 0 ? hint + std::max(2, hint / 16) : 0);
 }
 
+// The plan of a level's sweeps, at most max_tiles tiles per block.
+SweepPlan level_plan(const amrfld_ctx* c, int n_tiles, int max_tiles = kMaxTilesPerBlock) {
+  return single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024, max_tiles), n_tiles);
+}
+
 // FP32 inner CG on A d = r inside an FP64 iterative-refinement loop: the FP64
 // sweep applies x += d and forms the true residual r = b - A x; the inner solve
 // uses the FP32 scaled operator, FP32 vectors and operator arithmetic with FP64 dot
@@ -777,9 +782,10 @@ void pcg_fp64(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveA
 // after 0 iterations, so it reads scalars only inside the inner solves.  With
 // `persistent` the whole solve is one cooperative launch (the same bits).  Once the
 // stream has run, the outer records hold the refinement sweeps (iter) and the inner
-// iterations (inner_total).
-void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SolveArrays& A, double tol,
-               LoopStats* ls) {
+// iterations (inner_total).  P plans the FP64 sweeps and P32 the FP32 inner ones
+// (the same problems; P32 may give a block longer ranges).
+void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const SweepPlan& P32, const SolveArrays& A,
+               double tol, LoopStats* ls) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
   const ScaledOp<float> A32 = operator_f32(c, s, A);
@@ -795,13 +801,13 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
   const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
   if (c->o.persistent && !D.cif) {
     if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
-    SweepPlan Pp = P;
-    Pp.done_count = c->bar + kBarDone;
+    SweepPlan Pp = P, P32p = P32;
+    Pp.done_count = P32p.done_count = c->bar + kBarDone;
     const MixedArgs M = mixed_args(c, A, A32, out, in, max_outer);
-    const int blocks = mixed_persistent_blocks(Pp, c->o.persistent_per_cu);
+    const int blocks = mixed_persistent_blocks(Pp, P32p, c->o.persistent_per_cu);
     if (blocks > 0) {
       launch_zero_u32(s, c->bar, kBarWords);
-      if (launch_mixed_persistent(s, D, Pp, M, c->o.persistent_per_cu) == hipSuccess) {
+      if (launch_mixed_persistent(s, D, Pp, P32p, M, c->o.persistent_per_cu) == hipSuccess) {
         unsigned aborted = 0;
         check(hipMemcpyAsync(&aborted, c->bar + kBarAbort, sizeof(unsigned), hipMemcpyDeviceToHost, s), "abort flag");
         check(hipStreamSynchronize(s), "abort flag");
@@ -821,8 +827,8 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Solve
                     out, in, c->partials);
     std::swap(x_cur, x_nxt);
     launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, max_outer, out, in, c->partials);
-    launch_inner_init(s, D, P, A32, c->r32, c->d32, c->cg32, out, in, c->partials);
-    const int done = pcg_iterations<float>(c, D, P, A32, c->cg32, c->d32, in, c->h_sc + np, c->o.max_iter, ls,
+    launch_inner_init(s, D, P32, A32, c->r32, c->d32, c->cg32, out, in, c->partials);
+    const int done = pcg_iterations<float>(c, D, P32, A32, c->cg32, c->d32, in, c->h_sc + np, c->o.max_iter, ls,
                                            hint + 1);
     if (done == 0) break;  // every refinement loop had stopped before this round's inner solves
     hint = done;
@@ -859,13 +865,13 @@ amrfld_status solve_one(amrfld_ctx* c, int level, double dt, int mode, double to
   const ScaledOp<double> Ah = scale_operator(c, s, D, Aop, L.Cp, L.diag, L.rs, L.Ch);
 
   const int n_tiles = tiles_of(D.n_slots);
-  const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
+  const SweepPlan P = level_plan(c, n_tiles);
   ensure_scalars(c, 1);
   LoopStats ls;
   ls.iters.assign(1, 0);
   const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots, Ah};
   if (c->o.precision == AMRFLD_MIXED) {
-    pcg_mixed(c, D, P, A, tol, &ls);
+    pcg_mixed(c, D, P, level_plan(c, n_tiles, kMaxTilesPerBlock32), A, tol, &ls);
   } else {
     pcg_fp64(c, D, P, A, tol, &ls, L.last_iters);
   }
@@ -970,9 +976,9 @@ hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int
   const ScaledOp<double> Ah = scale_operator(c, st, D, Aop, L.Cp, L.diag, L.rs, L.Ch);
   const SolveArrays A{Aop, L.diag, L.b, L.E, D.n_slots, Ah};
   const int n_tiles = tiles_of(D.n_slots);
-  const SweepPlan P = single_plan(sweep_blocks(n_tiles, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), n_tiles);
-  SweepPlan Pp = P;
-  Pp.done_count = c->bar + kBarDone;
+  const SweepPlan P = level_plan(c, n_tiles);
+  SweepPlan Pp = P, P32p = level_plan(c, n_tiles, kMaxTilesPerBlock32);
+  Pp.done_count = P32p.done_count = c->bar + kBarDone;
   const bool mixed = c->o.precision == AMRFLD_MIXED;
   launch_init_scalars(st, sc, 1, tol, c->o.abs_floor, c->o.max_iter, c->o.linf_test);
   launch_zero_u32(st, c->bar, kBarAbort);  // arrivals, releases, stop counts; not the abort flag
@@ -981,7 +987,8 @@ hipError_t record_solve(amrfld_ctx* c, hipStream_t st, int level, double dt, int
     const ScaledOp<float> A32 = operator_f32(c, st, A);
     launch_init_scalars(st, sc_inner, 1, c->o.inner_tol, 0.0, c->o.max_iter, 0);
     const int max_outer = c->o.max_outer > 0 ? c->o.max_outer : 30;
-    e = launch_mixed_persistent(st, D, Pp, mixed_args(c, A, A32, sc, sc_inner, max_outer), c->o.persistent_per_cu);
+    e = launch_mixed_persistent(st, D, Pp, P32p, mixed_args(c, A, A32, sc, sc_inner, max_outer),
+                                c->o.persistent_per_cu);
   } else {
     cg_start(c, st, D, P, A, sc);
     e = launch_pcg_persistent<double>(st, D, Pp, c->o.max_iter, Ah, c->cg, L.E, sc, c->partials, c->bar,
@@ -1020,8 +1027,9 @@ amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double to
   if (!c->bar) c->bar = dalloc<unsigned>(kBarWords, "barrier");
   for (int l = c->o.base_level; l <= c->finest; ++l) {
     const int nt = tiles_of(c->L(l).t.n_slots());
-    SweepPlan P = single_plan(sweep_blocks(nt, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), nt);
-    const int pb = mixed ? mixed_persistent_blocks(P, c->o.persistent_per_cu)
+    const SweepPlan P = level_plan(c, nt);
+    const int pb = mixed ? mixed_persistent_blocks(P, level_plan(c, nt, kMaxTilesPerBlock32),
+                                                   c->o.persistent_per_cu)
                          : persistent_blocks<double>(P, c->o.persistent_per_cu);
     if (pb <= 0) return AMRFLD_E_STATE;
   }
@@ -1079,7 +1087,7 @@ amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double to
     const PcgScalars& h = c->h_sc[k];
     const LevelState& L = c->L(sched[k].level);
     const int nt = tiles_of(L.t.n_slots());
-    const SweepPlan P = single_plan(sweep_blocks(nt, c->o.max_blocks > 0 ? c->o.max_blocks : 1024), nt);
+    const SweepPlan P = level_plan(c, nt);
     amrfld_stats st{};
     st.level = sched[k].level;
     st.iters = mixed ? h.inner_total : h.iter;
@@ -1096,7 +1104,8 @@ amrfld_status advance_graph(amrfld_ctx* c, double dt_coarse, int mode, double to
     st.rnorm0 = h.rnorm0;
     st.bnorm = h.bnorm;
     st.sweep_blocks = P.G;
-    st.launch_blocks = mixed ? mixed_persistent_blocks(P, c->o.persistent_per_cu)
+    st.launch_blocks = mixed ? mixed_persistent_blocks(P, level_plan(c, nt, kMaxTilesPerBlock32),
+                                                       c->o.persistent_per_cu)
                              : persistent_blocks<double>(P, c->o.persistent_per_cu);
     st.launch_mode = 2;
     st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
@@ -1553,7 +1562,7 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
   const unsigned* abort_flag = c->bar + kBarAbort;
   const int per_cu = c->o.persistent_per_cu;
   const bool mixed = precision == AMRFLD_MIXED;
-  if ((mixed ? mixed_persistent_blocks(P, per_cu) : persistent_blocks<double>(P, per_cu)) <= 0) return AMRFLD_E_STATE;
+  if ((mixed ? mixed_persistent_blocks(P, P, per_cu) : persistent_blocks<double>(P, per_cu)) <= 0) return AMRFLD_E_STATE;
   // one record per (step, patch), then the inner records of the mixed form (shared by the steps)
   ensure_scalars(c, n_steps * np + np);
   if (mixed) ensure_workspace32(c, B.n_slots);
@@ -1578,7 +1587,8 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       if (mixed) {
         const ScaledOp<float> A32 = operator_f32(c, st, A);
         launch_init_scalars(st, sc_inner, np, c->o.inner_tol, 0.0, c->o.max_iter, 0);
-        e = launch_mixed_persistent(st, D, P, mixed_args(c, A, A32, sc, sc_inner, max_outer), per_cu);
+        // the batch's FP32 sweeps keep its FP64 plan (16 tiles per block)
+        e = launch_mixed_persistent(st, D, P, P, mixed_args(c, A, A32, sc, sc_inner, max_outer), per_cu);
       } else {
         cg_start(c, st, D, P, A, sc);
         e = launch_pcg_persistent<double>(st, D, P, c->o.max_iter, Ah, c->cg, B.E, sc, c->partials, c->bar, per_cu);
@@ -1654,7 +1664,7 @@ amrfld_status solve_batch_persistent(amrfld_ctx* c, const std::vector<amrfld_pat
       st.rnorm0 = h.rnorm0;
       st.bnorm = h.bnorm;
       st.sweep_blocks = P.G;
-      st.launch_blocks = mixed ? mixed_persistent_blocks(P, per_cu) : persistent_blocks<double>(P, per_cu);
+      st.launch_blocks = mixed ? mixed_persistent_blocks(P, P, per_cu) : persistent_blocks<double>(P, per_cu);
       st.status = h.nonfinite ? AMRFLD_E_NONFINITE : (h.converged ? AMRFLD_OK : AMRFLD_E_NOCONV);
       if (st.status != AMRFLD_OK && worst == AMRFLD_OK) {
         worst = amrfld_status(st.status);
@@ -1735,7 +1745,7 @@ amrfld_status solve_batch(amrfld_ctx* c, const std::vector<amrfld_patch>& pt, in
     const ScaledOp<double> Ah = scale_operator(c, s, D, Aop, B.Cp, B.diag, B.rs, B.Ch);
     const SolveArrays A{Aop, B.diag, B.b, B.E, B.n_slots, Ah};
     if (precision == AMRFLD_MIXED) {
-      pcg_mixed(c, D, P, A, tol, &ls);
+      pcg_mixed(c, D, P, P, A, tol, &ls);  // one plan for the batch's FP64 and FP32 sweeps
     } else {
       pcg_fp64(c, D, P, A, tol, &ls, hint);
       hint = *std::max_element(ls.iters.begin(), ls.iters.end());

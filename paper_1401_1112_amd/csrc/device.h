@@ -8,7 +8,12 @@
 namespace amrfld {
 
 constexpr int kBlock = 256;  // threads per block = slots per tile
-constexpr int kMaxTilesPerBlock = 16;
+// LDS of one block's staged range of one vector in the staged sweeps: at most 16
+// tiles per block in the FP64 sweeps and, in the same bytes, 32 in the FP32 ones
+// (fewer, longer ranges: fewer faces gathered across range ends).
+constexpr int kStageBytes = 32768;
+constexpr int kMaxTilesPerBlock = kStageBytes / (kBlock * int(sizeof(double)));
+constexpr int kMaxTilesPerBlock32 = kStageBytes / (kBlock * int(sizeof(float)));
 
 // Words of the persistent launch's control buffer (unsigned), each on its own
 // 256-byte line: grid-barrier arrivals (of the XCD groups) and releases, the count
@@ -236,8 +241,9 @@ void launch_to_f32(hipStream_t s, int64_t n, const double* Ch, const double* K, 
 // recurrences of Chronopoulos and Gear: one fused sweep per iteration, whose two
 // dot products are reduced together at the head of the next sweep.  G = number of
 // blocks of every sweep of a solve (<= tiles); partials hold 8 G doubles, 4 per
-// block for each iteration parity.
-int sweep_blocks(int n_tiles, int max_blocks);
+// block for each iteration parity.  max_tiles: the most tiles one block may take
+// (kMaxTilesPerBlock for FP64 sweeps, kMaxTilesPerBlock32 for FP32 ones).
+int sweep_blocks(int n_tiles, int max_blocks, int max_tiles = kMaxTilesPerBlock);
 
 // Every launcher below covers all problems of the plan; sc points at n_prob
 // scalar records.
@@ -346,17 +352,21 @@ struct MixedArgs {
   int inner_cap = 10000;        // bound of the inner loop (the records' max_iter never exceeds it)
   unsigned spin_limit = 1u << 26;
 };
-// Blocks of the mixed persistent launch for this plan (0 if the device cannot run it).
-int mixed_persistent_blocks(const SweepPlan& P, int per_cu_cap);
-// P.done_count must be M.bar + kBarDone.  Returns an error if the device cannot run
-// the cooperative launch; bar[kBarAbort] becomes 1 if a grid barrier timed out.
-hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const MixedArgs& M,
-                                   int per_cu_cap);
+// Blocks of the mixed persistent launch for the plans of its FP64 refinement sweeps
+// (P) and of its FP32 inner sweeps (P32: the same problems, at most as many blocks)
+// (0 if the device cannot run it).
+int mixed_persistent_blocks(const SweepPlan& P, const SweepPlan& P32, int per_cu_cap);
+// P.done_count and P32.done_count must be M.bar + kBarDone.  Returns an error if the
+// device cannot run the cooperative launch; bar[kBarAbort] becomes 1 if a grid
+// barrier timed out.
+hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const SweepPlan& P32,
+                                   const MixedArgs& M, int per_cu_cap);
 // Inner start (one sweep): d = 0, r^ = rs r32, w^ = A^ r^ (the neighbours' r^
 // formed from their r32 and rs); for a fresh start (inner cont = 0) p^ = 0 and s^
 // buffer 0 = 0, for a continued one s^ is moved into buffer 0 and p^ kept; partials
-// (r^, r^), (w^, r^), ||r32||^2 twice (the inner ||r_0|| and ||b||).  Problems whose
-// refinement has stopped are left alone.
+// (r^, r^), (w^, r^), ||r32||^2 twice (the inner ||r_0|| and ||b||), laid out for
+// P, the plan of the inner sweeps that follow.  Problems whose refinement has
+// stopped are left alone.
 void launch_inner_init(hipStream_t s, const DevLevel& L, const SweepPlan& P, const ScaledOp<float>& Ah,
                        const float* r32, float* d, const CgVecs<float>& v, const PcgScalars* outer,
                        const PcgScalars* inner, double* part);

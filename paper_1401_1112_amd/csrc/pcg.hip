@@ -26,15 +26,16 @@
 
 namespace amrfld {
 
-// At most kMaxTilesPerBlock tiles per block: the iteration sweep stages the
-// block's whole range of the new residual in LDS (16 tiles = 32 KB in FP64).  A
-// level with more than max_blocks * 16 tiles gets a whole multiple of max_blocks,
-// so that the blocks of a persistent launch of max_blocks blocks each sweep the
-// same number of equal ranges.
-int sweep_blocks(int n_tiles, int max_blocks) {
+// At most max_tiles tiles per block: the iteration sweep stages the block's whole
+// range of the new residual in LDS (16 tiles = 32 KB in FP64, 32 tiles in FP32).  A
+// level with more than max_blocks * max_tiles tiles gets a whole multiple of
+// max_blocks, so that the blocks of a persistent launch of max_blocks blocks each
+// sweep the same number of equal ranges.
+int sweep_blocks(int n_tiles, int max_blocks, int max_tiles) {
   const int B = std::max(1, max_blocks);
+  const int64_t per = int64_t(B) * std::max(1, max_tiles);
   if (n_tiles <= B) return std::max(1, n_tiles);
-  const int64_t rounds = (int64_t(n_tiles) + int64_t(B) * kMaxTilesPerBlock - 1) / (int64_t(B) * kMaxTilesPerBlock);
+  const int64_t rounds = (int64_t(n_tiles) + per - 1) / per;
   return int(rounds * B);
 }
 
@@ -974,21 +975,22 @@ __global__ __launch_bounds__(kBlock) void k_pcg_persistent(DevLevel L, SweepPlan
   }
 }
 
-// The whole mixed-precision solve of every problem of the plan in one cooperative
+// The whole mixed-precision solve of every problem of the plans in one cooperative
 // launch: rounds of (FP64 refinement sweep, outer stopping test, inner start, FP32
 // inner iteration sweeps) with a grid barrier after each phase, the same bodies in
-// the same order as the host-driven launches, so the results are the same bits.
+// the same order and with the same plans (P for the FP64 sweeps, P32 for the FP32
+// ones) as the host-driven launches, so the results are the same bits.
 // Every decision is made on the device (body_ir_finish); the loop ends once every
 // problem's refinement has stopped (a count read right after the barrier that
 // follows the outer test) and in any case after max_outer + 1 refinement sweeps; an
 // inner solve ends once every problem's inner CG stopped, and in any case after
 // inner_cap + 1 sweeps.  A barrier that times out sets the abort flag and the
 // block returns (the others time out in turn).
-__global__ __launch_bounds__(kBlock) void k_mixed_persistent(DevLevel L, SweepPlan P, MixedArgs M) {
+__global__ __launch_bounds__(kBlock) void k_mixed_persistent(DevLevel L, SweepPlan P, SweepPlan P32, MixedArgs M) {
   __shared__ unsigned n_done;
   const unsigned nb = gridDim.x;
   dev::GridSync gs{M.bar, nb, M.spin_limit};
-  unsigned* inner_done = P.done_count;
+  unsigned* inner_done = P32.done_count;
   unsigned* outer_done = M.bar + kBarOuterDone;
   double* x_cur = M.x;
   double* x_nxt = M.x_alt;
@@ -1018,15 +1020,15 @@ __global__ __launch_bounds__(kBlock) void k_mixed_persistent(DevLevel L, SweepPl
       __hip_atomic_store(inner_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!sync()) return;
     if (read_count(outer_done) >= unsigned(P.n_prob)) break;
-    for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
-      body_inner_init(vb, L, P, M.Ah32, M.r32, M.d32, M.v32, M.outer, M.inner, M.part);
+    for (int vb = int(blockIdx.x); vb < P32.G; vb += int(nb))
+      body_inner_init(vb, L, P32, M.Ah32, M.r32, M.d32, M.v32, M.outer, M.inner, M.part);
     if (!sync()) return;
     for (int it = 1; it <= M.inner_cap + 1; ++it) {
-      for (int vb = int(blockIdx.x); vb < P.G; vb += int(nb))
-        body_cg_sweep<float>(vb, L, P, it, M.Ah32, M.v32, M.d32, M.inner, M.part);
+      for (int vb = int(blockIdx.x); vb < P32.G; vb += int(nb))
+        body_cg_sweep<float>(vb, L, P32, it, M.Ah32, M.v32, M.d32, M.inner, M.part);
       if (!sync()) return;
       // stops are counted only at the sweep heads (see k_pcg_persistent)
-      if (read_count(inner_done) >= unsigned(P.n_prob)) break;
+      if (read_count(inner_done) >= unsigned(P32.n_prob)) break;
     }
   }
   // the last refinement sweep wrote x_cur: make it the caller's iterate
@@ -1220,22 +1222,28 @@ hipError_t launch_pcg_persistent(hipStream_t s, const DevLevel& L, const SweepPl
                                     args, unsigned(lds), s);
 }
 
-int mixed_persistent_blocks(const SweepPlan& P, int per_cu_cap) {
-  const int res = resident_blocks(reinterpret_cast<const void*>(&k_mixed_persistent),
-                                  size_t(P.tpb_max) * kBlock * sizeof(double), per_cu_cap);
-  return res > 0 ? std::min(P.G, res) : 0;
+// The refinement sweeps stage FP64 values over P's ranges, the inner sweeps FP32
+// ones over P32's.
+size_t mixed_persistent_lds(const SweepPlan& P, const SweepPlan& P32) {
+  return std::max(size_t(P.tpb_max) * sizeof(double), size_t(P32.tpb_max) * sizeof(float)) * kBlock;
 }
 
-hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const MixedArgs& M,
-                                   int per_cu_cap) {
-  const int grid = mixed_persistent_blocks(P, per_cu_cap);
+int mixed_persistent_blocks(const SweepPlan& P, const SweepPlan& P32, int per_cu_cap) {
+  const int res = resident_blocks(reinterpret_cast<const void*>(&k_mixed_persistent),
+                                  mixed_persistent_lds(P, P32), per_cu_cap);
+  return res > 0 ? std::min(std::max(P.G, P32.G), res) : 0;
+}
+
+hipError_t launch_mixed_persistent(hipStream_t s, const DevLevel& L, const SweepPlan& P, const SweepPlan& P32,
+                                   const MixedArgs& M, int per_cu_cap) {
+  const int grid = mixed_persistent_blocks(P, P32, per_cu_cap);
   if (grid <= 0) return hipErrorNotSupported;
-  // the refinement sweeps stage FP64 values, the inner sweeps FP32 ones
-  const size_t lds = size_t(P.tpb_max) * kBlock * sizeof(double);
+  const size_t lds = mixed_persistent_lds(P, P32);
   DevLevel Lv = L;
   SweepPlan Pv = P;
+  SweepPlan P32v = P32;
   MixedArgs Mv = M;
-  void* args[] = {&Lv, &Pv, &Mv};
+  void* args[] = {&Lv, &Pv, &P32v, &Mv};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_mixed_persistent), dim3(grid), dim3(kBlock),
                                     args, unsigned(lds), s);
 }
