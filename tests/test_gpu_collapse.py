@@ -171,3 +171,36 @@ def test_collapse_full_size_properties(collapse_full):
         for k in (0, 1):
             a, b = res_p[l][k], res_f[l][k]
             assert float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) <= 1e-8
+
+
+@pytest.mark.parametrize("mode", ["persistent", "graph"])
+def test_collapse_mixed_inner_plan_of_its_own(mode):
+    # One block per sweep at most: the FP64 sweeps of a 21-tile level take 2 blocks of
+    # <= 16 tiles, the FP32 inner sweeps 1 block of <= 32 tiles.  The persistent launch
+    # (and its graph capture) follows both plans and gives the host-driven bits, and
+    # the result meets the oracle's bar for the mixed form.
+    from paper_1401_1112_amd import MIXED
+    from paper_1401_1112_amd.solver import solver_from_problem
+    p = _small(1.5)
+    tiles = {l: (len(p.hierarchy.octs[l]) * 8 + 255) // 256 for l in p.hierarchy.levels}
+    assert any(-(-t // 16) != -(-t // 32) for t in tiles.values()), tiles
+    res = []
+    for kw in ({}, {"persistent": True, "graph": mode == "graph"}):
+        s = solver_from_problem(p, precision=MIXED, max_blocks=1, **kw)
+        s.advance(p.dt_coarse, 0, p.tol)
+        st = s.stats()
+        for x in st:
+            thr = max(p.tol * x["rnorm0"], p.abs_floor * x["bnorm"])
+            assert x["converged"] == 1 and x["true_rel_res"] * x["rnorm0"] <= thr * (1 + 1e-12), x
+            assert x["sweep_blocks"] == -(-tiles[x["level"]] // 16), x
+        res.append((_gpu_fields(s, p.hierarchy.levels), [(x["iters"], x["outer_iters"]) for x in st],
+                    [x["launch_mode"] for x in st]))
+        s.close()
+    (a, ia, ma), (b, ib, mb) = res
+    assert set(ma) == {0} and set(mb) == {2 if mode == "graph" else 1}
+    assert ia == ib
+    for l in p.hierarchy.levels:
+        assert np.array_equal(a[l][0], b[l][0]) and np.array_equal(a[l][1], b[l][1])
+    o = oracle_from_problem(p)
+    o.advance_subcycled(p.dt_coarse, ora.DIRICHLET, 1e-13)
+    assert _worst(p, a, o) <= 1e-8
