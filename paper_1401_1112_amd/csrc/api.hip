@@ -558,11 +558,13 @@ bool all_done(const PcgScalars* h, int n) {
 // Launches after a problem converged return at once.  Returns the largest
 // iteration count of the problems' solves (0: every problem was already stopped).
 // first_chunk > 0: size of the first batch (a prediction, e.g. the previous inner
-// solve's count), else the default.
+// solve's count), else the default.  lead: records stored just before sc_dev (and
+// sc_host) that every check also brings to the host (the outer records of the mixed
+// form).
 template <typename T>
 int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const ScaledOp<T>& Ah,
                    const CgVecs<T>& v, T* x, PcgScalars* sc_dev, PcgScalars* sc_host, int max_iter, LoopStats* ls,
-                   int first_chunk = 0) {
+                   int first_chunk = 0, int lead = 0) {
   const hipStream_t s = c->stream();
   const int np = P.n_prob;
   if (c->o.persistent && !D.cif) {
@@ -623,7 +625,7 @@ int pcg_iterations(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const S
     launched += k;
     launch_check(s, P, launched, sc_dev, c->partials);
     check(hipGetLastError(), "launch");
-    read_scalars(c, sc_host, sc_dev, np);
+    read_scalars(c, sc_host - lead, sc_dev - lead, np + lead);
     if (autochunk && !all_done(sc_host, np)) {
       int est = 2;
       for (int qq = 0; qq < np; ++qq) {
@@ -822,16 +824,29 @@ void pcg_mixed(amrfld_ctx* c, const DevLevel& D, const SweepPlan& P, const Sweep
   double* x_cur = A.x;
   double* x_nxt = c->x_alt;
   int hint = 0;
+  bool expect_stop = false;
   for (int outer = 0; outer <= max_outer; ++outer) {
     launch_ir_sweep(s, D, P, A.Ah, A.b, x_cur, outer == 0 ? nullptr : c->d32, c->cg32.p, A32.rs, x_nxt, c->r32,
                     out, in, c->partials);
     std::swap(x_cur, x_nxt);
     launch_ir_finish(s, P, outer == 0 ? 1 : 0, c->o.inner_tol, max_outer, out, in, c->partials);
     launch_inner_init(s, D, P32, A32, c->r32, c->d32, c->cg32, out, in, c->partials);
+    if (expect_stop) {
+      // the refinement test is expected to stop every problem here: read its outcome
+      // before enqueuing inner sweeps that would only find their problems stopped
+      read_scalars(c, c->h_sc + np, in, np);
+      if (all_done(c->h_sc + np, np)) break;
+    }
     const int done = pcg_iterations<float>(c, D, P32, A32, c->cg32, c->d32, in, c->h_sc + np, c->o.max_iter, ls,
-                                           hint + 1);
+                                           hint + 1, np);
     if (done == 0) break;  // every refinement loop had stopped before this round's inner solves
     hint = done;
+    // expected when every running problem's inner solve ended with a residual (that of
+    // the FP64 one the next refinement sweep forms, up to FP32 rounding) well below its
+    // refinement threshold; a wrong guess costs one read of the scalars
+    expect_stop = true;
+    for (int q = 0; q < np && expect_stop; ++q)
+      expect_stop = c->h_sc[q].done || c->h_sc[np + q].rnorm <= 0.5 * c->h_sc[q].thresh;
   }
   if (x_cur != A.x) launch_copy_f64(s, A.x, x_cur, A.n);
 }
