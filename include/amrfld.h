@@ -287,7 +287,9 @@ amrfld_status amrfld_last_stats(const amrfld_ctx* c, amrfld_stats* out, int max_
 /* Launch shape of the PCG sweeps for the following calls on this context; not a
  * step of the method (the same sweeps, dealt differently to the GPU), used to
  * time candidate shapes on the device.  max_blocks: blocks per sweep (0 = 1024;
- * each block sweeps a contiguous range of at most 16 tiles of 256 slots);
+ * each block sweeps a contiguous range of at most 16 tiles of 256 slots, or 32 in
+ * the FP32 inner sweeps of an AMRFLD_MIXED level solve, which may then take fewer
+ * blocks than its FP64 sweeps);
  * persistent, persistent_per_cu, form_coefs: as in amrfld_opts.  Negative values
  * are rejected with AMRFLD_E_INVALID and change nothing.  Results of one shape are
  * bitwise reproducible, and form_coefs changes no FP64 bit; between block counts
