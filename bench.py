@@ -861,7 +861,9 @@ def _collapse_form(args):
                                 traffic=_measured_traffic("k_cg_sweep<double>", args.max_blocks,
                                                           "collapse_L6-13_fp64_polled_hbm_counters.txt")),
         "fp32_inner_sweep": _roofline(stats["mixed_polled"], ALG_BYTES_FP32, "k_cg_sweep<float>, inner solves of "
-                                      "the host-driven mixed form", "leaves of the level of each timed sweep")}
+                                      "the host-driven mixed form", "leaves of the level of each timed sweep",
+                                      traffic=_measured_traffic("k_cg_sweep<float>", args.max_blocks,
+                                                                "collapse_L6-13_mixed_polled_hbm_counters.txt"))}
     return out
 
 
