@@ -778,10 +778,12 @@ SweepPlan level_plan(const amrfld_ctx* c, int n_tiles, int max_tiles = kMaxTiles
 // sweep applies x += d and forms the true residual r = b - A x; the inner solve
 // uses the FP32 scaled operator, FP32 vectors and operator arithmetic with FP64 dot
 // products, and after each refinement sweep continues its search direction from the
-// replaced residual instead of starting afresh.  Outer scalars of problem q at sc[q], inner ones at sc[n_prob + q].
-// Every decision of the loop is made on the device (k_ir_finish): the host enqueues
-// rounds and learns that all problems stopped when a round's inner solves all end
-// after 0 iterations, so it reads scalars only inside the inner solves.  With
+// replaced residual instead of starting afresh.  Outer scalars of problem q at
+// sc[q], inner ones at sc[n_prob + q].  Every decision of the loop is made on the
+// device (k_ir_finish): the host enqueues rounds and learns that all problems
+// stopped when a round's inner solves all end after 0 iterations, so it reads
+// scalars inside the inner solves, and right after the refinement test of a round
+// that it expects to stop every problem.  With
 // `persistent` the whole solve is one cooperative launch (the same bits).  Once the
 // stream has run, the outer records hold the refinement sweeps (iter) and the inner
 // iterations (inner_total).  P plans the FP64 sweeps and P32 the FP32 inner ones
